@@ -1,0 +1,343 @@
+"""IVF search with DADE distance comparisons, in float64.
+
+Follows the end of the Methodology section: IVF selects the N_probe clusters whose
+centroids are nearest to the query, then scans their candidates while keeping the KNN set
+in a max-heap of size K; each candidate gets one DCO against the heap's maximum distance
+and, when the DCO answers yes, the heap is updated.  The DCO is Algorithm 1 with the
+estimate of Eq. (13) and the test built on eps_d of Eq. (14) (see ``estimator``), or
+FDScanning when ``mode="exact"``.
+
+Readings where the paper is silent (each is a parameter or stated rule here):
+* k-means lists (Experiments: Faiss k-means, N_c about sqrt(N)): Lloyd iterations from
+  seed rows that are passed in; an empty cluster keeps its centroid; distance ties go to
+  the lower centroid id; rows are finally assigned to the last centroids and each list
+  holds its rows in ascending row id.
+* Probe order: ascending (squared centroid distance, list id).
+* Heap order: the total order on (squared distance, id).  r is the square root of the
+  K-th smallest squared distance held, or +inf while fewer than K are held.  A candidate
+  that survives every test is kept iff the heap is not full or (dist^2, id) < (r^2, id_r).
+* Round schedule (fixes the threshold each DCO sees): the probe ranks are split into
+  rounds; every candidate of a round is compared against the heap as it was when the
+  round started, and the round's accepted candidates are merged in at its end.
+  ``per_rank`` = one probed list per round; ``doubling`` = rank boundaries 0,1,2,4,8,...;
+  ``sequential`` = one candidate per round in list order, i.e. the heap is updated after
+  every DCO exactly as the paper describes.
+
+Low-precision index (not in the paper): tests use the stored coordinates; a survivor whose
+stored-precision S_D exceeds (1 + delta) r^2 is dropped, the rest are reranked with the
+exact coordinates before the keep rule above.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+from . import estimator, pca
+
+
+# ----------------------------------------------------------------------------- k-means
+
+def _sqdist(A, B, chunk=16_384, direct_limit=100_000_000):
+    """Exact float64 squared distances between rows of A and rows of B ([len(A), len(B)])."""
+    A = np.asarray(A, dtype=np.float64)
+    B = np.asarray(B, dtype=np.float64)
+    if A.shape[0] * B.shape[0] * A.shape[1] <= direct_limit:
+        return np.stack([np.sum((B - a) ** 2, axis=1) for a in A]) if len(A) else np.zeros((0, len(B)))
+    out = np.empty((A.shape[0], B.shape[0]))
+    bn = np.einsum("ij,ij->i", B, B)
+    for s in range(0, A.shape[0], chunk):
+        a = A[s:s + chunk]
+        an = np.einsum("ij,ij->i", a, a)
+        out[s:s + chunk] = np.maximum(an[:, None] - 2.0 * (a @ B.T) + bn[None, :], 0.0)
+    return out
+
+
+def assign(X, C, chunk=65_536) -> np.ndarray:
+    """Nearest centroid per row; ties to the lower centroid id (argmin keeps the first)."""
+    X = np.asarray(X)
+    lab = np.empty(X.shape[0], dtype=np.int64)
+    for s in range(0, X.shape[0], chunk):
+        lab[s:s + chunk] = np.argmin(_sqdist(X[s:s + chunk], C), axis=1)
+    return lab
+
+
+def kmeans(X, init_rows, iters: int = 10) -> np.ndarray:
+    """Lloyd's algorithm from the seed rows ``init_rows``; returns float64 centroids."""
+    X = np.asarray(X)
+    C = X[np.asarray(init_rows)].astype(np.float64)
+    for _ in range(iters):
+        lab = assign(X, C)
+        counts = np.bincount(lab, minlength=C.shape[0])
+        order = np.argsort(lab, kind="stable")
+        nonempty = np.nonzero(counts)[0]
+        starts = np.concatenate([[0], np.cumsum(counts)[:-1]])[nonempty]
+        sums = np.add.reduceat(X[order].astype(np.float64), starts, axis=0)
+        C[nonempty] = sums / counts[nonempty, None]
+    return C
+
+
+def objective(X, C, lab) -> float:
+    """Mean squared distance of each row to its assigned centroid."""
+    X = np.asarray(X, dtype=np.float64)
+    return float(np.mean(np.sum((X - np.asarray(C)[lab]) ** 2, axis=1)))
+
+
+def build_lists(lab, nlist: int):
+    """(offsets [nlist+1], ids [N]): rows grouped by list, ascending row id inside a list."""
+    order = np.argsort(np.asarray(lab), kind="stable").astype(np.int64)
+    counts = np.bincount(lab, minlength=nlist)
+    return np.concatenate([[0], np.cumsum(counts)]).astype(np.int64), order
+
+
+def probe_order(q_rot, cent_rot, nprobe: int):
+    """(list ids, squared distances) of the nprobe nearest centroids, by (dist^2, list id)."""
+    d2 = np.sum((np.asarray(cent_rot, dtype=np.float64) - q_rot) ** 2, axis=1)
+    order = np.lexsort((np.arange(len(d2)), d2))
+    return order[:nprobe], d2[order]
+
+
+# ----------------------------------------------------------------------------- index
+
+@dataclasses.dataclass
+class Index:
+    """Everything a search reads.  ``Y[ids]`` returns the stored rotated rows (float64)."""
+    mu: np.ndarray
+    W: np.ndarray
+    lam: np.ndarray
+    eps: np.ndarray            # eps_d, d = 1..D (Eq. (14))
+    centroids: np.ndarray      # original basis
+    offsets: np.ndarray
+    ids: np.ndarray
+    Y: object                  # stored rotated coordinates, indexable by row id
+    Y_exact: object = None     # exact rotated coordinates for the low-precision rerank
+    delta: float = 0.0         # rerank margin
+
+    @property
+    def dim(self):
+        return self.W.shape[0]
+
+    @property
+    def nlist(self):
+        return len(self.offsets) - 1
+
+    def cent_rot(self):
+        return pca.rotate(self.centroids, self.mu, self.W)
+
+
+class LazyRotated:
+    """Rotated rows computed on demand: rows -> (X[rows] - mu) @ W (optionally rounded)."""
+
+    def __init__(self, X, mu, W, rounding=None):
+        self.X, self.mu, self.W, self.rounding = X, mu, W, rounding
+
+    def __getitem__(self, rows):
+        y = pca.rotate(np.asarray(self.X)[rows], self.mu, self.W)
+        return self.rounding(y) if self.rounding is not None else y
+
+
+def build(X, nlist, init_rows, pairs, p_s=0.1, iters=10, store=None):
+    """Oracle index: transform, k-means lists and eps_d from the given pairs.
+
+    ``store`` (callable on rotated rows, e.g. ``lowp`` rounding) makes a low-precision
+    index: tests read the rounded coordinates, eps_d and delta are calibrated on them.
+    """
+    from . import lowp
+    mu, W, lam = pca.fit(X)
+    C = kmeans(X, init_rows, iters)
+    offsets, ids = build_lists(assign(X, C), nlist)
+    Y = pca.rotate(X, mu, W)
+    if store is None:
+        eps, _, _ = estimator.calibrate(X, W, lam, pairs, p_s)
+        return Index(mu, W, lam, eps, C, offsets, ids, Y)
+    Ys = store(Y)
+    eps, _, _ = estimator.calibrate(X, W, lam, pairs, p_s, stored=Ys)
+    delta = lowp.rerank_margin(X, pairs, Ys)
+    return Index(mu, W, lam, eps, C, offsets, ids, Ys, Y_exact=Y, delta=delta)
+
+
+# ----------------------------------------------------------------------------- search
+
+def round_bounds(nprobe: int, schedule: str):
+    """Probe-rank ranges [lo, hi) of each round."""
+    if schedule == "per_rank":
+        return [(t, t + 1) for t in range(nprobe)]
+    if schedule == "doubling":
+        b, x = [0], 1
+        while x < nprobe:
+            b.append(x)
+            x *= 2
+        b.append(nprobe)
+        return list(zip(b[:-1], b[1:]))
+    raise ValueError(schedule)
+
+
+def tested_dims(D: int, delta_d: int) -> np.ndarray:
+    """d = Delta_d, 2 Delta_d, ... strictly below D (Algorithm 1 with the d <= D reading)."""
+    return np.arange(delta_d, D, delta_d, dtype=np.int64)
+
+
+def _merge(hd, hi, d2, ids, K):
+    d = np.concatenate([hd, d2])
+    i = np.concatenate([hi, ids])
+    o = np.lexsort((i, d))
+    gap = math.inf
+    if len(o) > K and d[o[K - 1]] > 0:
+        gap = abs(d[o[K]] - d[o[K - 1]]) / d[o[K - 1]]
+    return d[o[:K]], i[o[:K]], gap
+
+
+def _scan_round(index, q, cand, hd, hi, K, delta_d, mode, tests):
+    """DCOs of one round against the snapshot heap (hd, hi).  Returns accepted + logs."""
+    D = index.dim
+    full = len(hd) == K
+    r2 = float(hd[-1]) if full else math.inf
+    idr = int(hi[-1]) if full else -1
+    r = math.sqrt(r2)
+    diff = index.Y[cand] - q
+    S = np.cumsum(diff * diff, axis=1)
+    n = len(cand)
+    margin = math.inf
+    exit_d = np.full(n, D, dtype=np.int64)
+    alive = np.ones(n, dtype=bool)
+    if mode == "dade" and len(tests) and full:
+        c = estimator.scale(index.lam)
+        est = estimator.estimate(S[:, tests - 1], c[tests - 1][None, :])
+        rej = estimator.reject(est, index.eps[tests - 1][None, :], r)
+        anyrej = rej.any(axis=1)
+        first = np.where(anyrej, rej.argmax(axis=1), len(tests) - 1)
+        exit_d = np.where(anyrej, tests[first], D)
+        alive = ~anyrej
+        bound2 = ((1.0 + index.eps[tests - 1]) * r) ** 2
+        with np.errstate(divide="ignore", invalid="ignore"):
+            rel = np.abs(est ** 2 - bound2[None, :]) / bound2[None, :]
+        seen = np.arange(len(tests))[None, :] <= np.where(anyrej, first, len(tests) - 1)[:, None]
+        rel = np.where(seen & np.isfinite(rel), rel, math.inf)
+        if rel.size:
+            margin = min(margin, float(rel.min()))
+    SD = S[:, -1]
+    if index.Y_exact is not None:
+        if full:
+            gate = (1.0 + index.delta) * r2
+            if alive.any():
+                margin = min(margin, float(np.min(np.abs(SD[alive] - gate) / gate)))
+            alive = alive & (SD <= gate)
+        de = index.Y_exact[cand[alive]] - q
+        SDx = SD.copy()
+        SDx[alive] = np.sum(de * de, axis=1)
+        SD = SDx
+    if full:
+        keep = alive & ((SD < r2) | ((SD == r2) & (cand < idr)))
+        if alive.any() and r2 > 0:
+            margin = min(margin, float(np.min(np.abs(SD[alive] - r2) / r2)))
+    else:
+        keep = alive
+    return SD[keep], cand[keep], exit_d, margin, int(alive.sum())
+
+
+def search(index: Index, Q, K, nprobe, delta_d: int, mode: str = "dade",
+           schedule: str = "per_rank", log: bool = False, q_rot=None):
+    """IVF search.  K and nprobe are ints or per-query arrays.
+
+    Returns (ids [nq, Kmax] int64 with -1 padding, dist2 [nq, Kmax] with +inf padding, logs).
+    ``logs`` (when requested) holds per-query: dcos, dims (sum of d_exit), accepted,
+    survivors (reached d = D), rounds, min_margin (smallest relative margin of any test,
+    rerank gate, keep compare or top-K boundary) and probe_gap (smallest relative gap
+    between consecutive probed centroid distances).
+    """
+    Q = np.asarray(Q)
+    nq = Q.shape[0]
+    Ks = np.broadcast_to(np.asarray(K, dtype=np.int64), (nq,))
+    nps = np.minimum(np.broadcast_to(np.asarray(nprobe, dtype=np.int64), (nq,)), index.nlist)
+    Kmax = int(Ks.max()) if nq else 0
+    Qr = pca.rotate(Q, index.mu, index.W) if q_rot is None else np.asarray(q_rot, np.float64)
+    cent = index.cent_rot()
+    D = index.dim
+    tests = tested_dims(D, delta_d)
+    out_i = np.full((nq, Kmax), -1, dtype=np.int64)
+    out_d = np.full((nq, Kmax), np.inf)
+    logs = {k: np.zeros(nq, dtype=np.float64) for k in
+            ("dcos", "dims", "accepted", "survivors", "rounds", "min_margin", "probe_gap")}
+    for qi in range(nq):
+        q = Qr[qi]
+        Kq, npq = int(Ks[qi]), int(nps[qi])
+        probes, d2c = probe_order(q, cent, npq)
+        gaps = np.diff(d2c[:min(npq + 1, len(d2c))])
+        den = d2c[1:min(npq + 1, len(d2c))]
+        with np.errstate(divide="ignore", invalid="ignore"):
+            rg = np.where(den > 0, gaps / den, math.inf)
+        logs["probe_gap"][qi] = float(rg.min()) if rg.size else math.inf
+        lists = [index.ids[index.offsets[l]:index.offsets[l + 1]] for l in probes]
+        if schedule == "sequential":
+            rounds = [np.array([c], dtype=np.int64) for lst in lists for c in lst]
+        else:
+            rounds = [np.concatenate(lists[lo:hi]) if hi > lo else np.zeros(0, np.int64)
+                      for lo, hi in round_bounds(npq, schedule)]
+        hd = np.zeros(0)
+        hi = np.zeros(0, dtype=np.int64)
+        mm = math.inf
+        for cand in rounds:
+            logs["rounds"][qi] += 1
+            if len(cand) == 0:
+                continue
+            d2, ids, exit_d, margin, surv = _scan_round(index, q, cand, hd, hi, Kq, delta_d, mode, tests)
+            logs["dcos"][qi] += len(cand)
+            logs["dims"][qi] += float(exit_d.sum())
+            logs["accepted"][qi] += len(ids)
+            logs["survivors"][qi] += surv
+            mm = min(mm, margin)
+            hd, hi, gap = _merge(hd, hi, d2, ids, Kq)
+            mm = min(mm, gap)
+        logs["min_margin"][qi] = mm
+        out_i[qi, :len(hi)] = hi
+        out_d[qi, :len(hd)] = hd
+    return (out_i, out_d, logs) if log else (out_i, out_d)
+
+
+def search_scalar(index: Index, Q, K: int, nprobe: int, delta_d: int, mode: str = "dade",
+                  log: bool = False):
+    """The paper's semantics, one candidate at a time: Algorithm 1 (or FDScanning) per
+    candidate against the live heap maximum, heap updated after every DCO.
+
+    A separate, scalar code path (``dco`` + an explicit heap) for small inputs; it must
+    agree with ``search(..., schedule="sequential")``.
+    """
+    import heapq
+
+    from . import dco
+    Q = np.asarray(Q)
+    Qr = pca.rotate(Q, index.mu, index.W)
+    cent = index.cent_rot()
+    c = estimator.scale(index.lam)
+    out_i = np.full((len(Q), K), -1, dtype=np.int64)
+    out_d = np.full((len(Q), K), np.inf)
+    logs = {"dims": np.zeros(len(Q)), "accepted": np.zeros(len(Q))}
+    for qi, q in enumerate(Qr):
+        probes, _ = probe_order(q, cent, min(nprobe, index.nlist))
+        heap = []  # entries (-dist2, -id): the root is the largest (dist2, id)
+        for l in probes:
+            for cid in index.ids[index.offsets[l]:index.offsets[l + 1]]:
+                full = len(heap) == K
+                r2 = -heap[0][0] if full else math.inf
+                idr = -heap[0][1] if full else -1
+                o = index.Y[np.array([cid])][0]
+                if mode == "dade":
+                    ok, dis, d_exit = dco.dade_dco(o, q, math.sqrt(r2), delta_d, index.eps, c)
+                else:
+                    ok, dis, d_exit = dco.fd_dco(o, q, math.sqrt(r2))
+                logs["dims"][qi] += d_exit
+                if not ok:
+                    continue
+                d2 = float(np.sum((q - o) ** 2))
+                if full and not (d2 < r2 or (d2 == r2 and cid < idr)):
+                    continue
+                logs["accepted"][qi] += 1
+                heapq.heappush(heap, (-d2, -int(cid)))
+                if len(heap) > K:
+                    heapq.heappop(heap)
+        items = sorted((-a, -b) for a, b in heap)
+        for j, (d2, cid) in enumerate(items):
+            out_i[qi, j] = cid
+            out_d[qi, j] = d2
+    return (out_i, out_d, logs) if log else (out_i, out_d)
