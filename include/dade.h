@@ -1,0 +1,192 @@
+/*
+ * dade.h -- C ABI of an MI355X (gfx950) engine for DADE distance comparisons inside an
+ * IVF scan (data-aware distance estimation, arXiv 2411.17229).
+ *
+ * The operations follow the paper's problem statement:
+ *   - Definition 1 (DCO): given q, o and r, decide whether dis(q, o) <= r and return dis.
+ *   - Algorithm 1: the DCO runs over growing prefixes of Delta_d transformed dimensions,
+ *     estimates the distance with Eq. (13), tests H0: dis < r by rejecting when
+ *     dis' > (1 + eps_d) r (eps_d from Eq. (14)), and compares exactly at d = D.
+ *   - End of the Methodology section: IVF selects the N_probe clusters nearest to the query
+ *     and scans their candidates with one DCO each against the maximum of a size-K heap.
+ *   - After Eq. (13): objects are transformed once by the PCA matrix W (Eqs. (10)-(12)) and
+ *     stored; eps_d is estimated from sampled data objects.
+ *
+ * Conventions shared by every call
+ *   - Device pointers: X, Q, per-query K / nprobe arrays and outputs are caller-owned device
+ *     memory of the current HIP device.  The library copies what it keeps; it keeps no
+ *     caller pointer after a call returns.  Host pointers are marked "host".
+ *   - Matrices are row-major and dense: X is [n x dim], Q is [nq x dim] (leading dimension
+ *     dim), outputs are [nq x k] (leading dimension k).
+ *   - stream: a hipStream_t passed as void*.  dade_search only enqueues work on it; its
+ *     outputs are valid once the stream has been synchronised.  dade_build_index,
+ *     dade_rotate, dade_calibrate and dade_import synchronise the stream before returning.
+ *   - Distances are SQUARED Euclidean distances (equal in the original and rotated bases,
+ *     Lemma 1).  Ids are 0-based row indices of X.
+ *   - Errors: every int-returning call returns DADE_OK or a negative dade_status, and
+ *     dade_last_error() returns a message for the calling thread's last failure.  A failed
+ *     call leaves the index as it was.  No C++ exception crosses this interface.
+ *   - Thread safety: calls on different indexes may run concurrently; calls on one index
+ *     must be serialised by the caller.
+ */
+#ifndef DADE_H
+#define DADE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dade_index dade_index; /* opaque; owns every device buffer of one index */
+
+typedef enum {
+  DADE_OK = 0,
+  DADE_EINVAL = -1,  /* an argument is out of range or a required pointer is NULL */
+  DADE_ESTATE = -2,  /* the call is not allowed in the index's current state */
+  DADE_ENOMEM = -3,  /* the HBM budget would be exceeded or an allocation failed */
+  DADE_EDEVICE = -4  /* a HIP runtime / library error; the message names it */
+} dade_status;
+
+typedef enum { DADE_F32 = 0, DADE_BF16 = 1, DADE_F16 = 2 } dade_dtype;
+
+/* FULL_D = FDScanning (Experiments, Algorithms): every DCO reads all D dimensions. */
+typedef enum { DADE_MODE_DADE = 0, DADE_MODE_FULL_D = 1 } dade_mode;
+
+/* Which heap state each DCO's threshold r comes from (the paper's IVF updates the heap after
+ * every candidate, which makes a parallel scan order-dependent).  The probe ranks of a query
+ * are split into rounds; every DCO of a round sees the heap as it was when the round started;
+ * the round's accepted candidates are merged at its end.  PER_RANK: one probed list per
+ * round.  DOUBLING: rank boundaries 0, 1, 2, 4, 8, ... */
+typedef enum { DADE_SCHED_PER_RANK = 0, DADE_SCHED_DOUBLING = 1 } dade_schedule;
+
+/* Index state machine: BUILT -> ROTATED -> CALIBRATED. */
+typedef enum { DADE_STATE_BUILT = 1, DADE_STATE_ROTATED = 2, DADE_STATE_CALIBRATED = 3 } dade_state;
+
+typedef struct {
+  int32_t kmeans_iters;       /* Lloyd iterations; 0 means 10 */
+  int32_t store_dtype;        /* dade_dtype of the stored rotated coordinates */
+  const int64_t* init_rows;   /* host, nlist distinct row ids seeding k-means; NULL: drawn
+                                 from `seed` */
+  uint64_t seed;
+  int64_t hbm_budget_bytes;   /* upper bound on device memory this index may hold; 0: none */
+} dade_build_opts;
+
+typedef struct {
+  int32_t delta_d;            /* Delta_d of Algorithm 1, in [1, dim]; 0 means 32 (or dim if
+                                 smaller) */
+  int32_t mode;               /* dade_mode */
+  int32_t schedule;           /* dade_schedule */
+  float rerank_delta;         /* low-precision stores only: a survivor whose stored-precision
+                                 S_D exceeds (1 + rerank_delta) r^2 is dropped before the exact
+                                 FP32 rerank; < 0 means the calibrated value */
+  int64_t* stats;             /* device, nullable: [nq x 4] int64 per query: DCOs, dimensions
+                                 read (sum of the d at which each DCO ended), candidates kept,
+                                 candidates reranked */
+  int32_t record_times;       /* nonzero: time the stages with HIP events (dade_stage_times) */
+} dade_search_opts;
+
+/* Host copies of an index's artifacts (for checkpoints and for parity checks).  All arrays
+ * are caller-allocated with the sizes dade_index_info reports. */
+typedef struct {
+  int64_t n;
+  int32_t dim;
+  int32_t nlist;
+  int32_t store_dtype;
+  int32_t state;
+  double* W;            /* [dim x dim]; W[i*dim + k] = component i of w_k (Eq. (11)) */
+  double* mu;           /* [dim] the mean of X (Lemma 1) */
+  double* lambda;       /* [dim] eigenvalues, descending (Eq. (12)) */
+  double* T;            /* [dim] reduced thresholds T_d, d = 1..dim (T_dim = 1); on import
+                           NULL means "not calibrated" */
+  double delta;         /* rerank margin (low-precision stores) */
+  double* centroids;    /* [nlist x dim] in the original basis */
+  int64_t* list_offsets;/* [nlist + 1] */
+  int64_t* list_ids;    /* [n] row ids grouped by list, ascending inside a list */
+} dade_artifacts;
+
+/*
+ * dade_build_index -- IVF lists by k-means (Experiments, Parameter Setting: N_c clusters as in
+ * Faiss).  Copies X (device, [n x dim] FP32) into the index, runs `kmeans_iters` Lloyd
+ * iterations in FP32 from the seed rows, assigns every row to its nearest final centroid
+ * (ties: lower centroid id) and groups rows by list in ascending row id.
+ * Requires 1 <= dim <= 4096, 1 <= nlist <= min(n, 8192), n < 2^31.
+ * On success *out is a new index in state BUILT.  Synchronises `stream`.
+ */
+int dade_build_index(const float* X, int64_t n, int32_t dim, int32_t nlist,
+                     const dade_build_opts* opts, void* stream, dade_index** out);
+
+/*
+ * dade_rotate -- the data-aware transform (Lemma 1; Eqs. (10)-(12)).  Computes mu and the
+ * 1/N second moment of the centred data in FP64 on the device, its eigendecomposition in FP64
+ * (rocSOLVER syevd), sorts eigenpairs by descending eigenvalue and fixes each eigenvector's
+ * sign (largest-magnitude entry positive).  Then stores every object once as W^T (x - mu) in
+ * the index's store dtype (round to nearest even), laid out list by list.
+ * Requires state >= BUILT; leaves the index ROTATED (a previous calibration is dropped).
+ * Synchronises `stream`.
+ */
+int dade_rotate(dade_index* ix, void* stream);
+
+/*
+ * dade_calibrate -- eps_d of Eq. (14) in its reduced form.  For each pair (a, b) of distinct
+ * data rows, f_d = S_d / ||x_a - x_b||^2 with S_d the squared norm of the first d rotated
+ * coordinates of x_a - x_b (FP64; for BF16/FP16 stores, of the stored coordinates).  Pairs
+ * with x_a == x_b are dropped (M pairs remain).  T_d is the ceil((1 - alpha) M)-th smallest
+ * f_d (alpha = P_s); rejecting when S_d > T_d r^2 is the same test as dis' > (1 + eps_d) r.
+ * For low-precision stores the rerank margin is the ceil(0.999 M)-th smallest relative error
+ * |S_D - ||x_a - x_b||^2| / ||x_a - x_b||^2.
+ * pairs: host [n_pairs x 2] int64 row ids, or NULL to draw n_pairs uniform ordered pairs with
+ * a != b from `seed`.  Requires state >= ROTATED, 0 < alpha < 1, n_pairs >= 1, M >= 1.
+ * Leaves the index CALIBRATED.  Synchronises `stream`.
+ */
+int dade_calibrate(dade_index* ix, double alpha, const int64_t* pairs, int64_t n_pairs,
+                   uint64_t seed, void* stream);
+
+/*
+ * dade_search -- IVF search with one DCO per candidate (Algorithm 1, or FDScanning in FULL_D
+ * mode).  Q: device [nq x dim] FP32.  k, nprobe: the values for every query, or the maxima
+ * when k_per_query / nprobe_per_query (device int32 [nq], nullable) are given; per-query
+ * values are clamped into [1, k] and [1, nprobe]; nprobe is clamped to nlist.
+ * Outputs: out_ids (device int64 [nq x k]) and out_dist2 (device FP32 [nq x k]), each row
+ * ascending by (squared distance, id), padded with (-1, +inf) after the query's K results.
+ * Requires state CALIBRATED for DADE mode and >= ROTATED for FULL_D; 1 <= k <= 128;
+ * nprobe >= 1; nq >= 0 (nq == 0 is a no-op).  opts may be NULL (defaults).
+ * Asynchronous on `stream`.
+ */
+int dade_search(dade_index* ix, const float* Q, int64_t nq, int32_t k, int32_t nprobe,
+                const int32_t* k_per_query, const int32_t* nprobe_per_query,
+                const dade_search_opts* opts, int64_t* out_ids, float* out_dist2,
+                void* stream);
+
+/* dade_index_info -- sizes and state (any pointer may be NULL). */
+int dade_index_info(const dade_index* ix, int64_t* n, int32_t* dim, int32_t* nlist,
+                    int32_t* store_dtype, int32_t* state);
+
+/* dade_export -- copy the artifacts to caller-allocated host arrays (NULL arrays are skipped).
+ * W, mu, lambda need state >= ROTATED; T and delta need CALIBRATED. */
+int dade_export(const dade_index* ix, dade_artifacts* out);
+
+/*
+ * dade_import -- an index from artifacts (host) and the base vectors X (device [n x dim]).
+ * Uses the given lists, centroids, W and mu instead of computing them and packs the store as
+ * dade_rotate does; with a non-NULL T it is CALIBRATED, else ROTATED.  opts->store_dtype
+ * selects the store.  Synchronises `stream`.
+ */
+int dade_import(const dade_artifacts* a, const float* X, const dade_build_opts* opts,
+                void* stream, dade_index** out);
+
+/* dade_stage_times -- after a dade_search with record_times set, wait for it and return the
+ * elapsed milliseconds of its stages: [0] query rotation, [1] probe selection, [2] list scan. */
+int dade_stage_times(dade_index* ix, float* ms3);
+
+/* dade_destroy -- free the index and all its device memory (NULL is a no-op). */
+void dade_destroy(dade_index* ix);
+
+/* dade_last_error -- message of the calling thread's last failed call ("" if none). */
+const char* dade_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DADE_H */

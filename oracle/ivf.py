@@ -113,6 +113,7 @@ class Index:
     Y: object                  # stored rotated coordinates, indexable by row id
     Y_exact: object = None     # exact rotated coordinates for the low-precision rerank
     delta: float = 0.0         # rerank margin
+    T: np.ndarray = None       # reduced-form thresholds T_d (same decisions as eps_d)
 
     @property
     def dim(self):
@@ -149,12 +150,12 @@ def build(X, nlist, init_rows, pairs, p_s=0.1, iters=10, store=None):
     offsets, ids = build_lists(assign(X, C), nlist)
     Y = pca.rotate(X, mu, W)
     if store is None:
-        eps, _, _ = estimator.calibrate(X, W, lam, pairs, p_s)
-        return Index(mu, W, lam, eps, C, offsets, ids, Y)
+        eps, T, _ = estimator.calibrate(X, W, lam, pairs, p_s)
+        return Index(mu, W, lam, eps, C, offsets, ids, Y, T=T)
     Ys = store(Y)
-    eps, _, _ = estimator.calibrate(X, W, lam, pairs, p_s, stored=Ys)
+    eps, T, _ = estimator.calibrate(X, W, lam, pairs, p_s, stored=Ys)
     delta = lowp.rerank_margin(X, pairs, Ys)
-    return Index(mu, W, lam, eps, C, offsets, ids, Ys, Y_exact=Y, delta=delta)
+    return Index(mu, W, lam, eps, C, offsets, ids, Ys, Y_exact=Y, delta=delta, T=T)
 
 
 # ----------------------------------------------------------------------------- search

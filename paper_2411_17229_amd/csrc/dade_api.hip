@@ -1,0 +1,720 @@
+// C ABI of the DADE-IVF engine: index lifecycle, offline build (k-means lists, FP64 transform,
+// eps_d calibration) and the search pipeline (query rotation -> probe selection -> list scan).
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "dade.h"
+#include "kernels.h"
+
+using namespace dade;
+
+namespace {
+thread_local std::string g_err;
+
+// splitmix64 (Steele, Lea and Flood, OOPSLA 2014), used only when the caller passes no
+// seed rows / calibration pairs.
+struct SplitMix64 {
+  uint64_t s;
+  uint64_t next() {
+    uint64_t z = (s += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+  }
+  uint64_t below(uint64_t n) { return static_cast<uint64_t>((static_cast<unsigned __int128>(next()) * n) >> 64); }
+};
+
+}  // namespace
+
+namespace dade {
+void set_error(const std::string& msg) { g_err = msg; }
+std::string hip_msg(hipError_t e, const char* what) {
+  return std::string(what) + ": " + hipGetErrorName(e) + " (" + hipGetErrorString(e) + ")";
+}
+}  // namespace dade
+
+#define FAIL(code, msg)      \
+  do {                       \
+    dade::set_error(msg);    \
+    return (code);           \
+  } while (0)
+
+#define HIPC(expr)                                             \
+  do {                                                         \
+    hipError_t e_ = (expr);                                    \
+    if (e_ != hipSuccess) FAIL(DADE_EDEVICE, hip_msg(e_, #expr)); \
+  } while (0)
+
+struct dade_index {
+  int device = 0;
+  int64_t n = 0;
+  int dim = 0, dp = 0, nlist = 0, store = DADE_F32, state = 0;
+  int64_t budget = 0, held = 0;
+  // device buffers
+  float* X = nullptr;          // [n x dp] original vectors (zero padded)
+  float* cent = nullptr;       // [nlist x dp] centroids, original basis
+  int64_t* d_off = nullptr;    // [nlist + 1]
+  int32_t* d_ids = nullptr;    // [n] packed position -> row id
+  int64_t* d_pos = nullptr;    // [n] row id -> packed position
+  float* d_W = nullptr;        // [dp x dp] FP32 copy of W (zero padded)
+  float* d_mu = nullptr;       // [dp]
+  float* d_cent_rot = nullptr; // [nlist x dp]
+  float* d_cent_norm = nullptr;// [nlist]
+  void* d_store = nullptr;     // [n x dp] rotated coordinates, list order
+  float* d_T = nullptr;        // [dim]
+  // host artifacts
+  std::vector<double> W, mu, lam, T, cent_h;
+  double delta = 0.0;
+  std::vector<int64_t> off_h, ids_h;
+  // search workspace
+  float* w_qpad = nullptr; float* w_qrot = nullptr; float* w_pd = nullptr;
+  int32_t* w_probes = nullptr; unsigned long long* w_acc = nullptr; int* w_counter = nullptr;
+  int64_t w_nq = 0, w_np = 0, w_acc_n = 0;
+  hipEvent_t ev[4] = {};
+  bool ev_made = false, ev_used = false;
+  int cus = 256;
+
+  std::vector<void*> owned;
+};
+
+namespace {
+
+size_t dtype_size(int dt) { return dt == DADE_F32 ? 4 : 2; }
+
+int dev_alloc(dade_index* ix, void** p, size_t bytes) {
+  *p = nullptr;
+  if (bytes == 0) bytes = 16;
+  if (ix->budget > 0 && ix->held + int64_t(bytes) > ix->budget)
+    FAIL(DADE_ENOMEM, "HBM budget exceeded: need " + std::to_string(ix->held + bytes) + " bytes, budget " +
+                          std::to_string(ix->budget));
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    (void)hipGetLastError();
+    FAIL(DADE_ENOMEM, hip_msg(e, "hipMalloc"));
+  }
+  ix->held += int64_t(bytes);
+  ix->owned.push_back(*p);
+  return DADE_OK;
+}
+
+template <typename T>
+int alloc_t(dade_index* ix, T** p, size_t count) {
+  void* v = nullptr;
+  int rc = dev_alloc(ix, &v, count * sizeof(T));
+  *p = static_cast<T*>(v);
+  return rc;
+}
+
+void dev_free(dade_index* ix, void* p, size_t bytes) {
+  if (!p) return;
+  auto it = std::find(ix->owned.begin(), ix->owned.end(), p);
+  if (it != ix->owned.end()) ix->owned.erase(it);
+  (void)hipFree(p);
+  ix->held -= int64_t(bytes == 0 ? 16 : bytes);
+}
+
+int check_device_pointer(const void* p, const char* name) {
+  if (!p) FAIL(DADE_EINVAL, std::string(name) + " is NULL");
+  hipPointerAttribute_t attr;
+  hipError_t e = hipPointerGetAttributes(&attr, p);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    FAIL(DADE_EINVAL, std::string(name) + " is not a device pointer");
+  }
+  if (attr.type != hipMemoryTypeDevice && attr.type != hipMemoryTypeManaged)
+    FAIL(DADE_EINVAL, std::string(name) + " is not device memory");
+  return DADE_OK;
+}
+
+// Common index creation: copy X (padded) and record sizes.
+int make_index(const float* X, int64_t n, int32_t dim, int32_t nlist, const dade_build_opts* opts,
+               hipStream_t s, dade_index** out) {
+  if (!out) FAIL(DADE_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (n < 1 || n >= (int64_t(1) << 31)) FAIL(DADE_EINVAL, "n must be in [1, 2^31)");
+  if (dim < 1 || dim > 4096) FAIL(DADE_EINVAL, "dim must be in [1, 4096]");
+  if (nlist < 1 || nlist > n || nlist > 8192) FAIL(DADE_EINVAL, "nlist must be in [1, min(n, 8192)]");
+  int rc = check_device_pointer(X, "X");
+  if (rc) return rc;
+  int store = opts ? opts->store_dtype : DADE_F32;
+  if (store != DADE_F32 && store != DADE_BF16 && store != DADE_F16) FAIL(DADE_EINVAL, "bad store_dtype");
+  auto* ix = new dade_index();
+  HIPC(hipGetDevice(&ix->device));
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ix->device) == hipSuccess && cus > 0)
+    ix->cus = cus;
+  ix->n = n; ix->dim = dim; ix->dp = pad_dim(dim); ix->nlist = nlist; ix->store = store;
+  ix->budget = opts ? opts->hbm_budget_bytes : 0;
+  if ((rc = alloc_t(ix, &ix->X, size_t(n) * ix->dp))) { dade_destroy(ix); return rc; }
+  hipError_t e = launch_pad_rows(X, n, dim, ix->X, ix->dp, s);
+  if (e != hipSuccess) { dade_destroy(ix); FAIL(DADE_EDEVICE, hip_msg(e, "pad X")); }
+  *out = ix;
+  return DADE_OK;
+}
+
+// Lists from row labels: stable counting sort (ascending row id inside a list).
+int set_lists(dade_index* ix, const std::vector<int32_t>& lab, hipStream_t s) {
+  const int64_t n = ix->n;
+  ix->off_h.assign(ix->nlist + 1, 0);
+  for (int64_t i = 0; i < n; ++i) ix->off_h[lab[i] + 1]++;
+  for (int l = 0; l < ix->nlist; ++l) ix->off_h[l + 1] += ix->off_h[l];
+  ix->ids_h.assign(n, 0);
+  std::vector<int64_t> fill(ix->off_h.begin(), ix->off_h.end() - 1);
+  for (int64_t i = 0; i < n; ++i) ix->ids_h[fill[lab[i]]++] = i;
+  std::vector<int32_t> ids32(n);
+  std::vector<int64_t> pos(n);
+  for (int64_t p = 0; p < n; ++p) { ids32[p] = int32_t(ix->ids_h[p]); pos[ix->ids_h[p]] = p; }
+  int rc;
+  if (!ix->d_off && (rc = alloc_t(ix, &ix->d_off, ix->nlist + 1))) return rc;
+  if (!ix->d_ids && (rc = alloc_t(ix, &ix->d_ids, n))) return rc;
+  if (!ix->d_pos && (rc = alloc_t(ix, &ix->d_pos, n))) return rc;
+  HIPC(hipMemcpyAsync(ix->d_off, ix->off_h.data(), sizeof(int64_t) * (ix->nlist + 1), hipMemcpyHostToDevice, s));
+  HIPC(hipMemcpyAsync(ix->d_ids, ids32.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s));
+  HIPC(hipMemcpyAsync(ix->d_pos, pos.data(), sizeof(int64_t) * n, hipMemcpyHostToDevice, s));
+  HIPC(hipStreamSynchronize(s));
+  return DADE_OK;
+}
+
+// Store W (host FP64) on the device, rotate the centroids, pack the store.
+int apply_transform(dade_index* ix, hipStream_t s) {
+  const int dim = ix->dim, dp = ix->dp, nl = ix->nlist;
+  int rc;
+  std::vector<float> Wf(size_t(dp) * dp, 0.f), muf(dp, 0.f);
+  for (int i = 0; i < dim; ++i)
+    for (int k = 0; k < dim; ++k) Wf[size_t(i) * dp + k] = float(ix->W[size_t(i) * dim + k]);
+  for (int i = 0; i < dim; ++i) muf[i] = float(ix->mu[i]);
+  if (!ix->d_W && (rc = alloc_t(ix, &ix->d_W, size_t(dp) * dp))) return rc;
+  if (!ix->d_mu && (rc = alloc_t(ix, &ix->d_mu, dp))) return rc;
+  HIPC(hipMemcpyAsync(ix->d_W, Wf.data(), sizeof(float) * Wf.size(), hipMemcpyHostToDevice, s));
+  HIPC(hipMemcpyAsync(ix->d_mu, muf.data(), sizeof(float) * dp, hipMemcpyHostToDevice, s));
+
+  // rotated centroids c' = W^T (c - mu) in FP64 on the device
+  double *dA = nullptr, *dWd = nullptr, *dC = nullptr;
+  std::vector<double> A(size_t(nl) * dim);
+  for (int l = 0; l < nl; ++l)
+    for (int i = 0; i < dim; ++i) A[size_t(l) * dim + i] = ix->cent_h[size_t(l) * dim + i] - ix->mu[i];
+  if ((rc = alloc_t(ix, &dA, A.size()))) return rc;
+  if ((rc = alloc_t(ix, &dWd, size_t(dim) * dim))) { dev_free(ix, dA, A.size() * 8); return rc; }
+  if ((rc = alloc_t(ix, &dC, A.size()))) { dev_free(ix, dA, A.size() * 8); dev_free(ix, dWd, size_t(dim) * dim * 8); return rc; }
+  HIPC(hipMemcpyAsync(dA, A.data(), sizeof(double) * A.size(), hipMemcpyHostToDevice, s));
+  HIPC(hipMemcpyAsync(dWd, ix->W.data(), sizeof(double) * size_t(dim) * dim, hipMemcpyHostToDevice, s));
+  HIPC(launch_dgemm(dA, dim, dWd, dim, dC, dim, nl, dim, dim, s));
+  HIPC(hipMemcpyAsync(A.data(), dC, sizeof(double) * A.size(), hipMemcpyDeviceToHost, s));
+  HIPC(hipStreamSynchronize(s));
+  dev_free(ix, dA, A.size() * 8);
+  dev_free(ix, dWd, size_t(dim) * dim * 8);
+  dev_free(ix, dC, A.size() * 8);
+  std::vector<float> cr(size_t(nl) * dp, 0.f);
+  for (int l = 0; l < nl; ++l)
+    for (int i = 0; i < dim; ++i) cr[size_t(l) * dp + i] = float(A[size_t(l) * dim + i]);
+  if (!ix->d_cent_rot && (rc = alloc_t(ix, &ix->d_cent_rot, cr.size()))) return rc;
+  if (!ix->d_cent_norm && (rc = alloc_t(ix, &ix->d_cent_norm, nl))) return rc;
+  HIPC(hipMemcpyAsync(ix->d_cent_rot, cr.data(), sizeof(float) * cr.size(), hipMemcpyHostToDevice, s));
+  HIPC(launch_row_norms(ix->d_cent_rot, nl, dp, ix->d_cent_norm, s));
+
+  // packed store: row p = W^T (X[ids[p]] - mu), in list order
+  if (!ix->d_store && (rc = dev_alloc(ix, &ix->d_store, size_t(ix->n) * dp * dtype_size(ix->store)))) return rc;
+  GemmArgs g;
+  g.M = int(ix->n); g.N = dp; g.K = dp;
+  g.A = ix->X; g.lda = dp; g.a_rows = ix->d_ids; g.a_shift = ix->d_mu;
+  g.B = ix->d_W; g.ldb = dp; g.C = ix->d_store; g.ldc = dp;
+  const GemmEpilogue epi = ix->store == DADE_F32 ? kEpiPackF32 : (ix->store == DADE_BF16 ? kEpiPackBF16 : kEpiPackF16);
+  HIPC(launch_gemm(g, epi, s));
+  HIPC(hipStreamSynchronize(s));
+  return DADE_OK;
+}
+
+int upload_T(dade_index* ix, hipStream_t s) {
+  int rc;
+  std::vector<float> Tf(ix->dim);
+  for (int d = 0; d < ix->dim; ++d) Tf[d] = float(ix->T[d]);
+  if (!ix->d_T && (rc = alloc_t(ix, &ix->d_T, ix->dim))) return rc;
+  HIPC(hipMemcpyAsync(ix->d_T, Tf.data(), sizeof(float) * ix->dim, hipMemcpyHostToDevice, s));
+  HIPC(hipStreamSynchronize(s));
+  return DADE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* dade_last_error(void) { return g_err.c_str(); }
+
+void dade_destroy(dade_index* ix) {
+  if (!ix) return;
+  (void)hipDeviceSynchronize();
+  for (void* p : ix->owned) (void)hipFree(p);
+  if (ix->ev_made)
+    for (auto& e : ix->ev) (void)hipEventDestroy(e);
+  delete ix;
+}
+
+int dade_index_info(const dade_index* ix, int64_t* n, int32_t* dim, int32_t* nlist,
+                    int32_t* store_dtype, int32_t* state) {
+  if (!ix) FAIL(DADE_EINVAL, "index is NULL");
+  if (n) *n = ix->n;
+  if (dim) *dim = ix->dim;
+  if (nlist) *nlist = ix->nlist;
+  if (store_dtype) *store_dtype = ix->store;
+  if (state) *state = ix->state;
+  return DADE_OK;
+}
+
+int dade_build_index(const float* X, int64_t n, int32_t dim, int32_t nlist,
+                     const dade_build_opts* opts, void* stream, dade_index** out) {
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  dade_index* ix = nullptr;
+  int rc = make_index(X, n, dim, nlist, opts, s, &ix);
+  if (rc) return rc;
+  const int dp = ix->dp;
+  const int iters = (opts && opts->kmeans_iters > 0) ? opts->kmeans_iters : 10;
+  // seed rows
+  std::vector<int64_t> init(nlist);
+  if (opts && opts->init_rows) {
+    std::vector<char> seen(n, 0);
+    for (int l = 0; l < nlist; ++l) {
+      const int64_t r = opts->init_rows[l];
+      if (r < 0 || r >= n || seen[r]) { dade_destroy(ix); FAIL(DADE_EINVAL, "init_rows must be distinct ids in [0, n)"); }
+      seen[r] = 1;
+      init[l] = r;
+    }
+  } else {  // Floyd's sampling of nlist distinct rows
+    SplitMix64 rng{opts ? opts->seed : 0};
+    std::vector<int64_t> chosen;
+    std::vector<char> seen(n, 0);
+    for (int64_t j = n - nlist; j < n; ++j) {
+      int64_t t = int64_t(rng.below(uint64_t(j + 1)));
+      if (seen[t]) t = j;
+      seen[t] = 1;
+      chosen.push_back(t);
+    }
+    std::sort(chosen.begin(), chosen.end());
+    init = chosen;
+  }
+  int64_t* d_init = nullptr;
+  unsigned long long* best = nullptr;
+  double* sums = nullptr;
+  int* counts = nullptr;
+  int32_t* labels = nullptr;
+  float* cn = nullptr;
+  auto cleanup = [&]() {
+    dev_free(ix, cn, sizeof(float) * nlist);
+    dev_free(ix, d_init, sizeof(int64_t) * nlist);
+    dev_free(ix, best, sizeof(unsigned long long) * n);
+    dev_free(ix, sums, sizeof(double) * size_t(nlist) * dp);
+    dev_free(ix, counts, sizeof(int) * nlist);
+    dev_free(ix, labels, sizeof(int32_t) * n);
+  };
+#define BUILD_TRY(expr)                          \
+  do {                                           \
+    int rc_ = (expr);                            \
+    if (rc_) { cleanup(); dade_destroy(ix); return rc_; } \
+  } while (0)
+#define BUILD_HIP(expr)                                                      \
+  do {                                                                       \
+    hipError_t e_ = (expr);                                                  \
+    if (e_ != hipSuccess) { cleanup(); dade_destroy(ix); FAIL(DADE_EDEVICE, hip_msg(e_, #expr)); } \
+  } while (0)
+  BUILD_TRY(alloc_t(ix, &ix->cent, size_t(nlist) * dp));
+  BUILD_TRY(alloc_t(ix, &d_init, nlist));
+  BUILD_TRY(alloc_t(ix, &best, n));
+  BUILD_TRY(alloc_t(ix, &sums, size_t(nlist) * dp));
+  BUILD_TRY(alloc_t(ix, &counts, nlist));
+  BUILD_TRY(alloc_t(ix, &labels, n));
+  BUILD_TRY(alloc_t(ix, &cn, nlist));
+  BUILD_HIP(hipMemcpyAsync(d_init, init.data(), sizeof(int64_t) * nlist, hipMemcpyHostToDevice, s));
+  BUILD_HIP(launch_gather_rows(ix->X, dp, d_init, nlist, ix->cent, s));
+  GemmArgs g;
+  g.M = int(n); g.N = nlist; g.K = dp;
+  g.A = ix->X; g.lda = dp; g.B = ix->cent; g.ldb = dp; g.b_trans = true;
+  g.col_norm = cn; g.row_best = best;
+  for (int it = 0; it <= iters; ++it) {
+    BUILD_HIP(launch_row_norms(ix->cent, nlist, dp, cn, s));
+    BUILD_HIP(launch_fill_u64(best, n, ~0ull, s));
+    BUILD_HIP(launch_gemm(g, kEpiArgmin, s));
+    if (it == iters) break;  // final assignment to the last centroids
+    BUILD_HIP(launch_fill_f64(sums, int64_t(nlist) * dp, 0.0, s));
+    BUILD_HIP(launch_fill_i32(counts, nlist, 0, s));
+    BUILD_HIP(launch_kmeans_accumulate(ix->X, n, dp, best, sums, counts, s));
+    BUILD_HIP(launch_kmeans_finalize(sums, counts, nlist, dp, ix->cent, s));
+  }
+  BUILD_HIP(launch_labels_from_best(best, n, labels, s));
+  std::vector<int32_t> lab(n);
+  std::vector<float> cf(size_t(nlist) * dp);
+  BUILD_HIP(hipMemcpyAsync(lab.data(), labels, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
+  BUILD_HIP(hipMemcpyAsync(cf.data(), ix->cent, sizeof(float) * cf.size(), hipMemcpyDeviceToHost, s));
+  BUILD_HIP(hipStreamSynchronize(s));
+  cleanup();
+  d_init = nullptr; best = nullptr; sums = nullptr; counts = nullptr; labels = nullptr; cn = nullptr;
+#undef BUILD_TRY
+#undef BUILD_HIP
+  for (int64_t i = 0; i < n; ++i)
+    if (lab[i] < 0 || lab[i] >= nlist) { dade_destroy(ix); FAIL(DADE_EDEVICE, "k-means produced an invalid label"); }
+  ix->cent_h.assign(size_t(nlist) * dim, 0.0);
+  for (int l = 0; l < nlist; ++l)
+    for (int i = 0; i < dim; ++i) ix->cent_h[size_t(l) * dim + i] = cf[size_t(l) * dp + i];
+  rc = set_lists(ix, lab, s);
+  if (rc) { dade_destroy(ix); return rc; }
+  ix->state = DADE_STATE_BUILT;
+  *out = ix;
+  return DADE_OK;
+}
+
+int dade_rotate(dade_index* ix, void* stream) {
+  if (!ix) FAIL(DADE_EINVAL, "index is NULL");
+  if (ix->state < DADE_STATE_BUILT) FAIL(DADE_ESTATE, "rotate needs a built index");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int dim = ix->dim, dp = ix->dp;
+  double *mean = nullptr, *C = nullptr, *evals = nullptr, *offd = nullptr;
+  rocblas_int* info = nullptr;
+  int rc;
+  auto cleanup = [&]() {
+    dev_free(ix, mean, sizeof(double) * dim);
+    dev_free(ix, C, sizeof(double) * size_t(dim) * dim);
+    dev_free(ix, evals, sizeof(double) * dim);
+    dev_free(ix, offd, sizeof(double) * dim);
+    dev_free(ix, info, sizeof(rocblas_int));
+  };
+  if ((rc = alloc_t(ix, &mean, dim)) || (rc = alloc_t(ix, &C, size_t(dim) * dim)) ||
+      (rc = alloc_t(ix, &evals, dim)) || (rc = alloc_t(ix, &offd, dim)) || (rc = alloc_t(ix, &info, 1))) {
+    cleanup();
+    return rc;
+  }
+  hipError_t e = launch_column_mean(ix->X, ix->n, dp, dim, mean, s);
+  if (e == hipSuccess) e = launch_covariance(ix->X, ix->n, dp, dim, mean, C, dim, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) { cleanup(); FAIL(DADE_EDEVICE, hip_msg(e, "covariance")); }
+  rocblas_handle h = nullptr;
+  if (rocblas_create_handle(&h) != rocblas_status_success) { cleanup(); FAIL(DADE_EDEVICE, "rocblas_create_handle failed"); }
+  rocblas_set_stream(h, s);
+  rocblas_status st = rocsolver_dsyevd(h, rocblas_evect_original, rocblas_fill_upper, dim, C, dim, evals, offd, info);
+  std::vector<double> V(size_t(dim) * dim), ev(dim), mu(dim);
+  rocblas_int hinfo = 0;
+  e = hipSuccess;
+  if (st == rocblas_status_success) {
+    e = hipMemcpyAsync(V.data(), C, sizeof(double) * V.size(), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(ev.data(), evals, sizeof(double) * dim, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(mu.data(), mean, sizeof(double) * dim, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(&hinfo, info, sizeof(rocblas_int), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+  }
+  rocblas_destroy_handle(h);
+  cleanup();
+  if (st != rocblas_status_success) FAIL(DADE_EDEVICE, std::string("rocsolver_dsyevd: ") + rocblas_status_to_string(st));
+  if (e != hipSuccess) FAIL(DADE_EDEVICE, hip_msg(e, "eigen readback"));
+  if (hinfo != 0) FAIL(DADE_EDEVICE, "rocsolver_dsyevd did not converge (info " + std::to_string(hinfo) + ")");
+  // V is column-major: eigenvector j = V[j*dim + i], eigenvalues ascending.
+  std::vector<int> order(dim);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return ev[a] > ev[b]; });
+  std::vector<double> W(size_t(dim) * dim), lam(dim);
+  for (int k = 0; k < dim; ++k) {
+    const int j = order[k];
+    lam[k] = ev[j];
+    int lead = 0;
+    for (int i = 1; i < dim; ++i)
+      if (std::fabs(V[size_t(j) * dim + i]) > std::fabs(V[size_t(j) * dim + lead])) lead = i;
+    const double sg = V[size_t(j) * dim + lead] < 0 ? -1.0 : 1.0;
+    for (int i = 0; i < dim; ++i) W[size_t(i) * dim + k] = sg * V[size_t(j) * dim + i];
+  }
+  ix->W = W; ix->lam = lam; ix->mu = mu;
+  rc = apply_transform(ix, s);
+  if (rc) return rc;
+  ix->T.clear();
+  ix->state = DADE_STATE_ROTATED;
+  return DADE_OK;
+}
+
+int dade_calibrate(dade_index* ix, double alpha, const int64_t* pairs, int64_t n_pairs,
+                   uint64_t seed, void* stream) {
+  if (!ix) FAIL(DADE_EINVAL, "index is NULL");
+  if (ix->state < DADE_STATE_ROTATED) FAIL(DADE_ESTATE, "calibrate needs a rotated index");
+  if (!(alpha > 0.0 && alpha < 1.0)) FAIL(DADE_EINVAL, "alpha must be in (0, 1)");
+  if (n_pairs < 1) FAIL(DADE_EINVAL, "n_pairs must be >= 1");
+  if (ix->n < 2) FAIL(DADE_EINVAL, "calibration needs at least two rows");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int dim = ix->dim, dp = ix->dp;
+  std::vector<int64_t> P(size_t(n_pairs) * 2);
+  if (pairs) {
+    for (int64_t i = 0; i < 2 * n_pairs; ++i) {
+      if (pairs[i] < 0 || pairs[i] >= ix->n) FAIL(DADE_EINVAL, "pair ids must be in [0, n)");
+      P[i] = pairs[i];
+    }
+  } else {
+    SplitMix64 rng{seed};
+    for (int64_t i = 0; i < n_pairs; ++i) {
+      const int64_t a = int64_t(rng.below(uint64_t(ix->n)));
+      const int64_t b = (a + 1 + int64_t(rng.below(uint64_t(ix->n - 1)))) % ix->n;
+      P[2 * i] = a; P[2 * i + 1] = b;
+    }
+  }
+  int64_t m = n_pairs;
+  int64_t* dP = nullptr;
+  double *delta = nullptr, *dis2 = nullptr, *Y = nullptr, *f = nullptr, *rel = nullptr, *dW = nullptr;
+  auto cleanup = [&]() {
+    dev_free(ix, dP, sizeof(int64_t) * 2 * n_pairs);
+    dev_free(ix, delta, sizeof(double) * size_t(n_pairs) * dp);
+    dev_free(ix, dis2, sizeof(double) * n_pairs);
+    dev_free(ix, Y, sizeof(double) * size_t(n_pairs) * dp);
+    dev_free(ix, f, sizeof(double) * size_t(std::max(dim - 1, 1)) * n_pairs);
+    dev_free(ix, rel, sizeof(double) * n_pairs);
+    dev_free(ix, dW, sizeof(double) * size_t(dp) * dp);
+    dP = nullptr; delta = dis2 = Y = f = rel = dW = nullptr;
+  };
+#define CAL_HIP(expr)                                                             \
+  do {                                                                            \
+    hipError_t e_ = (expr);                                                       \
+    if (e_ != hipSuccess) { cleanup(); FAIL(DADE_EDEVICE, hip_msg(e_, #expr)); } \
+  } while (0)
+  int rc;
+  if ((rc = alloc_t(ix, &dP, 2 * n_pairs)) || (rc = alloc_t(ix, &delta, size_t(n_pairs) * dp)) ||
+      (rc = alloc_t(ix, &dis2, n_pairs))) {
+    cleanup();
+    return rc;
+  }
+  // pass 1: drop pairs whose vectors are equal
+  CAL_HIP(hipMemcpyAsync(dP, P.data(), sizeof(int64_t) * 2 * m, hipMemcpyHostToDevice, s));
+  CAL_HIP(launch_pair_diff(ix->X, dp, dP, m, delta, dis2, s));
+  std::vector<double> d2(m);
+  CAL_HIP(hipMemcpyAsync(d2.data(), dis2, sizeof(double) * m, hipMemcpyDeviceToHost, s));
+  CAL_HIP(hipStreamSynchronize(s));
+  int64_t kept = 0;
+  for (int64_t i = 0; i < m; ++i)
+    if (d2[i] > 0.0) { P[2 * kept] = P[2 * i]; P[2 * kept + 1] = P[2 * i + 1]; ++kept; }
+  if (kept == 0) { cleanup(); FAIL(DADE_EINVAL, "every calibration pair has equal vectors"); }
+  if (kept != m) {
+    m = kept;
+    CAL_HIP(hipMemcpyAsync(dP, P.data(), sizeof(int64_t) * 2 * m, hipMemcpyHostToDevice, s));
+    CAL_HIP(launch_pair_diff(ix->X, dp, dP, m, delta, dis2, s));
+  }
+  // rotated prefix terms: exact FP64 rotation for an FP32 store, stored coordinates otherwise
+  if ((rc = alloc_t(ix, &f, size_t(std::max(dim - 1, 1)) * n_pairs)) || (rc = alloc_t(ix, &rel, n_pairs))) {
+    cleanup();
+    return rc;
+  }
+  const double* rows = nullptr;
+  if (ix->store == DADE_F32) {
+    if ((rc = alloc_t(ix, &Y, size_t(n_pairs) * dp)) || (rc = alloc_t(ix, &dW, size_t(dp) * dp))) { cleanup(); return rc; }
+    std::vector<double> Wp(size_t(dp) * dp, 0.0);
+    for (int i = 0; i < dim; ++i)
+      for (int k = 0; k < dim; ++k) Wp[size_t(i) * dp + k] = ix->W[size_t(i) * dim + k];
+    CAL_HIP(hipMemcpyAsync(dW, Wp.data(), sizeof(double) * Wp.size(), hipMemcpyHostToDevice, s));
+    CAL_HIP(launch_dgemm(delta, dp, dW, dp, Y, dp, int(m), dp, dp, s));
+    rows = Y;
+  } else {
+    if ((rc = alloc_t(ix, &Y, size_t(n_pairs) * dp))) { cleanup(); return rc; }
+    CAL_HIP(launch_pair_diff_stored(ix->d_store, ix->store, dp, ix->d_pos, dP, m, Y, s));
+    rows = Y;
+  }
+  CAL_HIP(launch_prefix_fraction(rows, dp, m, dim, dis2, f, rel, s));
+  std::vector<double> fh(size_t(std::max(dim - 1, 0)) * m), relh(m);
+  if (dim > 1) CAL_HIP(hipMemcpyAsync(fh.data(), f, sizeof(double) * fh.size(), hipMemcpyDeviceToHost, s));
+  CAL_HIP(hipMemcpyAsync(relh.data(), rel, sizeof(double) * m, hipMemcpyDeviceToHost, s));
+  CAL_HIP(hipStreamSynchronize(s));
+  cleanup();
+#undef CAL_HIP
+  // order statistic ceil((1 - alpha) M), 1-based
+  auto ostat = [](std::vector<double>::iterator b, int64_t cnt, double p) {
+    int64_t k = int64_t(std::ceil(p * double(cnt)));
+    k = std::min(std::max<int64_t>(k, 1), cnt);
+    std::nth_element(b, b + (k - 1), b + cnt);
+    return *(b + (k - 1));
+  };
+  std::vector<double> T(dim, 1.0);
+  for (int d = 0; d + 1 < dim; ++d) T[d] = ostat(fh.begin() + size_t(d) * m, m, 1.0 - alpha);
+  ix->T = T;
+  ix->delta = (ix->store == DADE_F32) ? 0.0 : ostat(relh.begin(), m, 0.999);
+  rc = upload_T(ix, s);
+  if (rc) return rc;
+  ix->state = DADE_STATE_CALIBRATED;
+  return DADE_OK;
+}
+
+int dade_export(const dade_index* ix, dade_artifacts* a) {
+  if (!ix || !a) FAIL(DADE_EINVAL, "index or artifacts is NULL");
+  a->n = ix->n; a->dim = ix->dim; a->nlist = ix->nlist; a->store_dtype = ix->store; a->state = ix->state;
+  const size_t D = ix->dim;
+  if (a->centroids) std::memcpy(a->centroids, ix->cent_h.data(), sizeof(double) * ix->cent_h.size());
+  if (a->list_offsets) std::memcpy(a->list_offsets, ix->off_h.data(), sizeof(int64_t) * ix->off_h.size());
+  if (a->list_ids) std::memcpy(a->list_ids, ix->ids_h.data(), sizeof(int64_t) * ix->ids_h.size());
+  if (a->W || a->mu || a->lambda) {
+    if (ix->state < DADE_STATE_ROTATED) FAIL(DADE_ESTATE, "W, mu and lambda exist after rotate");
+    if (a->W) std::memcpy(a->W, ix->W.data(), sizeof(double) * D * D);
+    if (a->mu) std::memcpy(a->mu, ix->mu.data(), sizeof(double) * D);
+    if (a->lambda) std::memcpy(a->lambda, ix->lam.data(), sizeof(double) * D);
+  }
+  if (a->T) {
+    if (ix->state < DADE_STATE_CALIBRATED) FAIL(DADE_ESTATE, "T exists after calibrate");
+    std::memcpy(a->T, ix->T.data(), sizeof(double) * D);
+  }
+  a->delta = ix->delta;
+  return DADE_OK;
+}
+
+int dade_import(const dade_artifacts* a, const float* X, const dade_build_opts* opts, void* stream,
+                dade_index** out) {
+  if (!a) FAIL(DADE_EINVAL, "artifacts is NULL");
+  if (!a->W || !a->mu || !a->lambda || !a->centroids || !a->list_offsets || !a->list_ids)
+    FAIL(DADE_EINVAL, "import needs W, mu, lambda, centroids and lists");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  dade_index* ix = nullptr;
+  int rc = make_index(X, a->n, a->dim, a->nlist, opts, s, &ix);
+  if (rc) return rc;
+  const int dim = ix->dim, nl = ix->nlist;
+  const int64_t n = ix->n;
+  if (a->list_offsets[0] != 0 || a->list_offsets[nl] != n) { dade_destroy(ix); FAIL(DADE_EINVAL, "list offsets must span [0, n]"); }
+  std::vector<int32_t> lab(n, -1);
+  for (int l = 0; l < nl; ++l) {
+    if (a->list_offsets[l + 1] < a->list_offsets[l]) { dade_destroy(ix); FAIL(DADE_EINVAL, "list offsets must not decrease"); }
+    for (int64_t p = a->list_offsets[l]; p < a->list_offsets[l + 1]; ++p) {
+      const int64_t id = a->list_ids[p];
+      if (id < 0 || id >= n || lab[id] != -1) { dade_destroy(ix); FAIL(DADE_EINVAL, "list ids must be a permutation of [0, n)"); }
+      if (p > a->list_offsets[l] && a->list_ids[p - 1] >= id) { dade_destroy(ix); FAIL(DADE_EINVAL, "list ids must ascend inside a list"); }
+      lab[id] = l;
+    }
+  }
+  ix->cent_h.assign(a->centroids, a->centroids + size_t(nl) * dim);
+  std::vector<float> cf(size_t(nl) * ix->dp, 0.f);
+  for (int l = 0; l < nl; ++l)
+    for (int i = 0; i < dim; ++i) cf[size_t(l) * ix->dp + i] = float(a->centroids[size_t(l) * dim + i]);
+  if ((rc = alloc_t(ix, &ix->cent, cf.size()))) { dade_destroy(ix); return rc; }
+  hipError_t e = hipMemcpyAsync(ix->cent, cf.data(), sizeof(float) * cf.size(), hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) { dade_destroy(ix); FAIL(DADE_EDEVICE, hip_msg(e, "centroids")); }
+  if ((rc = set_lists(ix, lab, s))) { dade_destroy(ix); return rc; }
+  ix->W.assign(a->W, a->W + size_t(dim) * dim);
+  ix->mu.assign(a->mu, a->mu + dim);
+  ix->lam.assign(a->lambda, a->lambda + dim);
+  if ((rc = apply_transform(ix, s))) { dade_destroy(ix); return rc; }
+  ix->state = DADE_STATE_ROTATED;
+  if (a->T) {
+    ix->T.assign(a->T, a->T + dim);
+    ix->delta = a->delta;
+    if ((rc = upload_T(ix, s))) { dade_destroy(ix); return rc; }
+    ix->state = DADE_STATE_CALIBRATED;
+  }
+  *out = ix;
+  return DADE_OK;
+}
+
+int dade_search(dade_index* ix, const float* Q, int64_t nq, int32_t k, int32_t nprobe,
+                const int32_t* k_per_query, const int32_t* nprobe_per_query,
+                const dade_search_opts* opts, int64_t* out_ids, float* out_dist2, void* stream) {
+  if (!ix) FAIL(DADE_EINVAL, "index is NULL");
+  if (nq < 0 || nq >= (int64_t(1) << 31)) FAIL(DADE_EINVAL, "nq must be in [0, 2^31)");
+  if (k < 1 || k > kMaxK) FAIL(DADE_EINVAL, "k must be in [1, 128]");
+  if (nprobe < 1) FAIL(DADE_EINVAL, "nprobe must be >= 1");
+  dade_search_opts o{};
+  o.delta_d = 0; o.mode = DADE_MODE_DADE; o.schedule = DADE_SCHED_PER_RANK; o.rerank_delta = -1.f;
+  if (opts) o = *opts;
+  const int dd = o.delta_d > 0 ? o.delta_d : std::min(32, ix->dim);
+  if (dd < 1 || dd > ix->dim) FAIL(DADE_EINVAL, "delta_d must be in [1, dim]");
+  if (o.mode != DADE_MODE_DADE && o.mode != DADE_MODE_FULL_D) FAIL(DADE_EINVAL, "bad mode");
+  if (o.schedule != DADE_SCHED_PER_RANK && o.schedule != DADE_SCHED_DOUBLING) FAIL(DADE_EINVAL, "bad schedule");
+  if (ix->state < DADE_STATE_ROTATED) FAIL(DADE_ESTATE, "search needs a rotated index");
+  if (o.mode == DADE_MODE_DADE && ix->state < DADE_STATE_CALIBRATED) FAIL(DADE_ESTATE, "DADE mode needs a calibrated index");
+  if (nq == 0) return DADE_OK;
+  int rc;
+  if ((rc = check_device_pointer(Q, "Q")) || (rc = check_device_pointer(out_ids, "out_ids")) ||
+      (rc = check_device_pointer(out_dist2, "out_dist2")))
+    return rc;
+  if (k_per_query && (rc = check_device_pointer(k_per_query, "k_per_query"))) return rc;
+  if (nprobe_per_query && (rc = check_device_pointer(nprobe_per_query, "nprobe_per_query"))) return rc;
+  if (o.stats && (rc = check_device_pointer(o.stats, "stats"))) return rc;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int dp = ix->dp, nl = ix->nlist;
+  const int npm = std::min<int>(nprobe, nl);
+  // accept-buffer capacity: the most candidates one round can hold
+  std::vector<int64_t> sizes(nl);
+  for (int l = 0; l < nl; ++l) sizes[l] = ix->off_h[l + 1] - ix->off_h[l];
+  std::sort(sizes.begin(), sizes.end(), std::greater<int64_t>());
+  int widest = 1;
+  if (o.schedule == DADE_SCHED_DOUBLING) {
+    int b = 1;
+    while (b < npm) { widest = std::max(widest, std::min(2 * b, npm) - b); b *= 2; }
+  }
+  int64_t cap = 0;
+  for (int i = 0; i < widest && i < nl; ++i) cap += sizes[i];
+  cap = std::max<int64_t>(cap, 1);
+  const int grid = int(std::min<int64_t>(nq, int64_t(ix->cus) * 8));
+  // workspace
+  if (nq > ix->w_nq || npm > ix->w_np) {
+    const int64_t new_nq = std::max(nq, ix->w_nq), new_np = std::max<int64_t>(npm, ix->w_np);
+    HIPC(hipStreamSynchronize(s));
+    dev_free(ix, ix->w_qpad, sizeof(float) * ix->w_nq * dp);
+    dev_free(ix, ix->w_qrot, sizeof(float) * ix->w_nq * dp);
+    dev_free(ix, ix->w_pd, sizeof(float) * ix->w_nq * nl);
+    dev_free(ix, ix->w_probes, sizeof(int32_t) * ix->w_nq * ix->w_np);
+    ix->w_qpad = ix->w_qrot = ix->w_pd = nullptr;
+    ix->w_probes = nullptr;
+    ix->w_nq = ix->w_np = 0;
+    if ((rc = alloc_t(ix, &ix->w_qpad, size_t(new_nq) * dp)) || (rc = alloc_t(ix, &ix->w_qrot, size_t(new_nq) * dp)) ||
+        (rc = alloc_t(ix, &ix->w_pd, size_t(new_nq) * nl)) || (rc = alloc_t(ix, &ix->w_probes, size_t(new_nq) * new_np)))
+      return rc;
+    ix->w_nq = new_nq; ix->w_np = new_np;
+  }
+  if (int64_t(grid) * cap > ix->w_acc_n) {
+    HIPC(hipStreamSynchronize(s));
+    dev_free(ix, ix->w_acc, sizeof(unsigned long long) * ix->w_acc_n);
+    ix->w_acc = nullptr;
+    ix->w_acc_n = 0;
+    if ((rc = alloc_t(ix, &ix->w_acc, size_t(grid) * cap))) return rc;
+    ix->w_acc_n = int64_t(grid) * cap;
+  }
+  if (!ix->w_counter && (rc = alloc_t(ix, &ix->w_counter, 2))) return rc;
+  if (o.record_times && !ix->ev_made) {
+    for (auto& e : ix->ev) HIPC(hipEventCreate(&e));
+    ix->ev_made = true;
+  }
+  if (o.record_times) HIPC(hipEventRecord(ix->ev[0], s));
+  // a1: q' = W^T (q - mu)
+  HIPC(launch_pad_rows(Q, nq, ix->dim, ix->w_qpad, dp, s));
+  GemmArgs g;
+  g.M = int(nq); g.N = dp; g.K = dp;
+  g.A = ix->w_qpad; g.lda = dp; g.a_shift = ix->d_mu;
+  g.B = ix->d_W; g.ldb = dp; g.C = ix->w_qrot; g.ldc = dp;
+  HIPC(launch_gemm(g, kEpiStore, s));
+  if (o.record_times) HIPC(hipEventRecord(ix->ev[1], s));
+  // a2: probe order by (squared centroid distance, list id)
+  GemmArgs p;
+  p.M = int(nq); p.N = nl; p.K = dp;
+  p.A = ix->w_qrot; p.lda = dp; p.B = ix->d_cent_rot; p.ldb = dp; p.b_trans = true;
+  p.C = ix->w_pd; p.ldc = nl; p.col_norm = ix->d_cent_norm;
+  HIPC(launch_gemm(p, kEpiProbe, s));
+  HIPC(launch_select_probes(ix->w_pd, nl, ix->w_qrot, dp, int(nq), dp, nl, npm, ix->w_probes, s));
+  if (o.record_times) HIPC(hipEventRecord(ix->ev[2], s));
+  // a3-a6: the list scan
+  HIPC(launch_fill_i32(ix->w_counter, 2, 0, s));
+  ScanArgs sa;
+  sa.nq = int(nq); sa.dim = ix->dim; sa.dp = dp; sa.delta_d = dd; sa.schedule = o.schedule;
+  sa.k_max = k; sa.nprobe_max = npm; sa.k_pq = k_per_query; sa.nprobe_pq = nprobe_per_query;
+  sa.qrot = ix->w_qrot; sa.qorig = ix->w_qpad; sa.probes = ix->w_probes; sa.list_off = ix->d_off;
+  sa.store = ix->d_store; sa.ids = ix->d_ids; sa.X = ix->X; sa.T = ix->d_T;
+  sa.rerank_delta = o.rerank_delta >= 0.f ? o.rerank_delta : float(ix->delta);
+  sa.out_ids = out_ids; sa.out_d2 = out_dist2; sa.stats = o.stats;
+  sa.acc_buf = ix->w_acc; sa.acc_cap = cap; sa.counter = ix->w_counter; sa.overflow = ix->w_counter + 1;
+  sa.grid = grid;
+  HIPC(launch_scan(sa, ix->store, o.mode, s));
+  if (o.record_times) {
+    HIPC(hipEventRecord(ix->ev[3], s));
+    ix->ev_used = true;
+  }
+  return DADE_OK;
+}
+
+int dade_stage_times(dade_index* ix, float* ms3) {
+  if (!ix || !ms3) FAIL(DADE_EINVAL, "index or output is NULL");
+  if (!ix->ev_used) FAIL(DADE_ESTATE, "no timed search was recorded");
+  HIPC(hipEventSynchronize(ix->ev[3]));
+  for (int i = 0; i < 3; ++i) HIPC(hipEventElapsedTime(&ms3[i], ix->ev[i], ix->ev[i + 1]));
+  return DADE_OK;
+}
+
+}  // extern "C"

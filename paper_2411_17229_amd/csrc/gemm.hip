@@ -1,0 +1,202 @@
+// FP32 GEMM on gfx950 matrix cores (v_mfma_f32_32x32x2_f32) with fused epilogues.
+//
+// Used for the dense contractions of the path: the query rotation Q' = (Q - mu) W, the
+// query-centroid distances of probe selection, the k-means assignment (argmin fused, no
+// distance matrix is written) and the packing of the rotated base (X[ids] - mu) W into the
+// list-ordered store.
+//
+// Tiling: a 256-thread workgroup (4 wave64s, 2 x 2) owns a BM x BN tile of C; each wave owns
+// (BM/2) x (BN/2) as a grid of 32 x 32 MFMA accumulators.  Each K-step stages a BK x BM slice
+// of A and a BK x BN slice of B in LDS, k-major, so that the MFMA operand reads of a half-wave
+// hit 32 consecutive floats.  The blockIdx -> tile mapping keeps consecutive N-tiles of one
+// M-tile on one XCD (blocks are dealt round-robin to the 8 XCDs).
+#include "kernels.h"
+
+namespace dade {
+namespace {
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+constexpr int BK = 16;
+constexpr int kThreads = 256;
+
+template <int BM, int BN, int EPI, bool BT>
+__global__ __launch_bounds__(kThreads) void gemm_kernel(GemmArgs g) {
+  constexpr int WM = BM / 2, WN = BN / 2;      // per-wave tile
+  constexpr int TM = WM / 32, TN = WN / 32;    // MFMA tiles per wave
+  constexpr int PA = BM + 4, PB = BN + 4;      // padded LDS rows
+  __shared__ float As[BK * PA];
+  __shared__ float Bs[BK * PB];
+
+  const int tiles_n = (g.N + BN - 1) / BN;
+  const int tiles_m = (g.M + BM - 1) / BM;
+  const int nblk = tiles_n * tiles_m;
+  // XCD-aware remap: hardware sends block b to XCD b % 8; give each XCD a contiguous range
+  // of logical tiles so neighbouring tiles (sharing an A panel) share that XCD's L2.
+  int b = blockIdx.x;
+  int logical = b;
+  if (nblk >= 64 && nblk % 8 == 0) logical = (b % 8) * (nblk / 8) + b / 8;
+  const int tm = logical / tiles_n, tn = logical % tiles_n;
+  const int m0 = tm * BM, n0 = tn * BN;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = (wave >> 1) * WM, wn = (wave & 1) * WN;
+
+  floatx16 acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.f;
+
+  for (int k0 = 0; k0 < g.K; k0 += BK) {
+    // ---- stage A: BM rows x BK columns, float4 along k, stored k-major.
+    for (int e = tid; e < BM * (BK / 4); e += kThreads) {
+      const int r = e / (BK / 4), q = e % (BK / 4);
+      const int gm = m0 + r;
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (gm < g.M) {
+        const int64_t src = g.a_rows ? g.a_rows[gm] : gm;
+        v = *reinterpret_cast<const float4*>(g.A + src * g.lda + k0 + 4 * q);
+        if (g.a_shift) {
+          const float4 s = *reinterpret_cast<const float4*>(g.a_shift + k0 + 4 * q);
+          v.x -= s.x; v.y -= s.y; v.z -= s.z; v.w -= s.w;
+        }
+      }
+      As[(4 * q + 0) * PA + r] = v.x;
+      As[(4 * q + 1) * PA + r] = v.y;
+      As[(4 * q + 2) * PA + r] = v.z;
+      As[(4 * q + 3) * PA + r] = v.w;
+    }
+    // ---- stage B: BK x BN.
+    if (!BT) {
+      for (int e = tid; e < BK * (BN / 4); e += kThreads) {
+        const int kk = e / (BN / 4), q = e % (BN / 4);
+        const int gn = n0 + 4 * q;
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        const float* src = g.B + int64_t(k0 + kk) * g.ldb + gn;
+        if (gn + 3 < g.N) {
+          v = *reinterpret_cast<const float4*>(src);
+        } else {
+          if (gn + 0 < g.N) v.x = src[0];
+          if (gn + 1 < g.N) v.y = src[1];
+          if (gn + 2 < g.N) v.z = src[2];
+        }
+        *reinterpret_cast<float4*>(&Bs[kk * PB + 4 * q]) = v;
+      }
+    } else {
+      for (int e = tid; e < BN * (BK / 4); e += kThreads) {
+        const int c = e / (BK / 4), q = e % (BK / 4);
+        const int gn = n0 + c;
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (gn < g.N) v = *reinterpret_cast<const float4*>(g.B + int64_t(gn) * g.ldb + k0 + 4 * q);
+        Bs[(4 * q + 0) * PB + c] = v.x;
+        Bs[(4 * q + 1) * PB + c] = v.y;
+        Bs[(4 * q + 2) * PB + c] = v.z;
+        Bs[(4 * q + 3) * PB + c] = v.w;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 2) {
+      const int kr = kk + (lane >> 5);
+      float av[TM], bv[TN];
+#pragma unroll
+      for (int i = 0; i < TM; ++i) av[i] = As[kr * PA + wm + 32 * i + (lane & 31)];
+#pragma unroll
+      for (int j = 0; j < TN; ++j) bv[j] = Bs[kr * PB + wn + 32 * j + (lane & 31)];
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[i], bv[j], acc[i][j], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+
+  // ---- epilogue.  Accumulator v of a lane holds C[row][col] with
+  //      col = lane % 32, row = 8 (v / 4) + 4 (lane / 32) + v % 4   (32x32 tile).
+#pragma unroll
+  for (int i = 0; i < TM; ++i) {
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+      const int col = n0 + wn + 32 * j + (lane & 31);
+      if (EPI == kEpiArgmin) {
+        const bool cok = col < g.N;
+        const float cn = cok ? g.col_norm[col] : 0.f;
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          const int row = m0 + wm + 32 * i + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+          unsigned long long key = ~0ull;
+          if (cok) key = (static_cast<unsigned long long>(ordered_bits(cn - 2.f * acc[i][j][v])) << 32) |
+                         static_cast<unsigned>(col);
+#pragma unroll
+          for (int off = 16; off >= 1; off >>= 1) {
+            const unsigned long long o = __shfl_xor(key, off, 32);
+            key = o < key ? o : key;
+          }
+          if ((lane & 31) == 0 && row < g.M) atomicMin(g.row_best + row, key);
+        }
+      } else {
+        if (col >= g.N) continue;
+        const float cn = (EPI == kEpiProbe) ? g.col_norm[col] : 0.f;
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          const int row = m0 + wm + 32 * i + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+          if (row >= g.M) continue;
+          const float x = acc[i][j][v];
+          const int64_t o = int64_t(row) * g.ldc + col;
+          if (EPI == kEpiStore || EPI == kEpiPackF32) {
+            static_cast<float*>(g.C)[o] = x;
+          } else if (EPI == kEpiProbe) {
+            static_cast<float*>(g.C)[o] = cn - 2.f * x;
+          } else if (EPI == kEpiPackBF16) {
+            static_cast<uint16_t*>(g.C)[o] = f32_to_bf16_rne(x);
+          } else if (EPI == kEpiPackF16) {
+            static_cast<__half*>(g.C)[o] = __float2half_rn(x);
+          }
+        }
+      }
+    }
+  }
+}
+
+template <int BM, int BN, int EPI>
+hipError_t launch_tile(const GemmArgs& a, hipStream_t s) {
+  const int tiles = ((a.M + BM - 1) / BM) * ((a.N + BN - 1) / BN);
+  if (tiles == 0) return hipSuccess;
+  if (a.b_trans)
+    hipLaunchKernelGGL((gemm_kernel<BM, BN, EPI, true>), dim3(tiles), dim3(kThreads), 0, s, a);
+  else
+    hipLaunchKernelGGL((gemm_kernel<BM, BN, EPI, false>), dim3(tiles), dim3(kThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+template <int EPI>
+hipError_t launch_epi(const GemmArgs& a, hipStream_t s) {
+  // Large problems use 128 x 128 tiles (2 x 2 MFMA tiles per wave), small ones 64 x 64 so
+  // that the grid still covers the 256 CUs.
+  const int64_t big_tiles = int64_t((a.M + 127) / 128) * ((a.N + 127) / 128);
+  if (big_tiles >= 1024) return launch_tile<128, 128, EPI>(a, s);
+  return launch_tile<64, 64, EPI>(a, s);
+}
+
+}  // namespace
+
+hipError_t launch_gemm(const GemmArgs& a, GemmEpilogue epi, hipStream_t s) {
+  if (a.K % BK != 0 || a.lda % 4 != 0 || a.ldb % 4 != 0) return hipErrorInvalidValue;
+  switch (epi) {
+    case kEpiStore: return launch_epi<kEpiStore>(a, s);
+    case kEpiProbe: return launch_epi<kEpiProbe>(a, s);
+    case kEpiArgmin: return launch_epi<kEpiArgmin>(a, s);
+    case kEpiPackF32: return launch_epi<kEpiPackF32>(a, s);
+    case kEpiPackBF16: return launch_epi<kEpiPackBF16>(a, s);
+    case kEpiPackF16: return launch_epi<kEpiPackF16>(a, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace dade

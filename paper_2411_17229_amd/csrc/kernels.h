@@ -1,0 +1,114 @@
+// Host launchers of the DADE-IVF kernels (each defined next to its kernel).
+#pragma once
+
+#include "common.h"
+
+namespace dade {
+
+// ---------------------------------------------------------------- FP32 MFMA GEMM (gemm.hip)
+// C[M x N] = op(A)[M x K] * B[K x N] with FP32 inputs and FP32 accumulation on MFMA.
+// A row m is A[a_rows ? a_rows[m] : m] minus a_shift (per column k, nullable).
+// B is [K x N] (ldb) or, with b_trans, given as [N x K] (ldb).  K % 16 == 0, lda/ldb % 4 == 0.
+enum GemmEpilogue {
+  kEpiStore = 0,    // C (float) = acc
+  kEpiProbe = 1,    // C (float) = col_norm[n] - 2 acc
+  kEpiArgmin = 2,   // row_best[m] = min over n of key(col_norm[n] - 2 acc, n)   (atomic)
+  kEpiPackF32 = 3,  // C (float)   = acc
+  kEpiPackBF16 = 4, // C (bf16)    = RNE(acc)
+  kEpiPackF16 = 5,  // C (half)    = RNE(acc)
+};
+
+struct GemmArgs {
+  int M = 0, N = 0, K = 0;
+  const float* A = nullptr;
+  int lda = 0;
+  const int32_t* a_rows = nullptr;
+  const float* a_shift = nullptr;
+  const float* B = nullptr;
+  int ldb = 0;
+  bool b_trans = false;
+  void* C = nullptr;
+  int ldc = 0;
+  const float* col_norm = nullptr;
+  unsigned long long* row_best = nullptr;
+};
+hipError_t launch_gemm(const GemmArgs& a, GemmEpilogue epi, hipStream_t s);
+
+// ---------------------------------------------------------------- small kernels (misc.hip)
+hipError_t launch_pad_rows(const float* src, int64_t rows, int cols, float* dst, int ld,
+                           hipStream_t s);
+hipError_t launch_gather_rows(const float* src, int ld, const int64_t* rows, int64_t count,
+                              float* dst, hipStream_t s);
+hipError_t launch_row_norms(const float* A, int64_t rows, int ld, float* out, hipStream_t s);
+hipError_t launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v, hipStream_t s);
+hipError_t launch_fill_i32(int* p, int64_t n, int v, hipStream_t s);
+hipError_t launch_fill_f64(double* p, int64_t n, double v, hipStream_t s);
+
+// k-means update: FP64 atomic sums of the rows of X per assigned centroid, then the means.
+hipError_t launch_kmeans_accumulate(const float* X, int64_t n, int ld,
+                                    const unsigned long long* best, double* sums, int* counts,
+                                    hipStream_t s);
+hipError_t launch_kmeans_finalize(const double* sums, const int* counts, int nlist, int ld,
+                                  float* centroids, hipStream_t s);
+hipError_t launch_labels_from_best(const unsigned long long* best, int64_t n, int32_t* labels,
+                                   hipStream_t s);
+
+// ---------------------------------------------------------------- FP64 kernels (fp64.hip)
+hipError_t launch_column_mean(const float* X, int64_t n, int ld, int dim, double* mean,
+                              hipStream_t s);
+// C[dim x dim] (ld) = (1/n) sum_i (x_i - mean)(x_i - mean)^T, upper and lower triangles.
+hipError_t launch_covariance(const float* X, int64_t n, int ld, int dim, const double* mean,
+                             double* C, int ldc, hipStream_t s);
+// C[M x N] = A[M x K] * B[K x N], FP64, row-major with leading dimensions.
+hipError_t launch_dgemm(const double* A, int lda, const double* B, int ldb, double* C, int ldc,
+                        int M, int N, int K, hipStream_t s);
+// Delta[i] = X[a_i] - X[b_i] in FP64 (ld columns), dis2[i] = ||Delta[i]||^2.
+hipError_t launch_pair_diff(const float* X, int ld, const int64_t* pairs, int64_t m,
+                            double* delta, double* dis2, hipStream_t s);
+// Same from stored coordinates: S from store rows pos[a], pos[b]; dis2 from X.
+hipError_t launch_pair_diff_stored(const void* store, int dtype, int ld, const int64_t* pos,
+                                   const int64_t* pairs, int64_t m, double* delta,
+                                   hipStream_t s);
+// f[d][i] = (sum_{k<=d} Y[i][k]^2) / dis2[i] for d < dim; rel[i] = |S_dim - dis2| / dis2.
+hipError_t launch_prefix_fraction(const double* Y, int ld, int64_t m, int dim,
+                                  const double* dis2, double* f, double* rel, hipStream_t s);
+
+// ---------------------------------------------------------------- probe selection (select.hip)
+// probes[q][0..nprobe) = ids of the nprobe smallest (qn[q] + pd[q][c], c), ascending.
+hipError_t launch_select_probes(const float* pd, int ld_pd, const float* qrot, int ld_q, int nq,
+                                int dim_p, int nlist, int nprobe, int32_t* probes,
+                                hipStream_t s);
+
+// ---------------------------------------------------------------- the list scan (scan.hip)
+struct ScanArgs {
+  int nq = 0;
+  int dim = 0;          // real dimensionality D
+  int dp = 0;           // padded row length of stored coordinates
+  int delta_d = 32;
+  int schedule = 0;     // 0 per-rank, 1 doubling
+  int k_max = 0;
+  int nprobe_max = 0;
+  const int32_t* k_pq = nullptr;
+  const int32_t* nprobe_pq = nullptr;
+  const float* qrot = nullptr;    // [nq x dp] rotated queries
+  const float* qorig = nullptr;   // [nq x dp] original queries (rerank)
+  const int32_t* probes = nullptr;  // [nq x nprobe_max]
+  const int64_t* list_off = nullptr;
+  const void* store = nullptr;    // packed rotated coordinates [n x dp]
+  const int32_t* ids = nullptr;   // packed position -> row id
+  const float* X = nullptr;       // [n x dp] original vectors by row id (rerank)
+  const float* T = nullptr;       // [dim] T_d
+  float rerank_delta = 0.f;
+  int64_t* out_ids = nullptr;
+  float* out_d2 = nullptr;
+  int64_t* stats = nullptr;
+  unsigned long long* acc_buf = nullptr;
+  int64_t acc_cap = 0;
+  int* counter = nullptr;
+  int* overflow = nullptr;
+  int grid = 0;
+};
+// dtype: 0 f32, 1 bf16, 2 f16; mode: 0 DADE, 1 FULL_D.
+hipError_t launch_scan(const ScanArgs& a, int dtype, int mode, hipStream_t s);
+
+}  // namespace dade

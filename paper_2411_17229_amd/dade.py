@@ -1,0 +1,244 @@
+"""Python binding of the C ABI in include/dade.h (argument marshalling only).
+
+Every function here has the name of the C entry point it calls.  Device buffers are torch
+tensors on the current HIP device (torch is used for memory and streams only); the stream
+is ``torch.cuda.current_stream()`` unless one is passed.  The library must have been built
+(``paper_2411_17229_amd.build.build()``); importing this module does not load it, the first
+call does, and it raises if ``libdade.so`` is missing -- there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdade.so")
+
+DADE_OK, DADE_EINVAL, DADE_ESTATE, DADE_ENOMEM, DADE_EDEVICE = 0, -1, -2, -3, -4
+DTYPES = {"f32": 0, "bf16": 1, "f16": 2}
+MODES = {"dade": 0, "full_d": 1}
+SCHEDULES = {"per_rank": 0, "doubling": 1}
+STATE_BUILT, STATE_ROTATED, STATE_CALIBRATED = 1, 2, 3
+EXPORTED = ("dade_build_index", "dade_rotate", "dade_calibrate", "dade_search", "dade_index_info",
+            "dade_export", "dade_import", "dade_stage_times", "dade_destroy", "dade_last_error")
+
+
+class DadeError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"[{code}] {msg}")
+        self.code = code
+
+
+class BuildOpts(ctypes.Structure):
+    _fields_ = [("kmeans_iters", ctypes.c_int32), ("store_dtype", ctypes.c_int32),
+                ("init_rows", ctypes.POINTER(ctypes.c_int64)), ("seed", ctypes.c_uint64),
+                ("hbm_budget_bytes", ctypes.c_int64)]
+
+
+class SearchOpts(ctypes.Structure):
+    _fields_ = [("delta_d", ctypes.c_int32), ("mode", ctypes.c_int32), ("schedule", ctypes.c_int32),
+                ("rerank_delta", ctypes.c_float), ("stats", ctypes.c_void_p),
+                ("record_times", ctypes.c_int32)]
+
+
+class Artifacts(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("dim", ctypes.c_int32), ("nlist", ctypes.c_int32),
+                ("store_dtype", ctypes.c_int32), ("state", ctypes.c_int32),
+                ("W", ctypes.c_void_p), ("mu", ctypes.c_void_p), ("lambda_", ctypes.c_void_p),
+                ("T", ctypes.c_void_p), ("delta", ctypes.c_double), ("centroids", ctypes.c_void_p),
+                ("list_offsets", ctypes.c_void_p), ("list_ids", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libdade.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2411_17229_amd.build.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64, u64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64
+        pp = ctypes.POINTER(ctypes.c_void_p)
+        L.dade_build_index.argtypes = [vp, i64, i32, i32, ctypes.POINTER(BuildOpts), vp, pp]
+        L.dade_rotate.argtypes = [vp, vp]
+        L.dade_calibrate.argtypes = [vp, ctypes.c_double, vp, i64, u64, vp]
+        L.dade_search.argtypes = [vp, vp, i64, i32, i32, vp, vp, ctypes.POINTER(SearchOpts), vp, vp, vp]
+        L.dade_index_info.argtypes = [vp] + [ctypes.POINTER(t) for t in (i64, i32, i32, i32, i32)]
+        L.dade_export.argtypes = [vp, ctypes.POINTER(Artifacts)]
+        L.dade_import.argtypes = [ctypes.POINTER(Artifacts), vp, ctypes.POINTER(BuildOpts), vp, pp]
+        L.dade_stage_times.argtypes = [vp, ctypes.POINTER(ctypes.c_float)]
+        L.dade_destroy.argtypes = [vp]
+        L.dade_destroy.restype = None
+        L.dade_last_error.restype = ctypes.c_char_p
+        for name in EXPORTED:
+            if name not in ("dade_destroy", "dade_last_error"):
+                getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != DADE_OK:
+        raise DadeError(rc, lib().dade_last_error().decode())
+
+
+def _stream(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev(t, dtype, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != dtype or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous {dtype} tensor on the GPU")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Index:
+    """Owns one dade_index handle."""
+
+    def __init__(self, handle):
+        self.handle = handle
+
+    def info(self):
+        return dade_index_info(self)
+
+    def close(self):
+        if self.handle:
+            lib().dade_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _build_opts(store="f32", kmeans_iters=10, init_rows=None, seed=0, hbm_budget_bytes=0):
+    o = BuildOpts()
+    o.kmeans_iters = kmeans_iters
+    o.store_dtype = DTYPES[store]
+    keep = None
+    if init_rows is not None:
+        keep = np.ascontiguousarray(init_rows, dtype=np.int64)
+        o.init_rows = keep.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+    o.seed = seed
+    o.hbm_budget_bytes = hbm_budget_bytes
+    return o, keep
+
+
+def dade_build_index(X, nlist, store="f32", kmeans_iters=10, init_rows=None, seed=0,
+                     hbm_budget_bytes=0, stream=None) -> Index:
+    import torch
+    p = _dev(X, torch.float32, "X")
+    o, keep = _build_opts(store, kmeans_iters, init_rows, seed, hbm_budget_bytes)
+    h = ctypes.c_void_p()
+    _check(lib().dade_build_index(p, X.shape[0], X.shape[1], nlist, ctypes.byref(o), _stream(stream),
+                                  ctypes.byref(h)))
+    return Index(h)
+
+
+def dade_rotate(ix: Index, stream=None):
+    _check(lib().dade_rotate(ix.handle, _stream(stream)))
+
+
+def dade_calibrate(ix: Index, alpha=0.1, pairs=None, n_pairs=100_000, seed=0, stream=None):
+    if pairs is not None:
+        pairs = np.ascontiguousarray(pairs, dtype=np.int64).reshape(-1, 2)
+        n_pairs = pairs.shape[0]
+        ptr = ctypes.c_void_p(pairs.ctypes.data)
+    else:
+        ptr = None
+    _check(lib().dade_calibrate(ix.handle, float(alpha), ptr, n_pairs, seed, _stream(stream)))
+
+
+def dade_search(ix: Index, Q, k, nprobe, k_per_query=None, nprobe_per_query=None, delta_d=0,
+                mode="dade", schedule="per_rank", rerank_delta=-1.0, stats=None, record_times=False,
+                out_ids=None, out_dist2=None, stream=None):
+    """Returns (ids [nq, k] int64, dist2 [nq, k] float32) device tensors (asynchronous)."""
+    import torch
+    qp = _dev(Q, torch.float32, "Q")
+    nq = Q.shape[0]
+    if out_ids is None:
+        out_ids = torch.empty((nq, k), dtype=torch.int64, device=Q.device)
+    if out_dist2 is None:
+        out_dist2 = torch.empty((nq, k), dtype=torch.float32, device=Q.device)
+    o = SearchOpts()
+    o.delta_d, o.mode, o.schedule = delta_d, MODES[mode], SCHEDULES[schedule]
+    o.rerank_delta = rerank_delta
+    o.stats = None if stats is None else _dev(stats, torch.int64, "stats").value
+    o.record_times = int(bool(record_times))
+    kp = None if k_per_query is None else _dev(k_per_query, torch.int32, "k_per_query")
+    npp = None if nprobe_per_query is None else _dev(nprobe_per_query, torch.int32, "nprobe_per_query")
+    _check(lib().dade_search(ix.handle, qp, nq, k, nprobe, kp, npp, ctypes.byref(o),
+                             _dev(out_ids, torch.int64, "out_ids"),
+                             _dev(out_dist2, torch.float32, "out_dist2"), _stream(stream)))
+    return out_ids, out_dist2
+
+
+def dade_index_info(ix: Index):
+    n, d, nl, st, state = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().dade_index_info(ix.handle, ctypes.byref(n), ctypes.byref(d), ctypes.byref(nl),
+                                 ctypes.byref(st), ctypes.byref(state)))
+    return {"n": n.value, "dim": d.value, "nlist": nl.value, "store": st.value, "state": state.value}
+
+
+def dade_export(ix: Index) -> dict:
+    """Host copies (numpy) of the artifacts available in the index's state."""
+    inf = dade_index_info(ix)
+    n, dim, nl, state = inf["n"], inf["dim"], inf["nlist"], inf["state"]
+    out = {"centroids": np.zeros((nl, dim)), "list_offsets": np.zeros(nl + 1, np.int64),
+           "list_ids": np.zeros(n, np.int64)}
+    if state >= STATE_ROTATED:
+        out.update(W=np.zeros((dim, dim)), mu=np.zeros(dim), lam=np.zeros(dim))
+    if state >= STATE_CALIBRATED:
+        out["T"] = np.zeros(dim)
+    a = Artifacts()
+    ptr = lambda key: ctypes.c_void_p(out[key].ctypes.data) if key in out else None  # noqa: E731
+    a.W, a.mu, a.lambda_, a.T = ptr("W"), ptr("mu"), ptr("lam"), ptr("T")
+    a.centroids, a.list_offsets, a.list_ids = ptr("centroids"), ptr("list_offsets"), ptr("list_ids")
+    _check(lib().dade_export(ix.handle, ctypes.byref(a)))
+    out["delta"] = a.delta
+    out.update(n=n, dim=dim, nlist=nl, state=state, store=inf["store"])
+    return out
+
+
+def dade_import(art: dict, X, store="f32", hbm_budget_bytes=0, stream=None) -> Index:
+    """An index from host artifacts (keys: W, mu, lam, centroids, list_offsets, list_ids,
+    optional T and delta) and the base vectors X (device)."""
+    import torch
+    keep = {k: np.ascontiguousarray(art[k], dtype=np.int64 if k.startswith("list") else np.float64)
+            for k in ("W", "mu", "lam", "centroids", "list_offsets", "list_ids", "T") if art.get(k) is not None}
+    a = Artifacts()
+    a.n, a.dim, a.nlist = X.shape[0], X.shape[1], len(keep["list_offsets"]) - 1
+    a.W, a.mu, a.lambda_ = (ctypes.c_void_p(keep[k].ctypes.data) for k in ("W", "mu", "lam"))
+    a.T = ctypes.c_void_p(keep["T"].ctypes.data) if "T" in keep else None
+    a.delta = float(art.get("delta", 0.0) or 0.0)
+    a.centroids = ctypes.c_void_p(keep["centroids"].ctypes.data)
+    a.list_offsets = ctypes.c_void_p(keep["list_offsets"].ctypes.data)
+    a.list_ids = ctypes.c_void_p(keep["list_ids"].ctypes.data)
+    o, _ = _build_opts(store, hbm_budget_bytes=hbm_budget_bytes)
+    h = ctypes.c_void_p()
+    _check(lib().dade_import(ctypes.byref(a), _dev(X, torch.float32, "X"), ctypes.byref(o), _stream(stream),
+                             ctypes.byref(h)))
+    return Index(h)
+
+
+def dade_stage_times(ix: Index):
+    ms = (ctypes.c_float * 3)()
+    _check(lib().dade_stage_times(ix.handle, ms))
+    return {"rotate_ms": ms[0], "probe_ms": ms[1], "scan_ms": ms[2]}
+
+
+def dade_destroy(ix: Index):
+    ix.close()
+
+
+def dade_last_error() -> str:
+    return lib().dade_last_error().decode()

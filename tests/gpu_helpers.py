@@ -1,0 +1,71 @@
+"""Shared helpers of the GPU parity tests (oracle on the CPU, HIP path through the C ABI)."""
+import numpy as np
+
+from oracle import ivf, lowp
+from paper_2411_17229_amd import dade, workloads
+
+# FP32 distances vs the FP64 oracle (spec tolerance).
+DIST_RTOL = 1e-5
+# A query is excused from ID-set equality when the oracle logged a decision (test, rerank
+# gate, keep compare, top-K boundary) or probe-order gap within this relative margin: the
+# HIP path computes S_d, r^2 and centroid distances in FP32 from FP32-rotated coordinates,
+# whose relative error (a few 1e-6 for D <= 1024) can flip such a decision.
+MARGIN_TOL = 1e-4
+
+
+def oracle_index(X, nlist, seed, n_pairs=100_000, alpha=0.1, store=None):
+    init = workloads.kmeans_init_rows(len(X), nlist, seed)
+    pairs = workloads.calibration_pairs(len(X), n_pairs, seed)
+    st = None if store in (None, "f32") else (lambda y: lowp.store(y, store))
+    return ivf.build(X, nlist, init, pairs, p_s=alpha, iters=10, store=st), init, pairs
+
+
+def artifacts(oi):
+    return dict(W=oi.W, mu=oi.mu, lam=oi.lam, centroids=oi.centroids, list_offsets=oi.offsets,
+                list_ids=oi.ids, T=oi.T, delta=oi.delta)
+
+
+def exact_d2(X, Q, ids):
+    out = np.full(ids.shape, np.inf)
+    for qi in range(ids.shape[0]):
+        v = ids[qi] >= 0
+        out[qi, v] = np.sum((X[ids[qi, v]].astype(np.float64) - Q[qi].astype(np.float64)) ** 2, axis=1)
+    return out
+
+
+def compare(o_ids, logs, g_ids, g_d2, X, Q, K, rtol=DIST_RTOL, margin_tol=MARGIN_TOL, max_excused=0.02):
+    """Element-wise parity of a GPU search against the oracle.  Returns the excused count."""
+    nq = o_ids.shape[0]
+    Ks = np.broadcast_to(np.asarray(K), (nq,))
+    ex = exact_d2(X, Q, g_ids)
+    excused = 0
+    for qi in range(nq):
+        k = int(Ks[qi])
+        gi, gd = g_ids[qi], g_d2[qi]
+        assert np.all(gi[k:] == -1) and np.all(np.isinf(gd[k:])), qi
+        v = gi[:k] >= 0
+        # every returned distance is the exact distance (I1)
+        np.testing.assert_allclose(gd[:k][v], ex[qi, :k][v], rtol=rtol, err_msg=f"query {qi}")
+        # rows ascend by (dist2, id)
+        keys = list(zip(gd[:k][v].tolist(), gi[:k][v].tolist()))
+        assert keys == sorted(keys), qi
+        if set(gi[:k].tolist()) == set(o_ids[qi, :k].tolist()):
+            continue
+        if logs is not None and (logs["min_margin"][qi] <= margin_tol or logs["probe_gap"][qi] <= margin_tol):
+            excused += 1
+            continue
+        raise AssertionError(f"query {qi}: ids differ without a near tie: gpu {gi[:k]} oracle {o_ids[qi, :k]} "
+                             f"margin {logs['min_margin'][qi] if logs else None}")
+    assert excused <= max(1, int(max_excused * nq)), excused
+    return excused
+
+
+def to_np(t):
+    return t.detach().cpu().numpy()
+
+
+def gpu_search(gi, Qd, K, nprobe, **kw):
+    import torch
+    ids, d2 = dade.dade_search(gi, Qd, K, nprobe, **kw)
+    torch.cuda.synchronize()
+    return to_np(ids), to_np(d2)
