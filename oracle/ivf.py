@@ -16,16 +16,19 @@ Readings where the paper is silent (each is a parameter or stated rule here):
 * Heap order: the total order on (squared distance, id).  r is the square root of the
   K-th smallest squared distance held, or +inf while fewer than K are held.  A candidate
   that survives every test is kept iff the heap is not full or (dist^2, id) < (r^2, id_r).
-* Round schedule (fixes the threshold each DCO sees): the probe ranks are split into
-  rounds; every candidate of a round is compared against the heap as it was when the
-  round started, and the round's accepted candidates are merged in at its end.
-  ``per_rank`` = one probed list per round; ``doubling`` = rank boundaries 0,1,2,4,8,...;
-  ``sequential`` = one candidate per round in list order, i.e. the heap is updated after
-  every DCO exactly as the paper describes.
+* Round schedule (fixes the threshold each DCO sees): the candidate sequence (probed lists
+  concatenated in probe order) is split into rounds; every candidate of a round is compared
+  against the heap as it was when the round started, and the round's accepted candidates
+  are merged in at its end.  The first round is the first K candidates (they fill the heap);
+  after it, ``per_rank`` ends a round at every list end and ``doubling`` at the ends of
+  probe ranks 1, 2, 4, 8, ...; ``sequential`` = one candidate per round in list order, i.e.
+  the heap is updated after every DCO exactly as the paper describes.
 
 Low-precision index (not in the paper): tests use the stored coordinates; a survivor whose
-stored-precision S_D exceeds (1 + delta) r^2 is dropped, the rest are reranked with the
-exact coordinates before the keep rule above.
+stored-precision S_D exceeds (1 + delta) r^2 is dropped; of the rest, the K smallest are
+reranked with the exact coordinates, and the others only if their stored-precision S_D is
+within (1 + delta) of the K-th exact distance known at that point (see ``_rerank``); the keep
+rule above then applies to the exact distances.
 """
 from __future__ import annotations
 
@@ -174,6 +177,20 @@ def round_bounds(nprobe: int, schedule: str):
     raise ValueError(schedule)
 
 
+def round_starts(sizes, K: int, schedule: str) -> list:
+    """Round boundaries in the candidate sequence (probed lists concatenated in probe order).
+
+    The first round holds the first K candidates (they fill the heap, as the paper's IVF fills
+    its max-heap before any comparison can fail); later rounds end where the schedule's probe
+    ranks end (``round_bounds``).  Returns sorted positions 0 = b_0 < b_1 < ... = total.
+    """
+    ends = np.cumsum(sizes)
+    total = int(ends[-1]) if len(ends) else 0
+    fill = min(K, total)
+    cut = [int(ends[hi - 1]) for _, hi in round_bounds(len(sizes), schedule)]
+    return sorted(set([0, fill, total] + [c for c in cut if c > fill]))
+
+
 def tested_dims(D: int, delta_d: int) -> np.ndarray:
     """d = Delta_d, 2 Delta_d, ... strictly below D (Algorithm 1 with the d <= D reading)."""
     return np.arange(delta_d, D, delta_d, dtype=np.int64)
@@ -187,6 +204,49 @@ def _merge(hd, hi, d2, ids, K):
     if len(o) > K and d[o[K - 1]] > 0:
         gap = abs(d[o[K]] - d[o[K - 1]]) / d[o[K - 1]]
     return d[o[:K]], i[o[:K]], gap
+
+
+def _rerank(index, q, cand, SD, alive, full, r2, hd, hi, K):
+    """Low-precision rerank of one round's survivors (the rule both sides implement).
+
+    A = survivors with stored-precision S_D <= (1 + delta) r^2 (every survivor while the heap
+    is not full).  F = the K smallest of A by (S_D, id); they are reranked with the exact
+    coordinates.  b = the K-th smallest exact distance of the heap and F (+inf if fewer than
+    K); the rest of A is reranked only where S_D <= (1 + delta) b.  Returns the reranked mask,
+    the distances to keep-test (exact where reranked) and the smallest relative margin of the
+    gates.
+    """
+    delta = index.delta
+    margin = math.inf
+    A = alive.copy()
+    if full:
+        gate = (1.0 + delta) * r2
+        if alive.any():
+            margin = min(margin, float(np.min(np.abs(SD[alive] - gate) / gate)))
+        A &= SD <= gate
+    ia = np.nonzero(A)[0]
+    o = ia[np.lexsort((cand[ia], SD[ia]))]
+    F, rest = o[:K], o[K:]
+    if len(rest) and SD[F[-1]] > 0:
+        margin = min(margin, abs(SD[rest[0]] - SD[F[-1]]) / SD[F[-1]])
+    exact = SD.copy()
+    dF = index.Y_exact[cand[F]] - q
+    exact[F] = np.sum(dF * dF, axis=1)
+    pool_d = np.concatenate([hd, exact[F]])
+    pool_i = np.concatenate([hi, cand[F]])
+    b = math.inf
+    if len(pool_d) >= K:
+        b = float(pool_d[np.lexsort((pool_i, pool_d))[K - 1]])
+    bound = (1.0 + delta) * b
+    if len(rest) and math.isfinite(bound) and bound > 0:
+        margin = min(margin, float(np.min(np.abs(SD[rest] - bound) / bound)))
+    rest = rest[SD[rest] <= bound]
+    dR = index.Y_exact[cand[rest]] - q
+    exact[rest] = np.sum(dR * dR, axis=1)
+    R = np.zeros_like(alive)
+    R[F] = True
+    R[rest] = True
+    return R, exact, margin
 
 
 def _scan_round(index, q, cand, hd, hi, K, delta_d, mode, tests):
@@ -219,15 +279,8 @@ def _scan_round(index, q, cand, hd, hi, K, delta_d, mode, tests):
             margin = min(margin, float(rel.min()))
     SD = S[:, -1]
     if index.Y_exact is not None:
-        if full:
-            gate = (1.0 + index.delta) * r2
-            if alive.any():
-                margin = min(margin, float(np.min(np.abs(SD[alive] - gate) / gate)))
-            alive = alive & (SD <= gate)
-        de = index.Y_exact[cand[alive]] - q
-        SDx = SD.copy()
-        SDx[alive] = np.sum(de * de, axis=1)
-        SD = SDx
+        alive, SD, m2 = _rerank(index, q, cand, SD, alive, full, r2, hd, hi, K)
+        margin = min(margin, m2)
     if full:
         keep = alive & ((SD < r2) | ((SD == r2) & (cand < idr)))
         if alive.any() and r2 > 0:
@@ -270,11 +323,12 @@ def search(index: Index, Q, K, nprobe, delta_d: int, mode: str = "dade",
             rg = np.where(den > 0, gaps / den, math.inf)
         logs["probe_gap"][qi] = float(rg.min()) if rg.size else math.inf
         lists = [index.ids[index.offsets[l]:index.offsets[l + 1]] for l in probes]
+        seq = np.concatenate(lists) if lists else np.zeros(0, np.int64)
         if schedule == "sequential":
-            rounds = [np.array([c], dtype=np.int64) for lst in lists for c in lst]
+            rounds = [seq[i:i + 1] for i in range(len(seq))]
         else:
-            rounds = [np.concatenate(lists[lo:hi]) if hi > lo else np.zeros(0, np.int64)
-                      for lo, hi in round_bounds(npq, schedule)]
+            b = round_starts(np.array([len(x) for x in lists]), Kq, schedule)
+            rounds = [seq[b0:b1] for b0, b1 in zip(b[:-1], b[1:])]
         hd = np.zeros(0)
         hi = np.zeros(0, dtype=np.int64)
         mm = math.inf

@@ -7,9 +7,9 @@ import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-CSRC = os.path.join(HERE, "csrc")
-BUILD = os.path.join(ROOT, "_build")
-LIB = os.path.join(HERE, "libdade.so")
+CSRC = os.environ.get("DADE_CSRC", os.path.join(HERE, "csrc"))
+BUILD = os.environ.get("DADE_BUILD", os.path.join(ROOT, "_build"))
+LIB = os.environ.get("DADE_LIB", os.path.join(HERE, "libdade.so"))
 SOURCES = ["dade_api.hip", "gemm.hip", "misc.hip", "fp64.hip", "select.hip", "scan.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

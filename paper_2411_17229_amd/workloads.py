@@ -73,13 +73,17 @@ def haar_rotation(rng: np.random.Generator, dim: int) -> np.ndarray:
 
 
 def _mixture(rng_lab, rng_noise, centres, rot, sqrt_lam, count, chunk=1 << 16):
+    """Rows drawn in float32 (noise, scaling and rotation), chunk by chunk."""
     dim = centres.shape[1]
     out = np.empty((count, dim), dtype=np.float32)
     labels = rng_lab.integers(0, centres.shape[0], count)
+    rot_t = np.ascontiguousarray(rot.T, dtype=np.float32)
+    sl = sqrt_lam.astype(np.float32)
+    cen = centres.astype(np.float32)
     for s in range(0, count, chunk):
         e = min(count, s + chunk)
-        z = rng_noise.standard_normal((e - s, dim))
-        out[s:e] = (centres[labels[s:e]] + (z * sqrt_lam) @ rot.T).astype(np.float32)
+        z = rng_noise.standard_normal((e - s, dim), dtype=np.float32)
+        out[s:e] = cen[labels[s:e]] + (z * sl) @ rot_t
     return out, labels
 
 

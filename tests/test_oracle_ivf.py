@@ -138,6 +138,17 @@ def test_uneven_k_and_nprobe(setup):
         assert np.all(np.isinf(d2[qi, K[qi]:]))
 
 
+def test_round_starts_fill_then_schedule():
+    # lists of sizes 5, 7, 3, 4; K = 3: fill [0,3), rest of list 0, then each list
+    assert ivf.round_starts(np.array([5, 7, 3, 4]), 3, "per_rank") == [0, 3, 5, 12, 15, 19]
+    # K = 6 crosses into list 1: fill [0,6), then the rest of list 1
+    assert ivf.round_starts(np.array([5, 7, 3, 4]), 6, "per_rank") == [0, 6, 12, 15, 19]
+    # doubling: ranks end after lists 1, 2, 4 -> positions 5, 12, 19
+    assert ivf.round_starts(np.array([5, 7, 3, 4]), 3, "doubling") == [0, 3, 5, 12, 19]
+    # K larger than everything: one round
+    assert ivf.round_starts(np.array([2, 2]), 10, "per_rank") == [0, 4]
+
+
 def test_round_bounds():
     assert ivf.round_bounds(8, "doubling") == [(0, 1), (1, 2), (2, 4), (4, 8)]
     assert ivf.round_bounds(6, "doubling") == [(0, 1), (1, 2), (2, 4), (4, 6)]
@@ -188,8 +199,8 @@ def test_vectorised_round_on_hand_worked_cases():
 
 
 def test_keep_rule_breaks_distance_ties_by_id():
-    """Two identical rows: under the live heap (sequential) the later id ties with r and is
-    not kept; under one round from an empty heap both are kept and the merge keeps id 0."""
+    """Two identical rows: once the heap holds id 0 (sequential, or the K = 1 fill round of
+    per-rank), the later id ties with r and is not kept; the result is id 0 either way."""
     X = np.array([[1.0, 0.0], [1.0, 0.0], [3.0, 0.0]])
     index = ivf.Index(np.zeros(2), np.eye(2), np.array([1.0, 1.0]), np.zeros(2),
                       np.zeros((1, 2)), np.array([0, 3]), np.array([0, 1, 2]), X)
@@ -197,4 +208,91 @@ def test_keep_rule_breaks_distance_ties_by_id():
     ids, d2, logs = ivf.search(index, q, 1, 1, 1, mode="exact", schedule="sequential", log=True)
     assert ids[0, 0] == 0 and logs["accepted"][0] == 1
     ids, d2, logs = ivf.search(index, q, 1, 1, 1, mode="exact", schedule="per_rank", log=True)
-    assert ids[0, 0] == 0 and logs["accepted"][0] == 3
+    assert ids[0, 0] == 0 and logs["accepted"][0] == 1
+
+
+@pytest.mark.parametrize("delta", [0.0, 0.01, 1e9])
+def test_rerank_rule_with_exact_store_changes_nothing(setup, delta):
+    """With stored coordinates equal to the exact ones, the rerank rule (K smallest reranked,
+    the rest only within (1 + delta) of the K-th exact distance) keeps exactly the results of
+    the plain index for any delta >= 0: a candidate it skips is farther than the final K-th."""
+    import dataclasses
+    X, Q, _, index = setup
+    lp = dataclasses.replace(index, Y_exact=index.Y, delta=delta)
+    for schedule in ("per_rank", "doubling"):
+        a_i, a_d = ivf.search(index, Q, 10, 6, 8, schedule=schedule)
+        b_i, b_d = ivf.search(lp, Q, 10, 6, 8, schedule=schedule)
+        assert np.array_equal(a_i, b_i)
+        np.testing.assert_allclose(a_d, b_d, rtol=1e-12)
+
+
+def test_rerank_rule_reranks_few_when_heap_empty(setup):
+    """Round 0 (empty heap) queues every survivor but reranks only the K smallest and those
+    within the bound -- far fewer than the list."""
+    X, Q, init, _ = setup
+    pairs = workloads.calibration_pairs(N, 20000, seed=21)
+    idx = ivf.build(X, NLIST, init, pairs, store=lambda y: lowp.store(y, "bf16"))
+    calls = []
+    orig = idx.Y_exact
+    class Counting:
+        def __getitem__(self, rows):
+            calls.append(len(np.atleast_1d(rows)))
+            return orig[rows]
+    idx.Y_exact = Counting()
+    ivf.search(idx, Q[:1], 10, 1, 8)
+    list_len = max(np.diff(idx.offsets))
+    assert 10 <= sum(calls) < list_len
+
+
+def _two_list_index(stored, exact, n0, delta=0.1):
+    """W = I index in 2-D: list 0 = ids [0, n0) (centroid near q = 0), list 1 = the rest."""
+    Ys, Ye = np.asarray(stored, float), np.asarray(exact, float)
+    return ivf.Index(np.zeros(2), np.eye(2), np.array([1.0, 1.0]), np.zeros(2),
+                     np.array([[0.1, 0.0], [5.0, 5.0]]), np.array([0, n0, len(Ys)]), np.arange(len(Ys)),
+                     Ys, Y_exact=Ye, delta=delta)
+
+
+def _search2(index, nprobe):
+    ids, d2 = ivf.search(index, np.zeros((1, 2)), 2, nprobe, 1, mode="exact")
+    return list(ids[0]), d2[0]
+
+
+def test_rerank_rule_hand_worked_f_is_k_smallest():
+    """K = 2, delta = 0.1, full-D DCOs, per-rank.  (stored S_D / exact S_D)
+    list 0: id0 1.0/1.0, id1 1.44/1.44, id2 4.0/4.0; list 1: id3 1.45/1.09, id4 1.4641/1.04,
+    id5 1.565/1.565.  Fill round {0, 1}: heap (1.0, 0), (1.44, 1).  Rest of list 0: id2 fails
+    the gate 1.584.  List 1: all pass the gate; F = {3, 4} (two smallest stored) -> exact
+    1.09, 1.04; b = 2nd of {1.0, 1.44, 1.09, 1.04} = 1.04, bound 1.144: id5 not reranked.
+    Both of F kept -> heap (1.0, 0), (1.04, 4)."""
+    index = _two_list_index([[1, 0], [0, 1.2], [2, 0], [1.2, 0.1], [0, 1.21], [1.25, 0.05]],
+                            [[1, 0], [0, 1.2], [2, 0], [1.0, 0.3], [1.0, 0.2], [1.25, 0.05]], 3)
+    ids, d2 = _search2(index, 1)
+    assert ids == [0, 1]
+    ids, d2 = _search2(index, 2)
+    assert ids == [0, 4]
+    np.testing.assert_allclose(d2, [1.0, 1.04], rtol=1e-12)
+
+
+def test_rerank_rule_hand_worked_rest_within_bound():
+    """As above but list 1: id3 1.45/1.5025, id4 1.4641/1.5625, id5 1.4741/1.21.
+    F = {3, 4} -> exact 1.5025, 1.5625; b = 2nd of {1.0, 1.44, 1.5025, 1.5625} = 1.44,
+    bound 1.584 >= 1.4741: id5 reranked (1.21) and kept; F's exact values exceed r^2 = 1.44.
+    Heap -> (1.0, 0), (1.21, 5)."""
+    index = _two_list_index([[1, 0], [0, 1.2], [2, 0], [1.2, 0.1], [0, 1.21], [1.21, 0.1]],
+                            [[1, 0], [0, 1.2], [2, 0], [1.2, 0.25], [0, 1.25], [1.1, 0]], 3)
+    ids, d2 = _search2(index, 2)
+    assert ids == [0, 5]
+    np.testing.assert_allclose(d2, [1.0, 1.21], rtol=1e-12)
+
+
+def test_rerank_rule_hand_worked_bound_uses_heap():
+    """Heap after list 0: (1.0, 0), (1.21, 1).  List 1: id2 stored (0, 1.03) 1.0609 / exact
+    (1.01, 0) 1.0201; id3 (0, 1.04) 1.0816 / (1.02, 0) 1.0404; id4 (0, 1.065) 1.134225 /
+    (1.005, 0) 1.010025.  Gate 1.331 passes all; F = {2, 3}; b = 2nd of {1.0, 1.21, 1.0201,
+    1.0404} = 1.0201, bound 1.12211 < 1.134225: id4 is NOT reranked (b computed from F alone
+    would be 1.0404 and let it in).  Heap -> (1.0, 0), (1.0201, 2)."""
+    index = _two_list_index([[1, 0], [1.1, 0], [0, 1.03], [0, 1.04], [0, 1.065]],
+                            [[1, 0], [1.1, 0], [1.01, 0], [1.02, 0], [1.005, 0]], 2)
+    ids, d2 = _search2(index, 2)
+    assert ids == [0, 2]
+    np.testing.assert_allclose(d2, [1.0, 1.0201], rtol=1e-12)
