@@ -17,6 +17,14 @@ constexpr int kMaxNlist = 8192;     // probe selection sorts nlist keys in LDS (
 
 inline int pad_dim(int dim) { return (dim + kDimAlign - 1) / kDimAlign * kDimAlign; }
 
+// Packed store of the rotated coordinates: a head block holding coordinates [0, kHead) of every
+// row ([n x kHead]), then a tail block holding the rest ([n x (dp - kHead)]).  The first
+// hypothesis test of a scan reads only the head, so a list's first-test reads are contiguous.
+constexpr int kHead = 32;
+__host__ __device__ inline int64_t stored_index(int64_t p, int c, int64_t n, int dp) {
+  return c < kHead ? p * kHead + c : n * kHead + p * (dp - kHead) + (c - kHead);
+}
+
 // Error state for the C ABI (thread-local message).
 void set_error(const std::string& msg);
 std::string hip_msg(hipError_t e, const char* what);

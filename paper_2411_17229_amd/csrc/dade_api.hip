@@ -67,16 +67,24 @@ struct dade_index {
   float* d_mu = nullptr;       // [dp]
   float* d_cent_rot = nullptr; // [nlist x dp]
   float* d_cent_norm = nullptr;// [nlist]
-  void* d_store = nullptr;     // [n x dp] rotated coordinates, list order
+  void* d_store = nullptr;     // rotated coordinates in list order, head/tail layout (stored_index)
   float* d_T = nullptr;        // [dim]
   // host artifacts
   std::vector<double> W, mu, lam, T, cent_h;
   double delta = 0.0;
   std::vector<int64_t> off_h, ids_h;
-  // search workspace
+  // search workspace (grown on demand, each with its element count)
   float* w_qpad = nullptr; float* w_qrot = nullptr; float* w_pd = nullptr;
-  int32_t* w_probes = nullptr; unsigned long long* w_acc = nullptr; int* w_counter = nullptr;
-  int64_t w_nq = 0, w_np = 0, w_acc_n = 0;
+  int32_t* w_probes = nullptr;
+  int64_t w_nq = 0, w_np = 0;
+  unsigned long long* w_topk = nullptr; int64_t w_topk_n = 0;
+  unsigned long long* w_keyr = nullptr; int64_t w_keyr_n = 0;
+  float* w_r2 = nullptr; int64_t w_r2_n = 0;
+  int* w_qint = nullptr; int64_t w_qint_n = 0;      // q_topn, q_kc, q_cur (6 per query)
+  unsigned long long* w_kb = nullptr; int64_t w_kb_n = 0;
+  int4* w_items = nullptr; int64_t w_items_n = 0;   // two buffers
+  int* w_counter = nullptr; int64_t w_counter_n = 0;  // n_items[2], overflow
+  int scan_occ[3][2][2] = {};                        // resident scan workgroups per CU
   hipEvent_t ev[4] = {};
   bool ev_made = false, ev_used = false;
   int cus = 256;
@@ -119,6 +127,20 @@ void dev_free(dade_index* ix, void* p, size_t bytes) {
   if (it != ix->owned.end()) ix->owned.erase(it);
   (void)hipFree(p);
   ix->held -= int64_t(bytes == 0 ? 16 : bytes);
+}
+
+// Make *p hold at least `need` elements (contents are not kept).
+template <typename T>
+int grow(dade_index* ix, T** p, int64_t& have, int64_t need, hipStream_t s) {
+  if (need <= have && *p) return DADE_OK;
+  HIPC(hipStreamSynchronize(s));
+  dev_free(ix, *p, sizeof(T) * size_t(have));
+  *p = nullptr;
+  have = 0;
+  const int rc = alloc_t(ix, p, size_t(need));
+  if (rc) return rc;
+  have = need;
+  return DADE_OK;
 }
 
 int check_device_pointer(const void* p, const char* name) {
@@ -225,7 +247,7 @@ int apply_transform(dade_index* ix, hipStream_t s) {
   GemmArgs g;
   g.M = int(ix->n); g.N = dp; g.K = dp;
   g.A = ix->X; g.lda = dp; g.a_rows = ix->d_ids; g.a_shift = ix->d_mu;
-  g.B = ix->d_W; g.ldb = dp; g.C = ix->d_store; g.ldc = dp;
+  g.B = ix->d_W; g.ldb = dp; g.C = ix->d_store; g.ldc = dp; g.split_rows = ix->n;
   const GemmEpilogue epi = ix->store == DADE_F32 ? kEpiPackF32 : (ix->store == DADE_BF16 ? kEpiPackBF16 : kEpiPackF16);
   HIPC(launch_gemm(g, epi, s));
   HIPC(hipStreamSynchronize(s));
@@ -511,7 +533,7 @@ int dade_calibrate(dade_index* ix, double alpha, const int64_t* pairs, int64_t n
     rows = Y;
   } else {
     if ((rc = alloc_t(ix, &Y, size_t(n_pairs) * dp))) { cleanup(); return rc; }
-    CAL_HIP(launch_pair_diff_stored(ix->d_store, ix->store, dp, ix->d_pos, dP, m, Y, s));
+    CAL_HIP(launch_pair_diff_stored(ix->d_store, ix->store, ix->n, dp, ix->d_pos, dP, m, Y, s));
     rows = Y;
   }
   CAL_HIP(launch_prefix_fraction(rows, dp, m, dim, dis2, f, rel, s));
@@ -631,19 +653,23 @@ int dade_search(dade_index* ix, const float* Q, int64_t nq, int32_t k, int32_t n
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int dp = ix->dp, nl = ix->nlist;
   const int npm = std::min<int>(nprobe, nl);
-  // accept-buffer capacity: the most candidates one round can hold
+  // the most candidates one round can hold (per-rank: one list; doubling: its widest round)
   std::vector<int64_t> sizes(nl);
   for (int l = 0; l < nl; ++l) sizes[l] = ix->off_h[l + 1] - ix->off_h[l];
   std::sort(sizes.begin(), sizes.end(), std::greater<int64_t>());
-  int widest = 1;
+  int widest = 1, rounds = npm + 1;
   if (o.schedule == DADE_SCHED_DOUBLING) {
-    int b = 1;
-    while (b < npm) { widest = std::max(widest, std::min(2 * b, npm) - b); b *= 2; }
+    int b = 1, nb = 0;
+    while (b < npm) { widest = std::max(widest, std::min(2 * b, npm) - b); b *= 2; ++nb; }
+    rounds = nb + 3;
   }
-  int64_t cap = 0;
-  for (int i = 0; i < widest && i < nl; ++i) cap += sizes[i];
-  cap = std::max<int64_t>(cap, 1);
-  const int grid = int(std::min<int64_t>(nq, int64_t(ix->cus) * 8));
+  int64_t kb_cap = 0;
+  for (int i = 0; i < widest && i < nl; ++i) kb_cap += sizes[i];
+  kb_cap = std::max<int64_t>(kb_cap, k);
+  const int64_t items_pq = std::max<int64_t>((kb_cap + 63) / 64 + widest + 1, (k + 63) / 64 + npm);
+  // queries per pass: the round workspace stays under 1 GiB
+  const int64_t per_q = kb_cap * 8 + 2 * items_pq * 16 + int64_t(k) * 8 + 48;
+  const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(nq, (int64_t(1) << 30) / per_q));
   // workspace
   if (nq > ix->w_nq || npm > ix->w_np) {
     const int64_t new_nq = std::max(nq, ix->w_nq), new_np = std::max<int64_t>(npm, ix->w_np);
@@ -660,15 +686,14 @@ int dade_search(dade_index* ix, const float* Q, int64_t nq, int32_t k, int32_t n
       return rc;
     ix->w_nq = new_nq; ix->w_np = new_np;
   }
-  if (int64_t(grid) * cap > ix->w_acc_n) {
-    HIPC(hipStreamSynchronize(s));
-    dev_free(ix, ix->w_acc, sizeof(unsigned long long) * ix->w_acc_n);
-    ix->w_acc = nullptr;
-    ix->w_acc_n = 0;
-    if ((rc = alloc_t(ix, &ix->w_acc, size_t(grid) * cap))) return rc;
-    ix->w_acc_n = int64_t(grid) * cap;
-  }
-  if (!ix->w_counter && (rc = alloc_t(ix, &ix->w_counter, 2))) return rc;
+  if ((rc = grow(ix, &ix->w_topk, ix->w_topk_n, chunk * k, s)) || (rc = grow(ix, &ix->w_keyr, ix->w_keyr_n, chunk, s)) ||
+      (rc = grow(ix, &ix->w_r2, ix->w_r2_n, chunk, s)) || (rc = grow(ix, &ix->w_qint, ix->w_qint_n, chunk * 6, s)) ||
+      (rc = grow(ix, &ix->w_kb, ix->w_kb_n, chunk * kb_cap, s)) ||
+      (rc = grow(ix, &ix->w_items, ix->w_items_n, 2 * chunk * items_pq, s)) ||
+      (rc = grow(ix, &ix->w_counter, ix->w_counter_n, 3, s)))
+    return rc;
+  int& occ = ix->scan_occ[ix->store][o.mode][dd % 8 != 0];
+  if (occ == 0) occ = round_blocks_per_cu(ix->store, o.mode, dd);
   if (o.record_times && !ix->ev_made) {
     for (auto& e : ix->ev) HIPC(hipEventCreate(&e));
     ix->ev_made = true;
@@ -690,18 +715,40 @@ int dade_search(dade_index* ix, const float* Q, int64_t nq, int32_t k, int32_t n
   HIPC(launch_gemm(p, kEpiProbe, s));
   HIPC(launch_select_probes(ix->w_pd, nl, ix->w_qrot, dp, int(nq), dp, nl, npm, ix->w_probes, s));
   if (o.record_times) HIPC(hipEventRecord(ix->ev[2], s));
-  // a3-a6: the list scan
-  HIPC(launch_fill_i32(ix->w_counter, 2, 0, s));
-  ScanArgs sa;
-  sa.nq = int(nq); sa.dim = ix->dim; sa.dp = dp; sa.delta_d = dd; sa.schedule = o.schedule;
-  sa.k_max = k; sa.nprobe_max = npm; sa.k_pq = k_per_query; sa.nprobe_pq = nprobe_per_query;
-  sa.qrot = ix->w_qrot; sa.qorig = ix->w_qpad; sa.probes = ix->w_probes; sa.list_off = ix->d_off;
-  sa.store = ix->d_store; sa.ids = ix->d_ids; sa.X = ix->X; sa.T = ix->d_T;
-  sa.rerank_delta = o.rerank_delta >= 0.f ? o.rerank_delta : float(ix->delta);
-  sa.out_ids = out_ids; sa.out_d2 = out_dist2; sa.stats = o.stats;
-  sa.acc_buf = ix->w_acc; sa.acc_cap = cap; sa.counter = ix->w_counter; sa.overflow = ix->w_counter + 1;
-  sa.grid = grid;
-  HIPC(launch_scan(sa, ix->store, o.mode, s));
+  // a3-a6: the list scan, in rounds, `chunk` queries at a time
+  RoundArgs ra;
+  ra.dim = ix->dim; ra.dp = dp; ra.delta_d = dd; ra.schedule = o.schedule;
+  ra.mode = o.mode == DADE_MODE_DADE ? 0 : 1; ra.dtype = ix->store;
+  ra.k_max = k; ra.nprobe_max = npm;
+  ra.list_off = ix->d_off;
+  ra.head = ix->d_store;
+  ra.tail = static_cast<const char*>(ix->d_store) + size_t(ix->n) * kHead * dtype_size(ix->store);
+  ra.ids = ix->d_ids; ra.X = ix->X; ra.T = ix->d_T;
+  ra.rerank_delta = o.rerank_delta >= 0.f ? o.rerank_delta : float(ix->delta);
+  ra.kb_cap = kb_cap;
+  ra.items_cap = int(std::min<int64_t>(chunk * items_pq, INT32_MAX));
+  ra.n_items = ix->w_counter; ra.overflow = ix->w_counter + 2;
+  ra.grid = ix->cus * occ;
+  for (int64_t c0 = 0; c0 < nq; c0 += chunk) {
+    const int64_t cn = std::min(chunk, nq - c0);
+    ra.nq = int(cn);
+    ra.k_pq = k_per_query ? k_per_query + c0 : nullptr;
+    ra.nprobe_pq = nprobe_per_query ? nprobe_per_query + c0 : nullptr;
+    ra.qrot = ix->w_qrot + c0 * dp; ra.qorig = ix->w_qpad + c0 * dp;
+    ra.probes = ix->w_probes + c0 * npm;
+    ra.out_ids = out_ids + c0 * k; ra.out_d2 = out_dist2 + c0 * k;
+    ra.stats = o.stats ? o.stats + c0 * 4 : nullptr;
+    ra.q_topk = ix->w_topk; ra.q_keyr = ix->w_keyr; ra.q_r2 = ix->w_r2;
+    ra.q_topn = ix->w_qint; ra.q_kc = ix->w_qint + cn; ra.q_cur = ix->w_qint + 2 * cn;
+    ra.kb = ix->w_kb;
+    ra.items[0] = ix->w_items; ra.items[1] = ix->w_items + chunk * items_pq;
+    HIPC(launch_fill_i32(ix->w_counter, 3, 0, s));
+    HIPC(launch_merge(ra, 0, 1, s));
+    for (int r = 0; r < rounds; ++r) {
+      HIPC(launch_round(ra, r & 1, s));
+      HIPC(launch_merge(ra, (r + 1) & 1, 0, s));
+    }
+  }
   if (o.record_times) {
     HIPC(hipEventRecord(ix->ev[3], s));
     ix->ev_used = true;

@@ -153,7 +153,7 @@ __device__ inline double load_stored<__half>(const void* p, int64_t e) {
 }
 
 template <typename T>
-__global__ void pair_diff_stored_kernel(const void* __restrict__ store, int ld,
+__global__ void pair_diff_stored_kernel(const void* __restrict__ store, int64_t rows, int ld,
                                         const int64_t* __restrict__ pos,
                                         const int64_t* __restrict__ pairs, int64_t m,
                                         double* __restrict__ delta) {
@@ -162,7 +162,8 @@ __global__ void pair_diff_stored_kernel(const void* __restrict__ store, int ld,
   if (i >= m) return;
   const int64_t pa = pos[pairs[2 * i]], pb = pos[pairs[2 * i + 1]];
   for (int k = lane; k < ld; k += 64)
-    delta[i * ld + k] = load_stored<T>(store, pa * ld + k) - load_stored<T>(store, pb * ld + k);
+    delta[i * ld + k] = load_stored<T>(store, stored_index(pa, k, rows, ld)) -
+                        load_stored<T>(store, stored_index(pb, k, rows, ld));
 }
 
 // One thread per pair: running prefix of squared rotated coordinates.
@@ -229,18 +230,19 @@ hipError_t launch_pair_diff(const float* X, int ld, const int64_t* pairs, int64_
   return hipGetLastError();
 }
 
-hipError_t launch_pair_diff_stored(const void* store, int dtype, int ld, const int64_t* pos,
-                                   const int64_t* pairs, int64_t m, double* delta,
-                                   hipStream_t s) {
+hipError_t launch_pair_diff_stored(const void* store, int dtype, int64_t rows, int ld,
+                                   const int64_t* pos, const int64_t* pairs, int64_t m,
+                                   double* delta, hipStream_t s) {
   if (m == 0) return hipSuccess;
   const dim3 g(int((m + 3) / 4)), b(kBlock);
   if (dtype == 0)
-    hipLaunchKernelGGL(pair_diff_stored_kernel<float>, g, b, 0, s, store, ld, pos, pairs, m, delta);
+    hipLaunchKernelGGL(pair_diff_stored_kernel<float>, g, b, 0, s, store, rows, ld, pos, pairs, m,
+                       delta);
   else if (dtype == 1)
-    hipLaunchKernelGGL(pair_diff_stored_kernel<__hip_bfloat16>, g, b, 0, s, store, ld, pos, pairs,
-                       m, delta);
+    hipLaunchKernelGGL(pair_diff_stored_kernel<__hip_bfloat16>, g, b, 0, s, store, rows, ld, pos,
+                       pairs, m, delta);
   else
-    hipLaunchKernelGGL(pair_diff_stored_kernel<__half>, g, b, 0, s, store, ld, pos, pairs, m,
+    hipLaunchKernelGGL(pair_diff_stored_kernel<__half>, g, b, 0, s, store, rows, ld, pos, pairs, m,
                        delta);
   return hipGetLastError();
 }

@@ -148,7 +148,9 @@ __global__ __launch_bounds__(kThreads) void gemm_kernel(GemmArgs g) {
           const int row = m0 + wm + 32 * i + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
           if (row >= g.M) continue;
           const float x = acc[i][j][v];
-          const int64_t o = int64_t(row) * g.ldc + col;
+          const int64_t o = (EPI >= kEpiPackF32 && g.split_rows > 0)
+                                ? stored_index(row, col, g.split_rows, g.ldc)
+                                : int64_t(row) * g.ldc + col;
           if (EPI == kEpiStore || EPI == kEpiPackF32) {
             static_cast<float*>(g.C)[o] = x;
           } else if (EPI == kEpiProbe) {

@@ -31,6 +31,7 @@ struct GemmArgs {
   int ldc = 0;
   const float* col_norm = nullptr;
   unsigned long long* row_best = nullptr;
+  int64_t split_rows = 0;   // pack epilogues: > 0 writes the head/tail store of that many rows
 };
 hipError_t launch_gemm(const GemmArgs& a, GemmEpilogue epi, hipStream_t s);
 
@@ -65,10 +66,10 @@ hipError_t launch_dgemm(const double* A, int lda, const double* B, int ldb, doub
 // Delta[i] = X[a_i] - X[b_i] in FP64 (ld columns), dis2[i] = ||Delta[i]||^2.
 hipError_t launch_pair_diff(const float* X, int ld, const int64_t* pairs, int64_t m,
                             double* delta, double* dis2, hipStream_t s);
-// Same from stored coordinates: S from store rows pos[a], pos[b]; dis2 from X.
-hipError_t launch_pair_diff_stored(const void* store, int dtype, int ld, const int64_t* pos,
-                                   const int64_t* pairs, int64_t m, double* delta,
-                                   hipStream_t s);
+// Same from stored coordinates (head/tail store of `rows` rows): rows pos[a], pos[b].
+hipError_t launch_pair_diff_stored(const void* store, int dtype, int64_t rows, int ld,
+                                   const int64_t* pos, const int64_t* pairs, int64_t m,
+                                   double* delta, hipStream_t s);
 // f[d][i] = (sum_{k<=d} Y[i][k]^2) / dis2[i] for d < dim; rel[i] = |S_dim - dis2| / dis2.
 hipError_t launch_prefix_fraction(const double* Y, int ld, int64_t m, int dim,
                                   const double* dis2, double* f, double* rel, hipStream_t s);
@@ -80,35 +81,54 @@ hipError_t launch_select_probes(const float* pd, int ld_pd, const float* qrot, i
                                 hipStream_t s);
 
 // ---------------------------------------------------------------- the list scan (scan.hip)
-struct ScanArgs {
+// ---------------------------------------------------------------- the list scan (scan.hip)
+// One search runs as rounds (see scan.hip): launch_merge(init) queues every query's first
+// round; then per round launch_round (the DCOs) and launch_merge (heap update, next round).
+struct RoundArgs {
   int nq = 0;
   int dim = 0;          // real dimensionality D
   int dp = 0;           // padded row length of stored coordinates
   int delta_d = 32;
   int schedule = 0;     // 0 per-rank, 1 doubling
+  int mode = 0;         // 0 DADE, 1 FULL_D
+  int dtype = 0;        // stored coordinates: 0 f32, 1 bf16, 2 f16
   int k_max = 0;
   int nprobe_max = 0;
   const int32_t* k_pq = nullptr;
   const int32_t* nprobe_pq = nullptr;
-  const float* qrot = nullptr;    // [nq x dp] rotated queries
-  const float* qorig = nullptr;   // [nq x dp] original queries (rerank)
+  const float* qrot = nullptr;      // [nq x dp] rotated queries
+  const float* qorig = nullptr;     // [nq x dp] original queries (rerank)
   const int32_t* probes = nullptr;  // [nq x nprobe_max]
   const int64_t* list_off = nullptr;
-  const void* store = nullptr;    // packed rotated coordinates [n x dp]
-  const int32_t* ids = nullptr;   // packed position -> row id
-  const float* X = nullptr;       // [n x dp] original vectors by row id (rerank)
-  const float* T = nullptr;       // [dim] T_d
+  const void* head = nullptr;       // stored coordinates [0, kHead) of each packed row
+  const void* tail = nullptr;       // the rest, [n x (dp - kHead)]
+  const int32_t* ids = nullptr;     // packed position -> row id
+  const float* X = nullptr;         // [n x dp] original vectors by row id (rerank)
+  const float* T = nullptr;         // [dim] T_d
   float rerank_delta = 0.f;
   int64_t* out_ids = nullptr;
   float* out_d2 = nullptr;
   int64_t* stats = nullptr;
-  unsigned long long* acc_buf = nullptr;
-  int64_t acc_cap = 0;
-  int* counter = nullptr;
-  int* overflow = nullptr;
+  // per-query round state
+  unsigned long long* q_topk = nullptr;  // [nq x k_max] heap keys, ascending
+  int* q_topn = nullptr;                 // [nq] heap size
+  unsigned long long* q_keyr = nullptr;  // [nq] K-th key at the round's start (~0: not full)
+  float* q_r2 = nullptr;                 // [nq] r^2 at the round's start (inf: not full)
+  int* q_cur = nullptr;                  // [nq x 4] round start (rank, offset), end (rank, offset)
+  int* q_kc = nullptr;                   // [nq] keys queued in the round
+  unsigned long long* kb = nullptr;      // [nq x kb_cap] queued keys
+  int64_t kb_cap = 0;
+  // work items of the current and the next round: {query, count, first packed position, 0}
+  int4* items[2] = {nullptr, nullptr};
+  int items_cap = 0;
+  int* n_items = nullptr;   // [2]
+  int* overflow = nullptr;  // [1] nonzero if a capacity was exceeded
   int grid = 0;
 };
-// dtype: 0 f32, 1 bf16, 2 f16; mode: 0 DADE, 1 FULL_D.
-hipError_t launch_scan(const ScanArgs& a, int dtype, int mode, hipStream_t s);
+hipError_t launch_round(const RoundArgs& a, int buf, hipStream_t s);
+// Resident scan_round workgroups per CU for a store type / mode / Delta_d.
+int round_blocks_per_cu(int dtype, int mode, int delta_d);
+// init != 0: set up every query's state and queue its first round into buffer 0.
+hipError_t launch_merge(const RoundArgs& a, int buf_out, int init, hipStream_t s);
 
 }  // namespace dade

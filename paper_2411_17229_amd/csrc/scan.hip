@@ -1,103 +1,102 @@
-// The DADE list scan: Algorithm 1 for every candidate of a query's probed lists, the
-// size-K heap of the IVF scan (end of the Methodology section) and, for low-precision
-// stores, an exact FP32 rerank of the survivors.
+// The DADE list scan: Algorithm 1 for every candidate of every query's probed lists, the size-K
+// heap of the IVF scan (end of the Methodology section) and, for low-precision stores, an exact
+// FP32 rerank of the survivors.
 //
-// Execution model (one persistent launch for the whole batch):
-//   * a 256-thread workgroup owns one query at a time, pulled from a global counter, and
-//     walks its probe ranks round by round; a round's DCOs all use the heap as it was when
-//     the round started (thresholds r^2 and T_d r^2 are fixed for the round), and the round's
-//     kept candidates are merged into the top-K in LDS at its end.  Queries never wait for
-//     one another, so results do not depend on the batch.
-//   * the partial distance of a DCO is always summed in one order: each 8-coordinate unit's
-//     squared differences by an FMA chain from zero, then S_d = S_{d-8} + unit sum, unit after
-//     unit.  Every code path below keeps that order, so a DCO's S_d (and decision) does not
-//     depend on which path ran it, on the tile shape or on the rest of the batch.
-//   * dense rounds (heap not yet full, so no test can reject, or FDScanning mode): 16 lanes
-//     cooperate on one candidate and fetch up to 512 coordinates of its row per step.
-//   * rounds with a full heap: one lane per candidate reads the row up to the first test
-//     d = Delta_d (64-byte loads) and tests S_d > T_d r^2 (Eq. (13) + the hypothesis test in
-//     reduced form); almost every far candidate stops here.  The survivors go to an LDS queue
-//     that 16-lane groups process with wide loads, replaying the remaining tests in order
-//     (d = 2 Delta_d, 3 Delta_d, ... below D) and stopping at the first rejection.
-//   * at d = D a candidate is kept iff the heap is not full or (S_D, id) < (r^2, id_r).
-//   * low-precision stores: a survivor is queued with its stored-precision S_D when the heap
-//     is not full or S_D <= (1 + delta) r^2.  After the round the K smallest queued keys are
-//     reranked exactly (FP32, from the original vectors); with b the K-th smallest exact
-//     distance of the heap and those, the other queued candidates are reranked only where
-//     S_D <= (1 + delta) b; the keep rule then applies to the exact values.
+// Rounds.  A query's candidate sequence (its probed lists in probe order) is cut into rounds:
+// the first round is its first K candidates (they fill the heap), later rounds end where the
+// schedule's probe ranks end (every rank, or ranks 1, 2, 4, 8, ...).  Every DCO of a round sees
+// the query's heap as it was when the round started (r^2 and the thresholds T_d r^2 are a
+// snapshot), and the round's kept candidates are merged at its end.  Queries never interact, so
+// a query's result does not depend on the batch or on how the work is spread over the GPU.
+//
+// The rounds run for all queries at once, two kernels per round:
+//   * scan_round: a persistent grid whose waves pull work items (one query, up to 64
+//     consecutive candidates of one list).  One lane per candidate reads the head block
+//     (coordinates [0, 32), contiguous across a list) and tests S_d > T_d r^2 at d = Delta_d
+//     (Eq. (13) with the hypothesis test in reduced form); a far candidate stops there.  A
+//     survivor goes on a per-wave LDS stack and is continued later, 64 at a time, in levels of
+//     1, 1, 2, 4, ... blocks of 32 coordinates (all loads of a level in flight at once), each
+//     level replaying the tests it covers in order.  Rounds whose heap is not yet full (no test
+//     can reject) and FDScanning read whole rows.
+//   * merge_round: one workgroup per query merges the round's queued keys into its top-K (for
+//     low-precision stores through the rerank rule below), takes the snapshot for the next
+//     round, advances the query's cursor and queues the next round's work items.
+// A DCO's partial distance is summed in one order on every path: each 8-coordinate unit's
+// squared differences by an FMA chain from zero, then S_d = S_{d-8} + unit sum, unit after unit.
+// Low-precision stores: a survivor is queued with its stored-precision S_D when the heap is not
+// full or S_D <= (1 + delta) r^2; at the merge the K smallest queued keys are reranked exactly
+// (FP32, from the original vectors); with b the K-th smallest exact distance of the heap and
+// those, the other queued candidates are reranked only where S_D <= (1 + delta) b; the keep rule
+// (heap not full, or (S_D, id) < (r^2, id_r)) then applies to exact values.
 #include "kernels.h"
 
 namespace dade {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kGroup = 16;                    // lanes per candidate in the cooperative paths
+constexpr int kWaves = kThreads / 64;
+constexpr int kStack = 128;        // deep-stack entries per wave (at most 127 are live)
+constexpr int kItem = 64;          // candidates per work item
+constexpr int kMergeChunk = 512;   // queued keys handled per LDS pass of the merge
+constexpr int kBlock = kHead;      // coordinates per block; block 0 is the head
+constexpr int kGroup = 16;         // lanes per candidate in the exact rerank
 constexpr int kGroups = kThreads / kGroup;
-constexpr int kMaxUnitsPerLane = 8;           // 8-coordinate units a lane fetches per group step
-constexpr int kMaxRoundLists = 64;            // lists handled together inside one round
-constexpr int kMergeChunk = 512;              // queued keys handled per LDS pass
-constexpr int kQueueLds = 512;                // queued keys kept in LDS (more spill to global)
-constexpr int kDeepCap = 2 * kThreads;        // first-test survivors of one pass, for the groups
-constexpr int kPreloadProbes = 128;           // probed lists whose offsets are kept in LDS
-constexpr int kDenseGroupMax = 64;            // dense rounds up to this size use 16-lane groups
 
-// ---- stored-coordinate access ---------------------------------------------------------------
-// A unit is 8 consecutive coordinates; a chunk is the 64 bytes one lane loads at a time.
+struct Rows {
+  const void* head;
+  const void* tail;
+  int tw;   // tail row length, dp - kBlock
+};
+
+// ---- stored-coordinate blocks (32 coordinates) ----------------------------------------------
 template <typename ST>
 struct Store;
 
 template <>
 struct Store<float> {
-  static constexpr int CH = 16;  // coordinates per chunk
-  static constexpr int R = 4;    // units per lane per group step (512 coordinates per step)
-  struct Chunk { float4 x[4]; };
-  __device__ static inline Chunk load_chunk(const void* base, int64_t pos, int dp, int g) {
-    const float4* p = reinterpret_cast<const float4*>(static_cast<const float*>(base) + pos * dp + g * CH);
-    return Chunk{{p[0], p[1], p[2], p[3]}};
+  static constexpr int kMaxB = 2;   // blocks per level: 256 bytes in flight per lane
+  struct Block { float4 x[8]; };
+  __device__ static inline Block load(const Rows& r, int64_t p, int bi) {
+    const float* base = bi == 0 ? static_cast<const float*>(r.head) + p * kBlock
+                                : static_cast<const float*>(r.tail) + p * r.tw + (bi - 1) * kBlock;
+    const float4* v = reinterpret_cast<const float4*>(base);
+    Block b;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) b.x[i] = v[i];
+    return b;
   }
-  __device__ static inline void chunk_unit(const Chunk& c, int i, float* v) {
-    const float4 a = c.x[2 * i], b = c.x[2 * i + 1];
-    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w; v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
-  }
-  struct Raw { float4 a, b; };
-  __device__ static inline Raw unit_raw(const void* base, int64_t pos, int dp, int u) {
-    const float4* p = reinterpret_cast<const float4*>(static_cast<const float*>(base) + pos * dp + 8 * u);
-    return Raw{p[0], p[1]};
-  }
-  __device__ static inline void unit_vals(const Raw& r, float* v) {
-    v[0] = r.a.x; v[1] = r.a.y; v[2] = r.a.z; v[3] = r.a.w;
-    v[4] = r.b.x; v[5] = r.b.y; v[6] = r.b.z; v[7] = r.b.w;
+  __device__ static inline void unit(const Block& b, int j, float* v) {
+    const float4 a = b.x[2 * j], c = b.x[2 * j + 1];
+    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w; v[4] = c.x; v[5] = c.y; v[6] = c.z; v[7] = c.w;
   }
 };
 
 template <bool BF16>
 struct Store16 {
-  static constexpr int CH = 32;
-  static constexpr int R = 8;    // units per lane per group step (1024 coordinates per step)
-  struct Chunk { uint4 x[4]; };
-  __device__ static inline void words(const uint4& r, float* v) {
-    const uint32_t w[4] = {r.x, r.y, r.z, r.w};
+  static constexpr int kMaxB = 4;
+  struct Block { uint4 x[4]; };
+  __device__ static inline Block load(const Rows& r, int64_t p, int bi) {
+    const uint16_t* base = bi == 0 ? static_cast<const uint16_t*>(r.head) + p * kBlock
+                                   : static_cast<const uint16_t*>(r.tail) + p * r.tw + (bi - 1) * kBlock;
+    const uint4* v = reinterpret_cast<const uint4*>(base);
+    Block b;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int i = 0; i < 4; ++i) b.x[i] = v[i];
+    return b;
+  }
+  __device__ static inline void unit(const Block& b, int j, float* v) {
+    const uint32_t w[4] = {b.x[j].x, b.x[j].y, b.x[j].z, b.x[j].w};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
       if (BF16) {
-        v[2 * j + 0] = __builtin_bit_cast(float, w[j] << 16);
-        v[2 * j + 1] = __builtin_bit_cast(float, w[j] & 0xFFFF0000u);
+        v[2 * k + 0] = __builtin_bit_cast(float, w[k] << 16);
+        v[2 * k + 1] = __builtin_bit_cast(float, w[k] & 0xFFFF0000u);
       } else {
-        v[2 * j + 0] = float(__builtin_bit_cast(_Float16, uint16_t(w[j] & 0xFFFFu)));
-        v[2 * j + 1] = float(__builtin_bit_cast(_Float16, uint16_t(w[j] >> 16)));
+        v[2 * k + 0] = float(__builtin_bit_cast(_Float16, uint16_t(w[k] & 0xFFFFu)));
+        v[2 * k + 1] = float(__builtin_bit_cast(_Float16, uint16_t(w[k] >> 16)));
       }
     }
   }
-  __device__ static inline Chunk load_chunk(const void* base, int64_t pos, int dp, int g) {
-    const uint4* p = reinterpret_cast<const uint4*>(static_cast<const uint16_t*>(base) + pos * dp + g * CH);
-    return Chunk{{p[0], p[1], p[2], p[3]}};
-  }
-  __device__ static inline void chunk_unit(const Chunk& c, int i, float* v) { words(c.x[i], v); }
-  using Raw = uint4;
-  __device__ static inline Raw unit_raw(const void* base, int64_t pos, int dp, int u) {
-    return *reinterpret_cast<const uint4*>(static_cast<const uint16_t*>(base) + pos * dp + 8 * u);
-  }
-  __device__ static inline void unit_vals(const Raw& r, float* v) { words(r, v); }
 };
 
 template <>
@@ -122,74 +121,213 @@ __device__ inline void q8(const float* qs, int d, float* q) {
   q[0] = a.x; q[1] = a.y; q[2] = a.z; q[3] = a.w; q[4] = b.x; q[5] = b.y; q[6] = b.z; q[7] = b.w;
 }
 
-// Reads that bypass the CU's L1, for keys other waves of the workgroup wrote to global memory.
-__device__ inline unsigned long long load_l2(const unsigned long long* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+// Bits of m set below this lane.
+__device__ inline int lanes_below(unsigned long long m) {
+  return int(__builtin_amdgcn_mbcnt_hi(uint32_t(m >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(m), 0u)));
 }
 
-// One DCO continued by a 16-lane group from unit u_start with running sum S.  Every lane of the
-// group fetches Store<ST>::R units per step; the unit sums are staged in the group's LDS slice
-// (gs, kGroup * kMaxUnitsPerLane floats) in unit order, and every lane then adds them
-// one by one, replaying the tests.  Returns the d at which the DCO ended (rejected, or
-// d >= dim) and updates S.  Control flow is uniform within the group.
-template <typename ST, bool DADE>
-__device__ int group_dco(const void* store, int64_t pos, int dp, int dim, const float* qs,
-                         const float* thr, int dd, int u_start, float& S, bool& rejected, int gl,
-                         float* gs) {
+// One level of a DCO: blocks [b, b + nb) of row p (nb <= NB), with all of their loads issued
+// first.  Adds the units below dim to S in the canonical order and, with tests on, rejects at
+// the first tested d (a multiple of dd, below dim) where S_d > T_d r^2.
+template <typename ST, bool PER_DIM, int NB>
+__device__ inline void advance(const Rows& rows, int64_t p, const float* qv, float r2,
+                               const float* __restrict__ T, int dim, int dd, bool tests, int b,
+                               int nb, float& S, bool& rej, int& dexit) {
   using SS = Store<ST>;
-  constexpr int R = SS::R;
-  constexpr int kStep = kGroup * R;
-  const int units = dp >> 3;
-  const int u_end = (dim + 7) >> 3;          // units that hold real coordinates
-  int u0 = u_start;
-  rejected = false;
-  int next_test = DADE ? (8 * u_start / dd + 1) * dd : 0;   // first tested d after u_start
-  int ti = DADE ? next_test / dd - 1 : 0;
-  while (u0 < u_end) {
-    typename SS::Raw raw[R];
+  typename SS::Block blk[NB];
 #pragma unroll
-    for (int r = 0; r < R; ++r) {   // clamped, unconditional: all loads in flight
-      const int u = u0 + r * kGroup + gl;
-      raw[r] = SS::unit_raw(store, pos, dp, u < units ? u : units - 1);
-    }
+  for (int i = 0; i < NB; ++i) blk[i] = SS::load(rows, p, b + (i < nb ? i : nb - 1));
+  int nt = tests ? (b * kBlock / dd + 1) * dd : 0x7fffffff;   // next tested d
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const int u = u0 + r * kGroup + gl;
-      const int uc = u < units ? u : units - 1;
-      float v[8], q[8];
-      SS::unit_vals(raw[r], v);
-      q8(qs, 8 * uc, q);
-      gs[r * kGroup + gl] = unit_sum(q, v);   // units past u_end are never read back
-    }
-    __builtin_amdgcn_wave_barrier();
-    const int n = (u_end - u0 < kStep) ? u_end - u0 : kStep;
-    for (int i = 0; i < n; i += 4) {
-      const float4 w = *reinterpret_cast<const float4*>(gs + i);
-      const float wv[4] = {w.x, w.y, w.z, w.w};
+  for (int i = 0; i < NB; ++i) {
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        if (i + t < n) {
-          S = S + wv[t];
-          if (DADE) {
-            const int d = 8 * (u0 + i + t + 1);
-            if (d == next_test) {
-              if (d < dim && S > thr[ti]) {
-                rejected = true;
-                __builtin_amdgcn_wave_barrier();
-                return d;
+    for (int j = 0; j < kBlock / 8; ++j) {
+      const int d0 = (b + i) * kBlock + 8 * j;
+      if (i < nb && !rej && d0 < dim) {
+        float v[8], qq[8];
+        SS::unit(blk[i], j, v);
+        q8(qv, d0, qq);
+        if (PER_DIM) {
+          float pp = 0.f;
+#pragma unroll
+          for (int c = 0; c < 8; ++c) {
+            const float df = qq[c] - v[c];
+            pp = fmaf(df, df, pp);
+            const int d = d0 + c + 1;
+            if (d == nt) {
+              if (!rej && d < dim && S + pp > T[d - 1] * r2) {
+                rej = true;
+                dexit = d;
               }
-              next_test += dd;
-              ++ti;
+              nt += dd;
             }
+          }
+          S = S + pp;
+        } else {
+          S = S + unit_sum(qq, v);
+          const int d = d0 + 8;
+          if (d == nt) {
+            if (d < dim && S > T[d - 1] * r2) {
+              rej = true;
+              dexit = d;
+            }
+            nt += dd;
           }
         }
       }
     }
-    __builtin_amdgcn_wave_barrier();
-    u0 += kStep;
   }
-  return dim;
 }
+
+// The round's filter on a finished DCO (d reached D): queue it for the merge or drop it.
+template <bool RERANK>
+__device__ inline bool passes(float S, uint32_t rid, bool full, unsigned long long keyr, float gate) {
+  return RERANK ? (!full || S <= gate) : (!full || make_key(S, rid) < keyr);
+}
+
+__device__ inline void put_key(const RoundArgs& a, int q, int slot, unsigned long long key) {
+  if (slot < a.kb_cap) a.kb[int64_t(q) * a.kb_cap + slot] = key;
+  else atomicOr(a.overflow, 1);
+}
+
+// ------------------------------------------------------------------------------------------------
+// scan_round: the DCOs of one round for every query.
+template <typename ST, bool DADE, bool RERANK, bool PER_DIM>
+__global__ __launch_bounds__(kThreads) void scan_round_kernel(RoundArgs a, int buf) {
+  using SS = Store<ST>;
+  constexpr int MB = SS::kMaxB;
+  __shared__ int4 stack_lds[kWaves][kStack];
+  __shared__ int s_claim;
+  const int lane = threadIdx.x & 63;
+  int4* stk = stack_lds[threadIdx.x >> 6];
+  const int dim = a.dim, dp = a.dp, dd = a.delta_d;
+  const int nblk = (dim + kBlock - 1) / kBlock;
+  int nb0 = ((dd < dim ? dd : dim) + kBlock - 1) / kBlock;   // level 0 reaches the first test
+  nb0 = nb0 > MB ? MB : nb0;
+  nb0 = nb0 > nblk ? nblk : nb0;
+  const bool any_tests = DADE && dd < dim;
+  const Rows rows{a.head, a.tail, dp - kBlock};
+  const int n_queued = a.n_items[buf];
+  const int n_items = n_queued < a.items_cap ? n_queued : a.items_cap;
+  const int4* items = a.items[buf];
+  if (blockIdx.x == 0 && threadIdx.x == 0) a.n_items[buf ^ 1] = 0;   // the merge refills it
+  const float gate_f = 1.f + a.rerank_delta;
+  // Workgroup g owns items g, g + grid, g + 2 grid, ... (a query's items are spread over the
+  // grid); its waves take them in turn from an LDS counter, so claims need no global atomics.
+  if (threadIdx.x == 0) s_claim = 0;
+  __syncthreads();
+
+  int sn = 0;             // live stack entries (wave-uniform)
+  bool drained = false;   // no work item left in this round
+  for (;;) {
+    if (sn >= 64 || (drained && sn > 0)) {
+      // ---- continue up to 64 stacked survivors by one level each
+      const int take = sn < 64 ? sn : 64;
+      const int base = sn - take;
+      const bool act = lane < take;
+      int4 e = make_int4(0, 0, 0, 0);
+      if (act) e = stk[base + lane];
+      sn = base;
+      const int q = e.x, p = e.y, lev = e.w & 255;
+      int b = e.w >> 8;
+      float S = __int_as_float(e.z);
+      bool cont = false;
+      if (act) {
+        const float r2 = a.q_r2[q];
+        int nb = 1 << (lev - 1 < 4 ? lev - 1 : 4);
+        nb = nb < nb0 ? nb0 : nb;
+        nb = nb > MB ? MB : nb;
+        nb = nb > nblk - b ? nblk - b : nb;
+        bool rej = false;
+        int dexit = dim;
+        advance<ST, PER_DIM, MB>(rows, p, a.qrot + int64_t(q) * dp, r2, a.T, dim, dd, true, b, nb, S,
+                                 rej, dexit);
+        b += nb;
+        if (rej || b >= nblk) {
+          if (a.stats) {
+            atomicAdd(reinterpret_cast<unsigned long long*>(a.stats + int64_t(q) * 4 + 0), 1ull);
+            atomicAdd(reinterpret_cast<unsigned long long*>(a.stats + int64_t(q) * 4 + 1),
+                      (unsigned long long)dexit);
+          }
+          const uint32_t rid = uint32_t(a.ids[p]);
+          if (!rej && passes<RERANK>(S, rid, true, a.q_keyr[q], gate_f * r2))
+            put_key(a, q, atomicAdd(a.q_kc + q, 1), make_key(S, rid));
+        } else {
+          cont = true;
+        }
+      }
+      const unsigned long long m = __ballot(cont);
+      if (cont) stk[sn + lanes_below(m)] = make_int4(q, p, __float_as_int(S), (b << 8) | (lev < 255 ? lev + 1 : 255));
+      sn += __popcll(m);
+      continue;
+    }
+    if (drained) break;
+
+    // ---- claim a work item
+    int k = 0;
+    if (lane == 0) k = atomicAdd(&s_claim, 1);
+    k = __shfl(k, 0);
+    const int64_t item = int64_t(blockIdx.x) + int64_t(k) * gridDim.x;
+    if (item >= n_items) {
+      drained = true;
+      continue;
+    }
+    const int4 it = items[item];
+    const int q = it.x, cnt = it.y;
+    const float r2 = a.q_r2[q];
+    const unsigned long long keyr = a.q_keyr[q];
+    const bool full = keyr != ~0ull;
+    const float* qv = a.qrot + int64_t(q) * dp;
+    const bool has = lane < cnt;
+    const int p = it.z + (has ? lane : 0);
+    const uint32_t rid = uint32_t(a.ids[p]);
+    float S = 0.f;
+    bool rej = false, done = true;
+    int dexit = dim;
+    if (!any_tests || !full) {
+      // whole rows: no test can reject (heap not full, FDScanning, or no d below D to test)
+      if (has)
+        for (int b = 0; b < nblk; b += MB)
+          advance<ST, false, MB>(rows, p, qv, r2, a.T, dim, dd, false, b, nblk - b < MB ? nblk - b : MB, S,
+                                 rej, dexit);
+    } else if (has) {
+      // level 0: up to the first test
+      if (nb0 == 1)
+        advance<ST, PER_DIM, 1>(rows, p, qv, r2, a.T, dim, dd, true, 0, 1, S, rej, dexit);
+      else
+        advance<ST, PER_DIM, MB>(rows, p, qv, r2, a.T, dim, dd, true, 0, nb0, S, rej, dexit);
+      done = rej || nb0 >= nblk;
+    }
+    const bool fin = has && done;
+    const bool queue = fin && !rej && passes<RERANK>(S, rid, full, keyr, gate_f * r2);
+    const unsigned long long mq = __ballot(queue);
+    if (mq) {
+      int slot = 0;
+      if (lane == 0) slot = atomicAdd(a.q_kc + q, __popcll(mq));
+      slot = __shfl(slot, 0);
+      if (queue) put_key(a, q, slot + lanes_below(mq), make_key(S, rid));
+    }
+    if (a.stats) {
+      unsigned nd = fin ? 1u : 0u, ds = fin ? unsigned(dexit) : 0u;
+#pragma unroll
+      for (int o = 32; o >= 1; o >>= 1) {
+        nd += __shfl_xor(nd, o, 64);
+        ds += __shfl_xor(ds, o, 64);
+      }
+      if (lane == 0 && nd) {
+        atomicAdd(reinterpret_cast<unsigned long long*>(a.stats + int64_t(q) * 4 + 0), (unsigned long long)nd);
+        atomicAdd(reinterpret_cast<unsigned long long*>(a.stats + int64_t(q) * 4 + 1), (unsigned long long)ds);
+      }
+    }
+    const bool deep = has && !done;
+    const unsigned long long md = __ballot(deep);
+    if (deep) stk[sn + lanes_below(md)] = make_int4(q, p, __float_as_int(S), (nb0 << 8) | 1);
+    sn += __popcll(md);
+  }
+}
+
+// ------------------------------------------------------------------------------------------------
+// merge_round helpers (one workgroup per query, keys in LDS).
 
 // heap[0..heap_n) (ascending keys) <- the K smallest of heap and cand[0..n); keys are unique,
 // so each key's rank is the count of smaller keys.  cand must have room for n + K entries.
@@ -213,443 +351,280 @@ __device__ void merge_into(unsigned long long* heap, int& heap_n, unsigned long 
   __syncthreads();
 }
 
-// keys[i] (stored-precision S_D, id) -> (exact FP32 S_D, id), one 16-lane group per key, in the
-// canonical unit order over the original vector.  Ends with a barrier.
+// keys[i] (stored-precision S_D, id) -> (exact FP32 S_D, id) over the original vectors: 16 lanes
+// per key, each summing its units (u = lane, lane + 16, ...) in order, then a fixed butterfly
+// over the 16 lanes.  Ends with a barrier.
 __device__ void exact_rerank(unsigned long long* keys, int n, const float* __restrict__ X,
-                             const float* qo, int dp, int dim, int tid, unsigned& count,
-                             float* gsum) {
-  const int grp = tid / kGroup, gl = tid % kGroup;
-  float* gs = gsum + grp * kGroup * kMaxUnitsPerLane;
-  for (int i = grp; i < n; i += kGroups) {
+                             const float* qo, int dp, int dim, int tid, unsigned& count) {
+  const int g = tid / kGroup, gl = tid % kGroup;
+  const int u_end = (dim + 7) / 8;
+  for (int i = g; i < n; i += kGroups) {
     const uint32_t id = key_id(keys[i]);
-    float S = 0.f;
-    bool rej;
-    group_dco<float, false>(X, int64_t(id), dp, dim, qo, nullptr, 1, 0, S, rej, gl, gs);
+    const float* x = X + int64_t(id) * dp;
+    float acc = 0.f;
+    for (int u0 = gl; u0 < u_end; u0 += 8 * kGroup) {
+      float4 ra[8], rb[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        int u = u0 + k * kGroup;
+        u = u < u_end ? u : u_end - 1;
+        ra[k] = *reinterpret_cast<const float4*>(x + 8 * u);
+        rb[k] = *reinterpret_cast<const float4*>(x + 8 * u + 4);
+      }
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const int u = u0 + k * kGroup;
+        if (u < u_end) {
+          const float v[8] = {ra[k].x, ra[k].y, ra[k].z, ra[k].w, rb[k].x, rb[k].y, rb[k].z, rb[k].w};
+          float qq[8];
+          q8(qo, 8 * u, qq);
+          acc = acc + unit_sum(qq, v);
+        }
+      }
+    }
+#pragma unroll
+    for (int o = kGroup / 2; o >= 1; o >>= 1) acc += __shfl_xor(acc, o, kGroup);
     if (gl == 0) {
-      keys[i] = make_key(S, id);
+      keys[i] = make_key(acc, id);
       ++count;
     }
   }
   __syncthreads();
 }
 
-template <typename ST, bool DADE, bool RERANK, bool PER_DIM_TESTS>
-__global__ __launch_bounds__(kThreads, 4) void scan_kernel(ScanArgs a) {
-  using SS = Store<ST>;
-  constexpr int CH = SS::CH;
-  extern __shared__ float dyn[];
-  float* qs = dyn;                              // [dp] rotated query
-  float* qo = dyn + a.dp;                       // [dp] original query (RERANK only)
-  float* thr = dyn + (RERANK ? 2 : 1) * a.dp;   // [ntests] T_d r^2 for the round
+// End (t1, off1) of the round that starts at (t, off): the first round holds the first K
+// candidates, later rounds end at the schedule's probe-rank boundaries.
+template <typename LenFn>
+__device__ void round_end(int t, int off, bool fill, int K, int np, int schedule, LenFn len_of,
+                          int& t1, int& off1) {
+  t1 = t + 1;
+  off1 = 0;
+  if (fill) {
+    int rem = K, tt = t, oo = off;
+    while (rem > 0 && tt < np) {
+      const int len = len_of(tt);
+      if (len - oo > rem) {
+        oo += rem;
+        rem = 0;
+      } else {
+        rem -= len - oo;
+        ++tt;
+        oo = 0;
+      }
+    }
+    t1 = tt;
+    off1 = oo;
+  } else if (schedule != 0) {
+    int B = 1;
+    while (B <= t) B <<= 1;
+    t1 = B < np ? B : np;
+  }
+}
 
+// Queue the work items of query q's round [(t, off), (t1, off1)).  One thread.
+template <typename LenFn, typename PosFn>
+__device__ void queue_items(const RoundArgs& a, int buf, int q, int t, int off, int t1, int off1,
+                            LenFn len_of, PosFn pos_of) {
+  const int t_last = off1 > 0 ? t1 : t1 - 1;
+  int n = 0;
+  for (int tt = t; tt <= t_last; ++tt) {
+    const int s0 = tt == t ? off : 0;
+    const int s1 = tt == t1 ? off1 : len_of(tt);
+    if (s1 > s0) n += (s1 - s0 + kItem - 1) / kItem;
+  }
+  if (n == 0) return;
+  int slot = atomicAdd(a.n_items + buf, n);
+  int4* items = a.items[buf];
+  for (int tt = t; tt <= t_last; ++tt) {
+    const int s0 = tt == t ? off : 0;
+    const int s1 = tt == t1 ? off1 : len_of(tt);
+    const int p0 = int(pos_of(tt));
+    for (int s = s0; s < s1; s += kItem) {
+      if (slot < a.items_cap) items[slot] = make_int4(q, s1 - s < kItem ? s1 - s : kItem, p0 + s, 0);
+      else atomicOr(a.overflow, 2);
+      ++slot;
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------------------
+// merge_round: per query, merge the round's queued keys, then set up its next round (or write
+// its result).  With init set it only sets up the first round.
+template <bool RERANK>
+__global__ __launch_bounds__(kThreads) void merge_round_kernel(RoundArgs a, int buf_out, int init) {
+  extern __shared__ float qo[];   // [dp] original query (RERANK)
   __shared__ unsigned long long topk[kMaxK];
   __shared__ unsigned long long newk[kMaxK];
   __shared__ unsigned long long fk[RERANK ? kMaxK : 1];
   __shared__ unsigned long long cand[kMergeChunk + kMaxK];
-  __shared__ int64_t lst_pos[kMaxRoundLists];
-  __shared__ int lst_pre[kMaxRoundLists + 1];
-  __shared__ int64_t pl_pos[kPreloadProbes];
-  __shared__ int pl_len[kPreloadProbes];
-  __shared__ int64_t dq_pos[kDeepCap];          // deep queue: survivors of the first test
-  __shared__ uint32_t dq_id[kDeepCap];
-  __shared__ float dq_S[kDeepCap];
-  __shared__ float gsum[kThreads * kMaxUnitsPerLane];   // per-group unit sums (cooperative paths)
-  __shared__ unsigned long long qkeys[kQueueLds];      // the round's queued keys
-  __shared__ int s_q, s_acc, s_nc, s_ndeep, s_t1, s_off1;
+  __shared__ int s_nc, s_fin;
   __shared__ unsigned long long s_b;
-  __shared__ unsigned long long s_stat[4];
 
+  const int q = blockIdx.x;
   const int tid = threadIdx.x;
-  const int grp = tid / kGroup, gl = tid % kGroup;
-  float* gs = gsum + grp * kGroup * kMaxUnitsPerLane;
-  const int dim = a.dim, dp = a.dp, dd = a.delta_d;
-  const int ntests = (dim - 1) / dd;
-  // lane-serial part of a full-heap round: up to the first test
-  const int a_chunks = (dd + CH - 1) / CH;
-  unsigned long long* acc = a.acc_buf + int64_t(blockIdx.x) * a.acc_cap;
+  const int dp = a.dp, dim = a.dim;
+  int K = a.k_pq ? a.k_pq[q] : a.k_max;
+  K = K < 1 ? 1 : (K > a.k_max ? a.k_max : K);
+  int np = a.nprobe_pq ? a.nprobe_pq[q] : a.nprobe_max;
+  np = np < 1 ? 1 : (np > a.nprobe_max ? a.nprobe_max : np);
+  const int32_t* pr = a.probes + int64_t(q) * a.nprobe_max;
+  auto len_of = [&](int tt) { return int(a.list_off[pr[tt] + 1] - a.list_off[pr[tt]]); };
+  auto pos_of = [&](int tt) { return a.list_off[pr[tt]]; };
+  int* cur = a.q_cur + 4 * int64_t(q);
+  unsigned long long* gtop = a.q_topk + int64_t(q) * a.k_max;
 
-  for (;;) {
-    if (tid == 0) s_q = atomicAdd(a.counter, 1);
-    __syncthreads();
-    const int qi = s_q;
-    if (qi >= a.nq) break;
-    int K = a.k_pq ? a.k_pq[qi] : a.k_max;
-    K = K < 1 ? 1 : (K > a.k_max ? a.k_max : K);
-    int np = a.nprobe_pq ? a.nprobe_pq[qi] : a.nprobe_max;
-    np = np < 1 ? 1 : (np > a.nprobe_max ? a.nprobe_max : np);
-    for (int c = tid; c < dp; c += kThreads) {
-      qs[c] = a.qrot[int64_t(qi) * dp + c];
-      if (RERANK) qo[c] = a.qorig[int64_t(qi) * dp + c];
+  if (init) {
+    if (tid == 0) {
+      a.q_topn[q] = 0;
+      a.q_kc[q] = 0;
+      a.q_keyr[q] = ~0ull;
+      a.q_r2[q] = __builtin_inff();
+      int t1, off1;
+      round_end(0, 0, true, K, np, a.schedule, len_of, t1, off1);
+      cur[0] = 0;
+      cur[1] = 0;
+      cur[2] = t1;
+      cur[3] = off1;
+      queue_items(a, buf_out, q, 0, 0, t1, off1, len_of, pos_of);
+      if (a.stats)
+        for (int i = 0; i < 4; ++i) a.stats[int64_t(q) * 4 + i] = 0;
     }
-    for (int t = tid; t < np && t < kPreloadProbes; t += kThreads) {
-      const int l = a.probes[int64_t(qi) * a.nprobe_max + t];
-      const int64_t o0 = a.list_off[l];
-      pl_pos[t] = o0;
-      pl_len[t] = int(a.list_off[l + 1] - o0);
-    }
-    if (tid < 4) s_stat[tid] = 0;
-    int topk_n = 0;
-    unsigned st_dco = 0, st_dims = 0, st_kept = 0, st_rr = 0;   // per thread, per query
-    __syncthreads();
+    return;
+  }
+  if (cur[0] >= np) return;   // finished in an earlier round
 
-    auto list_info = [&](int tt, int64_t& p0, int& len) {
-      if (tt < kPreloadProbes) {
-        p0 = pl_pos[tt];
-        len = pl_len[tt];
-      } else {
-        const int l = a.probes[int64_t(qi) * a.nprobe_max + tt];
-        p0 = a.list_off[l];
-        len = int(a.list_off[l + 1] - p0);
+  int topk_n = a.q_topn[q];
+  for (int i = tid; i < topk_n; i += kThreads) topk[i] = gtop[i];
+  if (RERANK)
+    for (int c = tid; c < dp; c += kThreads) qo[c] = a.qorig[int64_t(q) * dp + c];
+  const unsigned long long keyr = a.q_keyr[q];
+  const bool full = keyr != ~0ull;
+  const int kc = a.q_kc[q];
+  const int m = kc < a.kb_cap ? kc : int(a.kb_cap);
+  const unsigned long long* kb = a.kb + int64_t(q) * a.kb_cap;
+  unsigned st_kept = 0, st_rr = 0;
+  __syncthreads();
+
+  if (!RERANK) {
+    for (int base = 0; base < m; base += kMergeChunk) {
+      const int cnt = m - base < kMergeChunk ? m - base : kMergeChunk;
+      const unsigned long long kth = topk_n == K ? topk[K - 1] : ~0ull;
+      if (tid == 0) s_nc = 0;
+      __syncthreads();
+      for (int i = tid; i < cnt; i += kThreads) {
+        const unsigned long long key = kb[base + i];
+        if (key < kth) cand[atomicAdd(&s_nc, 1)] = key;
       }
-    };
-    // round cursor: probe rank t and offset inside that list
-    int t = 0, off = 0;
-    bool fill = true;
-    while (t < np) {
-      // ---- round extent [(t, off), (t1, off1)): the first round holds the first K candidates
-      //      (they fill the heap); later rounds end where the schedule's probe ranks end
+      __syncthreads();
+      if (tid == 0) st_kept += unsigned(s_nc);
+      merge_into(topk, topk_n, newk, cand, s_nc, K, tid);
+    }
+  } else if (m > 0) {
+    // F = the K smallest queued keys (stored-precision S_D, id), into cand[0..fn)
+    int fn = 0;
+    unsigned long long fmax = ~0ull;
+    if (m <= K) {
+      for (int i = tid; i < m; i += kThreads) cand[i] = kb[i];
+      fn = m;
+      __syncthreads();
+    } else {
+      for (int base = 0; base < m; base += kMergeChunk) {
+        const int cnt = m - base < kMergeChunk ? m - base : kMergeChunk;
+        const unsigned long long kth = fn == K ? fk[K - 1] : ~0ull;
+        if (tid == 0) s_nc = 0;
+        __syncthreads();
+        for (int i = tid; i < cnt; i += kThreads) {
+          const unsigned long long key = kb[base + i];
+          if (key < kth) cand[atomicAdd(&s_nc, 1)] = key;
+        }
+        __syncthreads();
+        merge_into(fk, fn, newk, cand, s_nc, K, tid);
+      }
+      fmax = fk[fn - 1];
+      for (int i = tid; i < fn; i += kThreads) cand[i] = fk[i];
+      __syncthreads();
+    }
+    exact_rerank(cand, fn, a.X, qo, dp, dim, tid, st_rr);
+    // b = K-th smallest exact key of the heap snapshot and F
+    if (tid == 0) s_b = ~0ull;
+    __syncthreads();
+    if (topk_n + fn >= K) {
+      for (int i = tid; i < topk_n + fn; i += kThreads) {
+        const unsigned long long key = i < topk_n ? topk[i] : cand[i - topk_n];
+        int rank = 0;
+        for (int j = 0; j < topk_n; ++j) rank += topk[j] < key;
+        for (int j = 0; j < fn; ++j) rank += cand[j] < key;
+        if (rank == K - 1) s_b = key;
+      }
+    }
+    __syncthreads();
+    const float bound = s_b == ~0ull ? __builtin_inff() : (1.f + a.rerank_delta) * key_dist(s_b);
+    if (tid == 0) {
+      int w = 0;
+      for (int i = 0; i < fn; ++i)
+        if (!full || cand[i] < keyr) cand[w++] = cand[i];
+      s_nc = w;
+      st_kept += unsigned(w);
+    }
+    __syncthreads();
+    merge_into(topk, topk_n, newk, cand, s_nc, K, tid);
+    // the rest of the queue, reranked only inside the bound
+    for (int base = 0; m > K && base < m; base += kMergeChunk) {
+      const int cnt = m - base < kMergeChunk ? m - base : kMergeChunk;
+      if (tid == 0) s_nc = 0;
+      __syncthreads();
+      for (int i = tid; i < cnt; i += kThreads) {
+        const unsigned long long key = kb[base + i];
+        if (key > fmax && key_dist(key) <= bound) cand[atomicAdd(&s_nc, 1)] = key;
+      }
+      __syncthreads();
+      const int nr = s_nc;
+      __syncthreads();
+      if (nr == 0) continue;
+      exact_rerank(cand, nr, a.X, qo, dp, dim, tid, st_rr);
       if (tid == 0) {
-        int t1 = t + 1, off1 = 0;
-        if (fill) {
-          int rem = K, tt = t, oo = off;
-          while (rem > 0 && tt < np) {
-            int64_t p0;
-            int len;
-            list_info(tt, p0, len);
-            if (len - oo > rem) {
-              oo += rem;
-              rem = 0;
-            } else {
-              rem -= len - oo;
-              ++tt;
-              oo = 0;
-            }
-          }
-          t1 = tt;
-          off1 = oo;
-        } else if (a.schedule != 0) {
-          int B = 1;
-          while (B <= t) B <<= 1;
-          t1 = B < np ? B : np;
-        }
-        s_t1 = t1;
-        s_off1 = off1;
+        int w = 0;
+        for (int i = 0; i < nr; ++i)
+          if (!full || cand[i] < keyr) cand[w++] = cand[i];
+        s_nc = w;
+        st_kept += unsigned(w);
       }
-      // ---- round snapshot
-      const bool full = topk_n == K;
-      const unsigned long long keyr = full ? topk[K - 1] : ~0ull;
-      const float r2 = full ? key_dist(keyr) : __builtin_inff();
-      const float gate = (1.f + a.rerank_delta) * r2;
-      const bool dense = !DADE || !full || ntests == 0;
-      if (DADE)
-        for (int j = tid; j < ntests; j += kThreads) thr[j] = a.T[(j + 1) * dd - 1] * r2;
-      if (tid == 0) s_acc = 0;
       __syncthreads();
-      const int t1 = s_t1, off1 = s_off1;
-      const int t_last = off1 > 0 ? t1 : t1 - 1;   // last probe rank the round touches
-
-      // queue a finished DCO (FP32 store: the keep rule; low precision: the rerank gate)
-      bool wrote_global = false;
-      auto finish = [&](float S, uint32_t rid) {
-        const bool queue = RERANK ? (!full || S <= gate) : (!full || make_key(S, rid) < keyr);
-        if (queue) {
-          const int slot = atomicAdd(&s_acc, 1);
-          if (slot < kQueueLds) {
-            qkeys[slot] = make_key(S, rid);
-          } else if (slot - kQueueLds < a.acc_cap) {
-            acc[slot - kQueueLds] = make_key(S, rid);
-            wrote_global = true;
-          } else {
-            atomicOr(a.overflow, 1);
-          }
-        }
-      };
-
-      for (int lb = t; lb <= t_last; lb += kMaxRoundLists) {
-        const int le = (t_last + 1 - lb < kMaxRoundLists) ? t_last + 1 : lb + kMaxRoundLists;
-        const int nl = le - lb;
-        if (tid < 64) {   // the round's segment of each list and an exclusive prefix (one wave)
-          int len = 0;
-          int64_t p0 = 0;
-          if (tid < nl) {
-            const int tt = lb + tid;
-            int L;
-            list_info(tt, p0, L);
-            const int s0 = (tt == t) ? off : 0;
-            const int s1 = (tt == t1) ? off1 : L;
-            p0 += s0;
-            len = s1 - s0;
-          }
-          int incl = len;
-#pragma unroll
-          for (int o = 1; o < 64; o <<= 1) {
-            const int v = __shfl_up(incl, o, 64);
-            if (tid >= o) incl += v;
-          }
-          if (tid < nl) {
-            lst_pos[tid] = p0;
-            lst_pre[tid] = incl - len;
-          }
-          if (tid == nl - 1) lst_pre[nl] = incl;
-        }
-        __syncthreads();
-        const int total = lst_pre[nl];
-        auto locate = [&](int cc, int64_t& pos, uint32_t& rid) {
-          int lo = 0, hi = nl - 1;
-          while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (lst_pre[mid] <= cc) lo = mid; else hi = mid - 1;
-          }
-          pos = lst_pos[lo] + (cc - lst_pre[lo]);
-          rid = uint32_t(a.ids[pos]);
-        };
-
-        if (PER_DIM_TESTS && !dense) {
-          // ---- Delta_d not a multiple of 8: one lane per candidate, tests inside units
-          for (int c = tid; c < total; c += kThreads) {
-            int64_t pos;
-            uint32_t rid;
-            locate(c, pos, rid);
-            float S = 0.f;
-            int next_test = dd, ti = 0, dexit = dim;
-            bool rej = false;
-            for (int u = 0; u < (dim + 7) / 8 && !rej; ++u) {
-              const typename SS::Raw raw = SS::unit_raw(a.store, pos, dp, u);
-              float v[8], q[8];
-              SS::unit_vals(raw, v);
-              q8(qs, 8 * u, q);
-              float p = 0.f;
-              for (int i = 0; i < 8; ++i) {
-                const float df = q[i] - v[i];
-                p = fmaf(df, df, p);
-                const int d = 8 * u + i + 1;
-                if (!rej && d == next_test && d < dim) {
-                  if (S + p > thr[ti]) { rej = true; dexit = d; }
-                  ++ti;
-                  next_test += dd;
-                }
-              }
-              S = S + p;
-            }
-            ++st_dco;
-            st_dims += unsigned(dexit);
-            if (!rej) finish(S, rid);
-          }
-        } else if (dense && total > kDenseGroupMax) {
-          // ---- dense round, many candidates: one lane per candidate, the next 64-byte chunk
-          //      in flight while the current one is summed
-          const int nch = (dim + CH - 1) / CH;
-          for (int c = tid; c < total; c += kThreads) {
-            int64_t pos;
-            uint32_t rid;
-            locate(c, pos, rid);
-            float S = 0.f;
-            typename SS::Chunk cur = SS::load_chunk(a.store, pos, dp, 0);
-            for (int g = 0; g < nch; ++g) {
-              const typename SS::Chunk nxt = SS::load_chunk(a.store, pos, dp, g + 1 < nch ? g + 1 : g);
-#pragma unroll
-              for (int i = 0; i < CH / 8; ++i) {
-                float v[8], q[8];
-                SS::chunk_unit(cur, i, v);
-                q8(qs, g * CH + 8 * i, q);
-                S = S + unit_sum(q, v);
-              }
-              cur = nxt;
-            }
-            ++st_dco;
-            st_dims += unsigned(dim);
-            finish(S, rid);
-          }
-        } else if (dense) {
-          // ---- dense round, few candidates (the fill round): 16 lanes per candidate
-          for (int c = grp; c < total; c += kGroups) {
-            int64_t pos;
-            uint32_t rid;
-            locate(c, pos, rid);
-            float S = 0.f;
-            bool rej;
-            const int dexit = group_dco<ST, false>(a.store, pos, dp, dim, qs, thr, dd, 0, S, rej, gl, gs);
-            if (gl == 0) {
-              ++st_dco;
-              st_dims += unsigned(dexit);
-              finish(S, rid);
-            }
-          }
-        } else {
-          // ---- full heap: passes of 2 x 256 candidates; each lane tests two candidates up to
-          //      the first test (both first chunks in flight), survivors go to the deep queue,
-          //      which the 16-lane groups drain after the pass
-          for (int cb = 0; cb < total; cb += 2 * kThreads) {
-            if (tid == 0) s_ndeep = 0;
-            __syncthreads();
-            const int c0 = cb + tid, c1 = cb + kThreads + tid;
-            int64_t pos0, pos1;
-            uint32_t rid0, rid1;
-            locate(c0 < total ? c0 : total - 1, pos0, rid0);      // clamped: always a valid row
-            locate(c1 < total ? c1 : total - 1, pos1, rid1);
-            const typename SS::Chunk ch0 = SS::load_chunk(a.store, pos0, dp, 0);
-            const typename SS::Chunk ch1 = SS::load_chunk(a.store, pos1, dp, 0);
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-              const int c = h ? c1 : c0;
-              if (c >= total) continue;
-              const int64_t pos = h ? pos1 : pos0;
-              const uint32_t rid = h ? rid1 : rid0;
-              float S = 0.f;
-              bool rej = false;
-              int dexit = dim, next_test = dd, ti = 0;
-              int g = 0;
-              for (; g < a_chunks && !rej; ++g) {
-                const typename SS::Chunk ch = g == 0 ? (h ? ch1 : ch0) : SS::load_chunk(a.store, pos, dp, g);
-#pragma unroll
-                for (int i = 0; i < CH / 8; ++i) {
-                  if (!rej) {
-                    float v[8], q[8];
-                    SS::chunk_unit(ch, i, v);
-                    q8(qs, g * CH + 8 * i, q);
-                    S = S + unit_sum(q, v);
-                    const int d = g * CH + 8 * i + 8;
-                    if (d == next_test && d < dim) {
-                      if (S > thr[ti]) { rej = true; dexit = d; }
-                      ++ti;
-                      next_test += dd;
-                    }
-                  }
-                }
-              }
-              if (rej || g * CH >= dim) {
-                ++st_dco;
-                st_dims += unsigned(dexit);
-                if (!rej) finish(S, rid);
-              } else {
-                const int slot = atomicAdd(&s_ndeep, 1);   // < 2 * kThreads <= kDeepCap
-                dq_pos[slot] = pos;
-                dq_id[slot] = rid;
-                dq_S[slot] = S;
-              }
-            }
-            __syncthreads();
-            const int nd = s_ndeep;
-            for (int j = grp; j < nd; j += kGroups) {
-              float S = dq_S[j];
-              bool rej;
-              const int dexit = group_dco<ST, true>(a.store, dq_pos[j], dp, dim, qs, thr, dd,
-                                                    a_chunks * CH / 8, S, rej, gl, gs);
-              if (gl == 0) {
-                ++st_dco;
-                st_dims += unsigned(dexit);
-                if (!rej) finish(S, dq_id[j]);
-              }
-            }
-            __syncthreads();
-          }
-        }
-        __syncthreads();
-      }
-      if (wrote_global) __threadfence();   // spilled queue keys reach L2 before others read them
-      __syncthreads();
-
-      const int m = s_acc < kQueueLds + a.acc_cap ? s_acc : int(kQueueLds + a.acc_cap);
-      auto queued = [&](int i) -> unsigned long long {
-        return i < kQueueLds ? qkeys[i] : load_l2(acc + (i - kQueueLds));
-      };
-      if (!RERANK) {
-        // ---- merge the round's kept keys into the top-K
-        for (int base = 0; base < m; base += kMergeChunk) {
-          const int cnt = (m - base < kMergeChunk) ? m - base : kMergeChunk;
-          const unsigned long long kth = (topk_n == K) ? topk[K - 1] : ~0ull;
-          if (tid == 0) s_nc = 0;
-          __syncthreads();
-          for (int i = tid; i < cnt; i += kThreads) {
-            const unsigned long long key = queued(base + i);
-            if (key < kth) cand[atomicAdd(&s_nc, 1)] = key;
-          }
-          __syncthreads();
-          st_kept += (tid == 0) ? unsigned(s_nc) : 0u;
-          merge_into(topk, topk_n, newk, cand, s_nc, K, tid);
-        }
-      } else if (m > 0) {
-        // ---- F = the K smallest queued keys (stored-precision S_D, id), into cand[0..fn)
-        int fn = 0;
-        unsigned long long fmax = ~0ull;
-        if (m <= K) {
-          for (int i = tid; i < m; i += kThreads) cand[i] = queued(i);
-          fn = m;
-          __syncthreads();
-        } else {
-          for (int base = 0; base < m; base += kMergeChunk) {
-            const int cnt = (m - base < kMergeChunk) ? m - base : kMergeChunk;
-            const unsigned long long kth = (fn == K) ? fk[K - 1] : ~0ull;
-            if (tid == 0) s_nc = 0;
-            __syncthreads();
-            for (int i = tid; i < cnt; i += kThreads) {
-              const unsigned long long key = queued(base + i);
-              if (key < kth) cand[atomicAdd(&s_nc, 1)] = key;
-            }
-            __syncthreads();
-            merge_into(fk, fn, newk, cand, s_nc, K, tid);
-          }
-          fmax = fk[fn - 1];
-          for (int i = tid; i < fn; i += kThreads) cand[i] = fk[i];
-          __syncthreads();
-        }
-        exact_rerank(cand, fn, a.X, qo, dp, dim, tid, st_rr, gsum);
-        // b = K-th smallest exact key of the heap snapshot and F
-        if (tid == 0) s_b = ~0ull;
-        __syncthreads();
-        if (topk_n + fn >= K) {
-          for (int i = tid; i < topk_n + fn; i += kThreads) {
-            const unsigned long long key = i < topk_n ? topk[i] : cand[i - topk_n];
-            int rank = 0;
-            for (int j = 0; j < topk_n; ++j) rank += topk[j] < key;
-            for (int j = 0; j < fn; ++j) rank += cand[j] < key;
-            if (rank == K - 1) s_b = key;
-          }
-        }
-        __syncthreads();
-        const float bound = (s_b == ~0ull) ? __builtin_inff() : (1.f + a.rerank_delta) * key_dist(s_b);
-        if (tid == 0) {
-          int w = 0;
-          for (int i = 0; i < fn; ++i)
-            if (!full || cand[i] < keyr) cand[w++] = cand[i];
-          s_nc = w;
-          st_kept += unsigned(w);
-        }
-        __syncthreads();
-        merge_into(topk, topk_n, newk, cand, s_nc, K, tid);
-        // the rest of the queue, reranked only inside the bound
-        for (int base = 0; m > K && base < m; base += kMergeChunk) {
-          const int cnt = (m - base < kMergeChunk) ? m - base : kMergeChunk;
-          if (tid == 0) s_nc = 0;
-          __syncthreads();
-          for (int i = tid; i < cnt; i += kThreads) {
-            const unsigned long long key = queued(base + i);
-            if (key > fmax && key_dist(key) <= bound) cand[atomicAdd(&s_nc, 1)] = key;
-          }
-          __syncthreads();
-          const int nr = s_nc;
-          __syncthreads();
-          if (nr == 0) continue;
-          exact_rerank(cand, nr, a.X, qo, dp, dim, tid, st_rr, gsum);
-          if (tid == 0) {
-            int w = 0;
-            for (int i = 0; i < nr; ++i)
-              if (!full || cand[i] < keyr) cand[w++] = cand[i];
-            s_nc = w;
-            st_kept += unsigned(w);
-          }
-          __syncthreads();
-          merge_into(topk, topk_n, newk, cand, s_nc, K, tid);
-        }
-      }
-      t = t1;
-      off = off1;
-      fill = false;
+      merge_into(topk, topk_n, newk, cand, s_nc, K, tid);
     }
+  }
 
-    // ---- output row: ascending (dist2, id), padded with (-1, +inf)
+  // ---- store the heap, advance the cursor, queue the next round or write the result
+  for (int i = tid; i < topk_n; i += kThreads) gtop[i] = topk[i];
+  if (a.stats) {
+    if (st_kept)
+      atomicAdd(reinterpret_cast<unsigned long long*>(a.stats + int64_t(q) * 4 + 2), (unsigned long long)st_kept);
+    if (st_rr)
+      atomicAdd(reinterpret_cast<unsigned long long*>(a.stats + int64_t(q) * 4 + 3), (unsigned long long)st_rr);
+  }
+  if (tid == 0) {
+    a.q_topn[q] = topk_n;
+    a.q_kc[q] = 0;
+    const int t = cur[2], off = cur[3];
+    cur[0] = t;
+    cur[1] = off;
+    s_fin = t >= np;
+    if (t < np) {
+      const bool nfull = topk_n == K;
+      const unsigned long long nkey = nfull ? topk[K - 1] : ~0ull;
+      a.q_keyr[q] = nkey;
+      a.q_r2[q] = nfull ? key_dist(nkey) : __builtin_inff();
+      int t1, off1;
+      round_end(t, off, false, K, np, a.schedule, len_of, t1, off1);
+      cur[2] = t1;
+      cur[3] = off1;
+      queue_items(a, buf_out, q, t, off, t1, off1, len_of, pos_of);
+    }
+  }
+  __syncthreads();
+  if (s_fin) {
     for (int j = tid; j < a.k_max; j += kThreads) {
-      const int64_t o = int64_t(qi) * a.k_max + j;
+      const int64_t o = int64_t(q) * a.k_max + j;
       if (j < topk_n) {
         a.out_ids[o] = int64_t(key_id(topk[j]));
         a.out_d2[o] = key_dist(topk[j]);
@@ -658,44 +633,63 @@ __global__ __launch_bounds__(kThreads, 4) void scan_kernel(ScanArgs a) {
         a.out_d2[o] = __builtin_inff();
       }
     }
-    if (a.stats) {
-      atomicAdd(&s_stat[0], (unsigned long long)st_dco);
-      atomicAdd(&s_stat[1], (unsigned long long)st_dims);
-      atomicAdd(&s_stat[2], (unsigned long long)st_kept);
-      atomicAdd(&s_stat[3], (unsigned long long)st_rr);
-      __syncthreads();
-      if (tid < 4) a.stats[int64_t(qi) * 4 + tid] = int64_t(s_stat[tid]);
-    }
-    __syncthreads();
   }
 }
 
 template <typename ST, bool DADE, bool RERANK>
-hipError_t launch_typed(const ScanArgs& a, hipStream_t s) {
-  const int ntests = (a.dim - 1) / a.delta_d;
-  const size_t lds = sizeof(float) * (size_t(RERANK ? 2 : 1) * a.dp + size_t(ntests > 0 ? ntests : 1));
-  const bool per_dim = DADE && (a.delta_d % 8 != 0);
-  if (per_dim)
-    hipLaunchKernelGGL((scan_kernel<ST, DADE, RERANK, true>), dim3(a.grid), dim3(kThreads), lds, s, a);
+hipError_t launch_round_typed(const RoundArgs& a, int buf, hipStream_t s) {
+  if (DADE && a.delta_d % 8 != 0)
+    hipLaunchKernelGGL((scan_round_kernel<ST, DADE, RERANK, true>), dim3(a.grid), dim3(kThreads), 0, s, a, buf);
   else
-    hipLaunchKernelGGL((scan_kernel<ST, DADE, RERANK, false>), dim3(a.grid), dim3(kThreads), lds, s, a);
+    hipLaunchKernelGGL((scan_round_kernel<ST, DADE, RERANK, false>), dim3(a.grid), dim3(kThreads), 0, s, a, buf);
   return hipGetLastError();
 }
 
-template <typename ST>
-hipError_t launch_mode(const ScanArgs& a, int mode, bool rerank, hipStream_t s) {
-  if (mode == 0)
-    return rerank ? launch_typed<ST, true, true>(a, s) : launch_typed<ST, true, false>(a, s);
-  return rerank ? launch_typed<ST, false, true>(a, s) : launch_typed<ST, false, false>(a, s);
+template <typename ST, bool RERANK>
+hipError_t launch_round_mode(const RoundArgs& a, int buf, hipStream_t s) {
+  return a.mode == 0 ? launch_round_typed<ST, true, RERANK>(a, buf, s)
+                     : launch_round_typed<ST, false, RERANK>(a, buf, s);
 }
 
 }  // namespace
 
-hipError_t launch_scan(const ScanArgs& a, int dtype, int mode, hipStream_t s) {
+hipError_t launch_round(const RoundArgs& a, int buf, hipStream_t s) {
   if (a.nq == 0) return hipSuccess;
-  if (dtype == 0) return launch_mode<float>(a, mode, false, s);
-  if (dtype == 1) return launch_mode<__hip_bfloat16>(a, mode, true, s);
-  return launch_mode<__half>(a, mode, true, s);
+  if (a.dtype == 0) return launch_round_mode<float, false>(a, buf, s);
+  if (a.dtype == 1) return launch_round_mode<__hip_bfloat16, true>(a, buf, s);
+  return launch_round_mode<__half, true>(a, buf, s);
+}
+
+int round_blocks_per_cu(int dtype, int mode, int delta_d) {
+  int n = 0;
+  hipError_t e = hipSuccess;
+  const bool pd = mode == 0 && delta_d % 8 != 0;
+#define DADE_OCC(ST, D, R, P) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, scan_round_kernel<ST, D, R, P>, kThreads, 0)
+  if (dtype == 0) {
+    if (mode != 0) DADE_OCC(float, false, false, false);
+    else if (pd) DADE_OCC(float, true, false, true);
+    else DADE_OCC(float, true, false, false);
+  } else if (dtype == 1) {
+    if (mode != 0) DADE_OCC(__hip_bfloat16, false, true, false);
+    else if (pd) DADE_OCC(__hip_bfloat16, true, true, true);
+    else DADE_OCC(__hip_bfloat16, true, true, false);
+  } else {
+    if (mode != 0) DADE_OCC(__half, false, true, false);
+    else if (pd) DADE_OCC(__half, true, true, true);
+    else DADE_OCC(__half, true, true, false);
+  }
+#undef DADE_OCC
+  return (e == hipSuccess && n > 0) ? n : 1;
+}
+
+hipError_t launch_merge(const RoundArgs& a, int buf_out, int init, hipStream_t s) {
+  if (a.nq == 0) return hipSuccess;
+  const size_t lds = a.dtype == 0 ? 0 : sizeof(float) * size_t(a.dp);
+  if (a.dtype == 0)
+    hipLaunchKernelGGL((merge_round_kernel<false>), dim3(a.nq), dim3(kThreads), lds, s, a, buf_out, init);
+  else
+    hipLaunchKernelGGL((merge_round_kernel<true>), dim3(a.nq), dim3(kThreads), lds, s, a, buf_out, init);
+  return hipGetLastError();
 }
 
 }  // namespace dade
