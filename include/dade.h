@@ -54,10 +54,13 @@ typedef enum { DADE_F32 = 0, DADE_BF16 = 1, DADE_F16 = 2 } dade_dtype;
 typedef enum { DADE_MODE_DADE = 0, DADE_MODE_FULL_D = 1 } dade_mode;
 
 /* Which heap state each DCO's threshold r comes from (the paper's IVF updates the heap after
- * every candidate, which makes a parallel scan order-dependent).  The probe ranks of a query
- * are split into rounds; every DCO of a round sees the heap as it was when the round started;
- * the round's accepted candidates are merged at its end.  PER_RANK: one probed list per
- * round.  DOUBLING: rank boundaries 0, 1, 2, 4, 8, ... */
+ * every candidate, which makes a parallel scan order-dependent).  A query's candidate
+ * sequence (its probed lists in probe order) is split into rounds; every DCO of a round sees
+ * the heap as it was when the round started; the round's accepted candidates are merged at its
+ * end.  The first round holds the first max(K, fill_min) candidates.  A later round ends at the
+ * next probe-rank boundary of the schedule -- PER_RANK: every rank; DOUBLING: ranks 1, 2, 4,
+ * 8, ... -- or once it holds growth times the candidates scanned before it, whichever comes
+ * first (growth 0: no such cap). */
 typedef enum { DADE_SCHED_PER_RANK = 0, DADE_SCHED_DOUBLING = 1 } dade_schedule;
 
 /* Index state machine: BUILT -> ROTATED -> CALIBRATED. */
@@ -84,6 +87,12 @@ typedef struct {
                                  read (sum of the d at which each DCO ended), candidates kept,
                                  candidates reranked */
   int32_t record_times;       /* nonzero: time the stages with HIP events (dade_stage_times) */
+  int32_t fill_min;           /* >= 0: the first round holds at least this many candidates */
+  int32_t growth;             /* >= 0: cap on a later round's size, as a multiple of the
+                                 candidates scanned before it; 0 means no cap */
+  int32_t use_graph;          /* nonzero: the list scan's kernel sequence is captured once into
+                                 a HIP graph and replayed while the arguments (pointers, sizes,
+                                 options) stay the same; results are identical either way */
 } dade_search_opts;
 
 /* Host copies of an index's artifacts (for checkpoints and for parity checks).  All arrays
@@ -150,13 +159,20 @@ int dade_calibrate(dade_index* ix, double alpha, const int64_t* pairs, int64_t n
  * Outputs: out_ids (device int64 [nq x k]) and out_dist2 (device FP32 [nq x k]), each row
  * ascending by (squared distance, id), padded with (-1, +inf) after the query's K results.
  * Requires state CALIBRATED for DADE mode and >= ROTATED for FULL_D; 1 <= k <= 128;
- * nprobe >= 1; nq >= 0 (nq == 0 is a no-op).  opts may be NULL (defaults).
+ * nprobe >= 1; nq >= 0 (nq == 0 is a no-op).  opts may be NULL: delta_d 32, DADE mode,
+ * PER_RANK, the calibrated rerank_delta, no stats or timing, fill_min 32, growth 4, graph.
  * Asynchronous on `stream`.
  */
 int dade_search(dade_index* ix, const float* Q, int64_t nq, int32_t k, int32_t nprobe,
                 const int32_t* k_per_query, const int32_t* nprobe_per_query,
                 const dade_search_opts* opts, int64_t* out_ids, float* out_dist2,
                 void* stream);
+
+/* dade_check -- synchronises `stream` and reports DADE_EDEVICE if any search on this index
+ * since its creation exceeded an internal capacity of the list scan (its results would be
+ * incomplete); DADE_OK otherwise.  The capacities are sized so that this does not happen; the
+ * call exists so that tests and callers can assert it. */
+int dade_check(dade_index* ix, void* stream);
 
 /* dade_index_info -- sizes and state (any pointer may be NULL). */
 int dade_index_info(const dade_index* ix, int64_t* n, int32_t* dim, int32_t* nlist,

@@ -177,18 +177,34 @@ def round_bounds(nprobe: int, schedule: str):
     raise ValueError(schedule)
 
 
-def round_starts(sizes, K: int, schedule: str) -> list:
+# Round-size defaults shared with the GPU path's search options (they are part of what a
+# search computes, so both sides take them as parameters).
+FILL_MIN = 32   # the first round holds at least this many candidates
+GROWTH = 4      # a later round holds at most GROWTH times the candidates before it
+
+
+def round_starts(sizes, K: int, schedule: str, fill_min: int = FILL_MIN, growth: int = GROWTH) -> list:
     """Round boundaries in the candidate sequence (probed lists concatenated in probe order).
 
-    The first round holds the first K candidates (they fill the heap, as the paper's IVF fills
-    its max-heap before any comparison can fail); later rounds end where the schedule's probe
-    ranks end (``round_bounds``).  Returns sorted positions 0 = b_0 < b_1 < ... = total.
+    The first round holds the first max(K, fill_min) candidates: they fill the heap, as the
+    paper's IVF fills its max-heap before any comparison can fail (a larger first round gives
+    the following rounds a tighter r).  A later round that starts after s candidates ends at the
+    first schedule cut after s (``round_bounds``: where the schedule's probe ranks end) or after
+    growth * s candidates if that comes first (growth = 0: no such cap).  Returns the positions
+    0 = b_0 < b_1 < ... = total.
     """
     ends = np.cumsum(sizes)
     total = int(ends[-1]) if len(ends) else 0
-    fill = min(K, total)
-    cut = [int(ends[hi - 1]) for _, hi in round_bounds(len(sizes), schedule)]
-    return sorted(set([0, fill, total] + [c for c in cut if c > fill]))
+    pos = min(max(K, fill_min), total)
+    cuts = sorted(set([int(ends[hi - 1]) for _, hi in round_bounds(len(sizes), schedule)] + [total]))
+    out = [0] + ([pos] if pos > 0 else [])
+    while pos < total:
+        nxt = min(c for c in cuts if c > pos)
+        if growth > 0:
+            nxt = min(nxt, pos + growth * pos)
+        out.append(nxt)
+        pos = nxt
+    return out
 
 
 def tested_dims(D: int, delta_d: int) -> np.ndarray:
@@ -291,8 +307,9 @@ def _scan_round(index, q, cand, hd, hi, K, delta_d, mode, tests):
 
 
 def search(index: Index, Q, K, nprobe, delta_d: int, mode: str = "dade",
-           schedule: str = "per_rank", log: bool = False, q_rot=None):
-    """IVF search.  K and nprobe are ints or per-query arrays.
+           schedule: str = "per_rank", log: bool = False, q_rot=None,
+           fill_min: int = FILL_MIN, growth: int = GROWTH):
+    """IVF search.  K and nprobe are ints or per-query arrays; rounds follow ``round_starts``.
 
     Returns (ids [nq, Kmax] int64 with -1 padding, dist2 [nq, Kmax] with +inf padding, logs).
     ``logs`` (when requested) holds per-query: dcos, dims (sum of d_exit), accepted,
@@ -327,7 +344,7 @@ def search(index: Index, Q, K, nprobe, delta_d: int, mode: str = "dade",
         if schedule == "sequential":
             rounds = [seq[i:i + 1] for i in range(len(seq))]
         else:
-            b = round_starts(np.array([len(x) for x in lists]), Kq, schedule)
+            b = round_starts(np.array([len(x) for x in lists]), Kq, schedule, fill_min, growth)
             rounds = [seq[b0:b1] for b0, b1 in zip(b[:-1], b[1:])]
         hd = np.zeros(0)
         hi = np.zeros(0, dtype=np.int64)

@@ -80,14 +80,27 @@ struct dade_index {
   unsigned long long* w_topk = nullptr; int64_t w_topk_n = 0;
   unsigned long long* w_keyr = nullptr; int64_t w_keyr_n = 0;
   float* w_r2 = nullptr; int64_t w_r2_n = 0;
-  int* w_qint = nullptr; int64_t w_qint_n = 0;      // q_topn, q_kc, q_cur (6 per query)
+  int* w_qint = nullptr; int64_t w_qint_n = 0;      // q_topn, q_kc, q_rounds
   unsigned long long* w_kb = nullptr; int64_t w_kb_n = 0;
-  int4* w_items = nullptr; int64_t w_items_n = 0;   // two buffers
-  int* w_counter = nullptr; int64_t w_counter_n = 0;  // n_items[2], overflow
+  int4* w_items = nullptr; int64_t w_items_n = 0;   // per group and round
+  int* w_counter = nullptr; int64_t w_counter_n = 0;  // per group: n_items[rounds]
+  int* w_counts = nullptr; int64_t w_counts_n = 0;    // per round and query: item counts / offsets
+  int* w_flags = nullptr;                             // sticky: a scan capacity was exceeded
   int scan_occ[3][2][2] = {};                        // resident scan workgroups per CU
   hipEvent_t ev[4] = {};
   bool ev_made = false, ev_used = false;
   int cus = 256;
+  // query groups of a search run their rounds on their own streams (default priority), so one
+  // group's merge overlaps another group's scan
+  static constexpr int kGroups = 4;
+  int n_groups = 1;   // groups a search uses (1 .. kGroups)
+  hipStream_t grp[kGroups] = {};
+  hipStream_t cap = nullptr;   // origin stream of graph captures (the caller's may be the null stream)
+  hipEvent_t fork = nullptr, join[kGroups] = {};
+  bool grp_made = false;
+  // the last captured round-launch sequence and the argument bytes it was captured with
+  hipGraphExec_t graph_exec = nullptr;
+  std::vector<unsigned char> graph_key;
 
   std::vector<void*> owned;
 };
@@ -274,6 +287,15 @@ void dade_destroy(dade_index* ix) {
   if (!ix) return;
   (void)hipDeviceSynchronize();
   for (void* p : ix->owned) (void)hipFree(p);
+  if (ix->graph_exec) (void)hipGraphExecDestroy(ix->graph_exec);
+  if (ix->grp_made) {
+    for (int g = 1; g < dade_index::kGroups; ++g) {
+      (void)hipStreamDestroy(ix->grp[g]);
+      (void)hipEventDestroy(ix->join[g]);
+    }
+    (void)hipStreamDestroy(ix->cap);
+    (void)hipEventDestroy(ix->fork);
+  }
   if (ix->ev_made)
     for (auto& e : ix->ev) (void)hipEventDestroy(e);
   delete ix;
@@ -626,6 +648,28 @@ int dade_import(const dade_artifacts* a, const float* X, const dade_build_opts* 
   return DADE_OK;
 }
 
+// The round launches of one pass: groups on their own streams, forked from and joined to s.
+static hipError_t enqueue_rounds(dade_index* ix, const RoundArgs* ga, const hipStream_t* gs, int ng, int rounds,
+                                 int64_t gsz, hipStream_t s) {
+  hipError_t e;
+#define ENQ(x) \
+  if ((e = (x)) != hipSuccess) return e
+  if (ng > 1) ENQ(hipEventRecord(ix->fork, s));
+  for (int g = 1; g < ng; ++g) ENQ(hipStreamWaitEvent(gs[g], ix->fork, 0));
+  for (int g = 0; g < ng; ++g) ENQ(launch_plan(ga[g], ix->w_counts + int64_t(rounds) * g * gsz, gs[g]));
+  for (int r = 0; r < rounds; ++r)
+    for (int g = 0; g < ng; ++g) {
+      ENQ(launch_round(ga[g], r, gs[g]));
+      ENQ(launch_merge(ga[g], r, gs[g]));
+    }
+  for (int g = 1; g < ng; ++g) {
+    ENQ(hipEventRecord(ix->join[g], gs[g]));
+    ENQ(hipStreamWaitEvent(s, ix->join[g], 0));
+  }
+#undef ENQ
+  return hipSuccess;
+}
+
 int dade_search(dade_index* ix, const float* Q, int64_t nq, int32_t k, int32_t nprobe,
                 const int32_t* k_per_query, const int32_t* nprobe_per_query,
                 const dade_search_opts* opts, int64_t* out_ids, float* out_dist2, void* stream) {
@@ -635,7 +679,9 @@ int dade_search(dade_index* ix, const float* Q, int64_t nq, int32_t k, int32_t n
   if (nprobe < 1) FAIL(DADE_EINVAL, "nprobe must be >= 1");
   dade_search_opts o{};
   o.delta_d = 0; o.mode = DADE_MODE_DADE; o.schedule = DADE_SCHED_PER_RANK; o.rerank_delta = -1.f;
+  o.fill_min = 32; o.growth = 4; o.use_graph = 1;
   if (opts) o = *opts;
+  if (o.fill_min < 0 || o.growth < 0) FAIL(DADE_EINVAL, "fill_min and growth must be >= 0");
   const int dd = o.delta_d > 0 ? o.delta_d : std::min(32, ix->dim);
   if (dd < 1 || dd > ix->dim) FAIL(DADE_EINVAL, "delta_d must be in [1, dim]");
   if (o.mode != DADE_MODE_DADE && o.mode != DADE_MODE_FULL_D) FAIL(DADE_EINVAL, "bad mode");
@@ -661,15 +707,24 @@ int dade_search(dade_index* ix, const float* Q, int64_t nq, int32_t k, int32_t n
   if (o.schedule == DADE_SCHED_DOUBLING) {
     int b = 1, nb = 0;
     while (b < npm) { widest = std::max(widest, std::min(2 * b, npm) - b); b *= 2; ++nb; }
-    rounds = nb + 3;
+    rounds = nb + 2;
   }
-  int64_t kb_cap = 0;
+  int64_t kb_cap = 0, most = 0;   // most: the largest candidate count a query can have
   for (int i = 0; i < widest && i < nl; ++i) kb_cap += sizes[i];
-  kb_cap = std::max<int64_t>(kb_cap, k);
-  const int64_t items_pq = std::max<int64_t>((kb_cap + 63) / 64 + widest + 1, (k + 63) / 64 + npm);
-  // queries per pass: the round workspace stays under 1 GiB
-  const int64_t per_q = kb_cap * 8 + 2 * items_pq * 16 + int64_t(k) * 8 + 48;
+  for (int i = 0; i < npm; ++i) most += sizes[i];
+  const int64_t first = std::max<int64_t>(k, o.fill_min);
+  kb_cap = std::max<int64_t>(kb_cap, std::min(first, most));
+  if (o.growth > 0)   // rounds cut short by the growth cap: positions grow by 1 + growth each
+    for (int64_t p = std::max<int64_t>(1, std::min<int64_t>(o.fill_min, most)); p < most; p *= 1 + o.growth) ++rounds;
+  // work items of one query in one round: its segments cut at 16 candidates (whole-row rounds;
+  // other rounds use 64)
+  const int64_t items_pq = std::max<int64_t>((kb_cap + 15) / 16 + widest + 1, (first + 15) / 16 + npm);
+  // queries per pass: the round workspace stays under 1 GiB; a pass is split into groups
+  const int64_t per_q = kb_cap * 8 + rounds * (items_pq * 16 + 4) + int64_t(k) * 8 + 48;
   const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(nq, (int64_t(1) << 30) / per_q));
+  const int groups = int(std::min<int64_t>(ix->n_groups, chunk));
+  const int64_t gsz = (chunk + groups - 1) / groups;
+  const int cstride = (rounds + 63) / 64 * 64;   // per group: n_items[rounds]
   // workspace
   if (nq > ix->w_nq || npm > ix->w_np) {
     const int64_t new_nq = std::max(nq, ix->w_nq), new_np = std::max<int64_t>(npm, ix->w_np);
@@ -687,11 +742,25 @@ int dade_search(dade_index* ix, const float* Q, int64_t nq, int32_t k, int32_t n
     ix->w_nq = new_nq; ix->w_np = new_np;
   }
   if ((rc = grow(ix, &ix->w_topk, ix->w_topk_n, chunk * k, s)) || (rc = grow(ix, &ix->w_keyr, ix->w_keyr_n, chunk, s)) ||
-      (rc = grow(ix, &ix->w_r2, ix->w_r2_n, chunk, s)) || (rc = grow(ix, &ix->w_qint, ix->w_qint_n, chunk * 6, s)) ||
+      (rc = grow(ix, &ix->w_r2, ix->w_r2_n, chunk, s)) || (rc = grow(ix, &ix->w_qint, ix->w_qint_n, chunk * 3, s)) ||
       (rc = grow(ix, &ix->w_kb, ix->w_kb_n, chunk * kb_cap, s)) ||
-      (rc = grow(ix, &ix->w_items, ix->w_items_n, 2 * chunk * items_pq, s)) ||
-      (rc = grow(ix, &ix->w_counter, ix->w_counter_n, 3, s)))
+      (rc = grow(ix, &ix->w_items, ix->w_items_n, int64_t(rounds) * groups * gsz * items_pq, s)) ||
+      (rc = grow(ix, &ix->w_counter, ix->w_counter_n, int64_t(cstride) * groups, s)) ||
+      (rc = grow(ix, &ix->w_counts, ix->w_counts_n, int64_t(rounds) * groups * gsz, s)))
     return rc;
+  if (!ix->w_flags) {
+    if ((rc = alloc_t(ix, &ix->w_flags, 1))) return rc;
+    HIPC(launch_fill_i32(ix->w_flags, 1, 0, s));
+  }
+  if (!ix->grp_made) {
+    HIPC(hipEventCreateWithFlags(&ix->fork, hipEventDisableTiming));
+    for (int g = 1; g < dade_index::kGroups; ++g) {
+      HIPC(hipStreamCreateWithFlags(&ix->grp[g], hipStreamNonBlocking));
+      HIPC(hipEventCreateWithFlags(&ix->join[g], hipEventDisableTiming));
+    }
+    HIPC(hipStreamCreateWithFlags(&ix->cap, hipStreamNonBlocking));
+    ix->grp_made = true;
+  }
   int& occ = ix->scan_occ[ix->store][o.mode][dd % 8 != 0];
   if (occ == 0) occ = round_blocks_per_cu(ix->store, o.mode, dd);
   if (o.record_times && !ix->ev_made) {
@@ -717,7 +786,9 @@ int dade_search(dade_index* ix, const float* Q, int64_t nq, int32_t k, int32_t n
   if (o.record_times) HIPC(hipEventRecord(ix->ev[2], s));
   // a3-a6: the list scan, in rounds, `chunk` queries at a time
   RoundArgs ra;
+  std::memset(&ra, 0, sizeof ra);   // zero padding: argument blocks are compared bytewise
   ra.dim = ix->dim; ra.dp = dp; ra.delta_d = dd; ra.schedule = o.schedule;
+  ra.fill_min = o.fill_min; ra.growth = o.growth;
   ra.mode = o.mode == DADE_MODE_DADE ? 0 : 1; ra.dtype = ix->store;
   ra.k_max = k; ra.nprobe_max = npm;
   ra.list_off = ix->d_off;
@@ -726,33 +797,83 @@ int dade_search(dade_index* ix, const float* Q, int64_t nq, int32_t k, int32_t n
   ra.ids = ix->d_ids; ra.X = ix->X; ra.T = ix->d_T;
   ra.rerank_delta = o.rerank_delta >= 0.f ? o.rerank_delta : float(ix->delta);
   ra.kb_cap = kb_cap;
-  ra.items_cap = int(std::min<int64_t>(chunk * items_pq, INT32_MAX));
-  ra.n_items = ix->w_counter; ra.overflow = ix->w_counter + 2;
+  ra.rounds = rounds;
   ra.grid = ix->cus * occ;
+  RoundArgs ga[dade_index::kGroups];
+  hipStream_t gstream[dade_index::kGroups];
   for (int64_t c0 = 0; c0 < nq; c0 += chunk) {
     const int64_t cn = std::min(chunk, nq - c0);
-    ra.nq = int(cn);
-    ra.k_pq = k_per_query ? k_per_query + c0 : nullptr;
-    ra.nprobe_pq = nprobe_per_query ? nprobe_per_query + c0 : nullptr;
-    ra.qrot = ix->w_qrot + c0 * dp; ra.qorig = ix->w_qpad + c0 * dp;
-    ra.probes = ix->w_probes + c0 * npm;
-    ra.out_ids = out_ids + c0 * k; ra.out_d2 = out_dist2 + c0 * k;
-    ra.stats = o.stats ? o.stats + c0 * 4 : nullptr;
-    ra.q_topk = ix->w_topk; ra.q_keyr = ix->w_keyr; ra.q_r2 = ix->w_r2;
-    ra.q_topn = ix->w_qint; ra.q_kc = ix->w_qint + cn; ra.q_cur = ix->w_qint + 2 * cn;
-    ra.kb = ix->w_kb;
-    ra.items[0] = ix->w_items; ra.items[1] = ix->w_items + chunk * items_pq;
-    HIPC(launch_fill_i32(ix->w_counter, 3, 0, s));
-    HIPC(launch_merge(ra, 0, 1, s));
-    for (int r = 0; r < rounds; ++r) {
-      HIPC(launch_round(ra, r & 1, s));
-      HIPC(launch_merge(ra, (r + 1) & 1, 0, s));
+    int ng = 0;
+    for (int g = 0; g < groups; ++g) {
+      const int64_t g0 = std::min(cn, g * gsz), gn = std::min(cn, g0 + gsz) - g0;
+      if (gn <= 0) continue;
+      RoundArgs& a = ga[ng];
+      std::memcpy(&a, &ra, sizeof ra);
+      const int64_t q0 = c0 + g0;
+      a.nq = int(gn);
+      a.k_pq = k_per_query ? k_per_query + q0 : nullptr;
+      a.nprobe_pq = nprobe_per_query ? nprobe_per_query + q0 : nullptr;
+      a.qrot = ix->w_qrot + q0 * dp; a.qorig = ix->w_qpad + q0 * dp;
+      a.probes = ix->w_probes + q0 * npm;
+      a.out_ids = out_ids + q0 * k; a.out_d2 = out_dist2 + q0 * k;
+      a.stats = o.stats ? o.stats + q0 * 4 : nullptr;
+      a.q_topk = ix->w_topk + g0 * k; a.q_keyr = ix->w_keyr + g0; a.q_r2 = ix->w_r2 + g0;
+      a.q_topn = ix->w_qint + 3 * g0; a.q_kc = a.q_topn + gn; a.q_rounds = a.q_topn + 2 * gn;
+      a.kb = ix->w_kb + g0 * kb_cap;
+      a.items_cap = int(std::min<int64_t>(gsz * items_pq, INT32_MAX));
+      a.items = ix->w_items + int64_t(rounds) * g * a.items_cap;
+      a.n_items = ix->w_counter + int64_t(cstride) * g; a.overflow = ix->w_flags;
+      gstream[ng] = ng == 0 ? s : ix->grp[ng];
+      ++ng;
     }
+    // the launch sequence of this pass; replayed from a captured graph when it is the same as
+    // the last captured one (a whole batch in one pass)
+    const bool graph = o.use_graph && chunk >= nq;
+    std::vector<unsigned char> key;
+    if (graph) {
+      key.resize(sizeof(RoundArgs) * ng + 3 * sizeof(int));
+      std::memcpy(key.data(), ga, sizeof(RoundArgs) * ng);
+      const int tail[3] = {ng, rounds, ix->device};
+      std::memcpy(key.data() + sizeof(RoundArgs) * ng, tail, sizeof tail);
+      if (ix->graph_exec && key == ix->graph_key) {
+        HIPC(hipGraphLaunch(ix->graph_exec, s));
+        continue;
+      }
+      gstream[0] = ix->cap;
+      HIPC(hipStreamBeginCapture(ix->cap, hipStreamCaptureModeRelaxed));
+    }
+    hipError_t e = enqueue_rounds(ix, ga, gstream, ng, rounds, gsz, gstream[0]);
+    if (graph) {
+      hipGraph_t g = nullptr;
+      const hipError_t e2 = hipStreamEndCapture(ix->cap, &g);
+      if (e == hipSuccess) e = e2;
+      hipGraphExec_t x = nullptr;
+      if (e == hipSuccess) e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+      if (g) (void)hipGraphDestroy(g);
+      if (e == hipSuccess) {
+        if (ix->graph_exec) (void)hipGraphExecDestroy(ix->graph_exec);
+        ix->graph_exec = x;
+        ix->graph_key.swap(key);
+        e = hipGraphLaunch(ix->graph_exec, s);
+      }
+    }
+    if (e != hipSuccess) FAIL(DADE_EDEVICE, hip_msg(e, "list scan launch"));
   }
   if (o.record_times) {
     HIPC(hipEventRecord(ix->ev[3], s));
     ix->ev_used = true;
   }
+  return DADE_OK;
+}
+
+int dade_check(dade_index* ix, void* stream) {
+  if (!ix) FAIL(DADE_EINVAL, "index is NULL");
+  if (!ix->w_flags) return DADE_OK;
+  int f = 0;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  HIPC(hipMemcpyAsync(&f, ix->w_flags, sizeof f, hipMemcpyDeviceToHost, s));
+  HIPC(hipStreamSynchronize(s));
+  if (f) FAIL(DADE_EDEVICE, "a list-scan capacity was exceeded (flags " + std::to_string(f) + ")");
   return DADE_OK;
 }
 

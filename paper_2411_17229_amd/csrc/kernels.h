@@ -81,19 +81,22 @@ hipError_t launch_select_probes(const float* pd, int ld_pd, const float* qrot, i
                                 hipStream_t s);
 
 // ---------------------------------------------------------------- the list scan (scan.hip)
-// ---------------------------------------------------------------- the list scan (scan.hip)
-// One search runs as rounds (see scan.hip): launch_merge(init) queues every query's first
-// round; then per round launch_round (the DCOs) and launch_merge (heap update, next round).
+// One search runs as rounds (see scan.hip): launch_plan lays out every query's work items for
+// all of its rounds; then, for r = 0 .. rounds - 1, launch_round (the DCOs of round r) and
+// launch_merge (round r's heap update; a query's result after its last round).
 struct RoundArgs {
   int nq = 0;
   int dim = 0;          // real dimensionality D
   int dp = 0;           // padded row length of stored coordinates
   int delta_d = 32;
   int schedule = 0;     // 0 per-rank, 1 doubling
+  int fill_min = 32;    // the first round holds at least this many candidates
+  int growth = 4;       // a later round holds at most growth x the candidates before it (0: any)
   int mode = 0;         // 0 DADE, 1 FULL_D
   int dtype = 0;        // stored coordinates: 0 f32, 1 bf16, 2 f16
   int k_max = 0;
   int nprobe_max = 0;
+  int rounds = 0;       // rounds launched (an upper bound on any query's round count)
   const int32_t* k_pq = nullptr;
   const int32_t* nprobe_pq = nullptr;
   const float* qrot = nullptr;      // [nq x dp] rotated queries
@@ -109,26 +112,27 @@ struct RoundArgs {
   int64_t* out_ids = nullptr;
   float* out_d2 = nullptr;
   int64_t* stats = nullptr;
-  // per-query round state
+  // per-query state
   unsigned long long* q_topk = nullptr;  // [nq x k_max] heap keys, ascending
   int* q_topn = nullptr;                 // [nq] heap size
   unsigned long long* q_keyr = nullptr;  // [nq] K-th key at the round's start (~0: not full)
   float* q_r2 = nullptr;                 // [nq] r^2 at the round's start (inf: not full)
-  int* q_cur = nullptr;                  // [nq x 4] round start (rank, offset), end (rank, offset)
-  int* q_kc = nullptr;                   // [nq] keys queued in the round
+  int* q_kc = nullptr;                   // [nq] keys queued in the current round
+  int* q_rounds = nullptr;               // [nq] the query's round count
   unsigned long long* kb = nullptr;      // [nq x kb_cap] queued keys
   int64_t kb_cap = 0;
-  // work items of the current and the next round: {query, count, first packed position, 0}
-  int4* items[2] = {nullptr, nullptr};
+  // work items {query, count, first packed position, 0}: round r's in items[r * items_cap ...]
+  int4* items = nullptr;
   int items_cap = 0;
-  int* n_items = nullptr;   // [2]
+  int* n_items = nullptr;   // [rounds]
   int* overflow = nullptr;  // [1] nonzero if a capacity was exceeded
   int grid = 0;
 };
-hipError_t launch_round(const RoundArgs& a, int buf, hipStream_t s);
+// counts: device scratch of rounds x nq ints.
+hipError_t launch_plan(const RoundArgs& a, int* counts, hipStream_t s);
+hipError_t launch_round(const RoundArgs& a, int r, hipStream_t s);
+hipError_t launch_merge(const RoundArgs& a, int r, hipStream_t s);
 // Resident scan_round workgroups per CU for a store type / mode / Delta_d.
 int round_blocks_per_cu(int dtype, int mode, int delta_d);
-// init != 0: set up every query's state and queue its first round into buffer 0.
-hipError_t launch_merge(const RoundArgs& a, int buf_out, int init, hipStream_t s);
 
 }  // namespace dade

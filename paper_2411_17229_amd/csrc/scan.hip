@@ -3,8 +3,9 @@
 // FP32 rerank of the survivors.
 //
 // Rounds.  A query's candidate sequence (its probed lists in probe order) is cut into rounds:
-// the first round is its first K candidates (they fill the heap), later rounds end where the
-// schedule's probe ranks end (every rank, or ranks 1, 2, 4, 8, ...).  Every DCO of a round sees
+// the first round is its first max(K, fill_min) candidates (they fill the heap), later rounds
+// end where the schedule's probe ranks end (every rank, or ranks 1, 2, 4, 8, ...) or once they
+// hold growth times the candidates scanned before them.  Every DCO of a round sees
 // the query's heap as it was when the round started (r^2 and the thresholds T_d r^2 are a
 // snapshot), and the round's kept candidates are merged at its end.  Queries never interact, so
 // a query's result does not depend on the batch or on how the work is spread over the GPU.
@@ -37,6 +38,7 @@ constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
 constexpr int kStack = 128;        // deep-stack entries per wave (at most 127 are live)
 constexpr int kItem = 64;          // candidates per work item
+constexpr int kDenseItem = 16;     // candidates per work item of a whole-row round
 constexpr int kMergeChunk = 512;   // queued keys handled per LDS pass of the merge
 constexpr int kBlock = kHead;      // coordinates per block; block 0 is the head
 constexpr int kGroup = 16;         // lanes per candidate in the exact rerank
@@ -190,10 +192,80 @@ __device__ inline void put_key(const RoundArgs& a, int q, int slot, unsigned lon
   else atomicOr(a.overflow, 1);
 }
 
+// Wave-wide: queue key (S, rid) of query q on lanes with `queue` set (one atomic per wave).
+__device__ inline void append_keys(const RoundArgs& a, int q, bool queue, unsigned long long key, int lane) {
+  const unsigned long long m = __ballot(queue);
+  if (!m) return;
+  int slot = 0;
+  if (lane == 0) slot = atomicAdd(a.q_kc + q, __popcll(m));
+  slot = __shfl(slot, 0);
+  if (queue) put_key(a, q, slot + lanes_below(m), key);
+}
+
+// Wave-wide: DCO counts and dimensions read by the lanes with `fin` set, added to query q's stats.
+__device__ inline void add_stats(const RoundArgs& a, int q, bool fin, int dexit, int lane) {
+  unsigned nd = fin ? 1u : 0u, ds = fin ? unsigned(dexit) : 0u;
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    nd += __shfl_xor(nd, o, 64);
+    ds += __shfl_xor(ds, o, 64);
+  }
+  if (lane == 0 && nd) {
+    atomicAdd(reinterpret_cast<unsigned long long*>(a.stats + int64_t(q) * 4 + 0), (unsigned long long)nd);
+    atomicAdd(reinterpret_cast<unsigned long long*>(a.stats + int64_t(q) * 4 + 1), (unsigned long long)ds);
+  }
+}
+
+// Wave-wide: whole-row distances of a small item's candidates (no test can reject them).  Four
+// lanes per candidate, 16 candidates per pass; lane j of a quad sums blocks j, j + 4, j + 8, ...
+// in order, and the quad's partials combine as (P0 + P1) + (P2 + P3).
+template <typename ST, bool RERANK>
+__device__ void dense_item(const RoundArgs& a, const Rows& rows, int q, int cnt, int p0, const float* qv,
+                           bool full, unsigned long long keyr, float gate, int nblk, int lane) {
+  using SS = Store<ST>;
+  constexpr int MB = SS::kMaxB;
+  const int dim = a.dim;
+  const int quad = lane >> 2, ql = lane & 3;
+  for (int c0 = 0; c0 < cnt; c0 += 16) {
+    const int ci = c0 + quad;
+    const bool hv = ci < cnt;
+    const int64_t p = p0 + (hv ? ci : 0);
+    const bool lead = hv && ql == 0;
+    const uint32_t rid = lead ? uint32_t(a.ids[p]) : 0u;
+    float part = 0.f;
+    for (int b0 = 0; b0 < nblk; b0 += 4 * MB) {
+      typename SS::Block blk[MB];
+#pragma unroll
+      for (int i = 0; i < MB; ++i) {
+        const int bi = b0 + ql + 4 * i;
+        blk[i] = SS::load(rows, p, bi < nblk ? bi : nblk - 1);
+      }
+#pragma unroll
+      for (int i = 0; i < MB; ++i) {
+        const int bi = b0 + ql + 4 * i;
+#pragma unroll
+        for (int j = 0; j < kBlock / 8; ++j) {
+          const int d0 = bi * kBlock + 8 * j;
+          if (bi < nblk && d0 < dim) {
+            float v[8], qq[8];
+            SS::unit(blk[i], j, v);
+            q8(qv, d0, qq);
+            part = part + unit_sum(qq, v);
+          }
+        }
+      }
+    }
+    const float pair = part + __shfl_xor(part, 1, 64);
+    const float S = pair + __shfl_xor(pair, 2, 64);
+    append_keys(a, q, lead && passes<RERANK>(S, rid, full, keyr, gate), make_key(S, rid), lane);
+    if (a.stats) add_stats(a, q, lead, dim, lane);
+  }
+}
+
 // ------------------------------------------------------------------------------------------------
 // scan_round: the DCOs of one round for every query.
 template <typename ST, bool DADE, bool RERANK, bool PER_DIM>
-__global__ __launch_bounds__(kThreads) void scan_round_kernel(RoundArgs a, int buf) {
+__global__ __launch_bounds__(kThreads) void scan_round_kernel(RoundArgs a, int r) {
   using SS = Store<ST>;
   constexpr int MB = SS::kMaxB;
   __shared__ int4 stack_lds[kWaves][kStack];
@@ -207,10 +279,9 @@ __global__ __launch_bounds__(kThreads) void scan_round_kernel(RoundArgs a, int b
   nb0 = nb0 > nblk ? nblk : nb0;
   const bool any_tests = DADE && dd < dim;
   const Rows rows{a.head, a.tail, dp - kBlock};
-  const int n_queued = a.n_items[buf];
+  const int n_queued = a.n_items[r];
   const int n_items = n_queued < a.items_cap ? n_queued : a.items_cap;
-  const int4* items = a.items[buf];
-  if (blockIdx.x == 0 && threadIdx.x == 0) a.n_items[buf ^ 1] = 0;   // the merge refills it
+  const int4* items = a.items + int64_t(r) * a.items_cap;
   const float gate_f = 1.f + a.rerank_delta;
   // Workgroup g owns items g, g + grid, g + 2 grid, ... (a query's items are spread over the
   // grid); its waves take them in turn from an LDS counter, so claims need no global atomics.
@@ -278,14 +349,20 @@ __global__ __launch_bounds__(kThreads) void scan_round_kernel(RoundArgs a, int b
     const unsigned long long keyr = a.q_keyr[q];
     const bool full = keyr != ~0ull;
     const float* qv = a.qrot + int64_t(q) * dp;
+    const bool dense = !any_tests || !full;   // no test can reject: whole rows
+    if (dense && cnt <= 16) {
+      // few candidates (the rounds that fill the heap): four lanes per row
+      dense_item<ST, RERANK>(a, rows, q, cnt, it.z, qv, full, keyr, gate_f * r2, nblk, lane);
+      continue;
+    }
     const bool has = lane < cnt;
     const int p = it.z + (has ? lane : 0);
     const uint32_t rid = uint32_t(a.ids[p]);
     float S = 0.f;
     bool rej = false, done = true;
     int dexit = dim;
-    if (!any_tests || !full) {
-      // whole rows: no test can reject (heap not full, FDScanning, or no d below D to test)
+    if (dense) {
+      // one lane per row (FDScanning, or no d below D to test)
       if (has)
         for (int b = 0; b < nblk; b += MB)
           advance<ST, false, MB>(rows, p, qv, r2, a.T, dim, dd, false, b, nblk - b < MB ? nblk - b : MB, S,
@@ -299,26 +376,8 @@ __global__ __launch_bounds__(kThreads) void scan_round_kernel(RoundArgs a, int b
       done = rej || nb0 >= nblk;
     }
     const bool fin = has && done;
-    const bool queue = fin && !rej && passes<RERANK>(S, rid, full, keyr, gate_f * r2);
-    const unsigned long long mq = __ballot(queue);
-    if (mq) {
-      int slot = 0;
-      if (lane == 0) slot = atomicAdd(a.q_kc + q, __popcll(mq));
-      slot = __shfl(slot, 0);
-      if (queue) put_key(a, q, slot + lanes_below(mq), make_key(S, rid));
-    }
-    if (a.stats) {
-      unsigned nd = fin ? 1u : 0u, ds = fin ? unsigned(dexit) : 0u;
-#pragma unroll
-      for (int o = 32; o >= 1; o >>= 1) {
-        nd += __shfl_xor(nd, o, 64);
-        ds += __shfl_xor(ds, o, 64);
-      }
-      if (lane == 0 && nd) {
-        atomicAdd(reinterpret_cast<unsigned long long*>(a.stats + int64_t(q) * 4 + 0), (unsigned long long)nd);
-        atomicAdd(reinterpret_cast<unsigned long long*>(a.stats + int64_t(q) * 4 + 1), (unsigned long long)ds);
-      }
-    }
+    append_keys(a, q, fin && !rej && passes<RERANK>(S, rid, full, keyr, gate_f * r2), make_key(S, rid), lane);
+    if (a.stats) add_stats(a, q, fin, dexit, lane);
     const bool deep = has && !done;
     const unsigned long long md = __ballot(deep);
     if (deep) stk[sn + lanes_below(md)] = make_int4(q, p, __float_as_int(S), (nb0 << 8) | 1);
@@ -392,106 +451,203 @@ __device__ void exact_rerank(unsigned long long* keys, int n, const float* __res
   __syncthreads();
 }
 
-// End (t1, off1) of the round that starts at (t, off): the first round holds the first K
-// candidates, later rounds end at the schedule's probe-rank boundaries.
+// End (t1, off1) of the round that starts at (t, off) after pos candidates; returns its
+// candidate count.  The first round holds the first max(K, fill_min) candidates; a later round
+// ends at the schedule's next probe-rank boundary (every rank, or ranks 1, 2, 4, ...) or after
+// growth * pos candidates if that comes first (growth 0: no cap).
 template <typename LenFn>
-__device__ void round_end(int t, int off, bool fill, int K, int np, int schedule, LenFn len_of,
-                          int& t1, int& off1) {
-  t1 = t + 1;
-  off1 = 0;
-  if (fill) {
-    int rem = K, tt = t, oo = off;
-    while (rem > 0 && tt < np) {
-      const int len = len_of(tt);
-      if (len - oo > rem) {
-        oo += rem;
-        rem = 0;
-      } else {
-        rem -= len - oo;
-        ++tt;
-        oo = 0;
-      }
+__device__ int64_t round_end(const RoundArgs& a, int t, int off, int64_t pos, bool first, int K, int np,
+                             LenFn len_of, int& t1, int& off1) {
+  int tb = np;
+  int64_t rem;
+  if (first) {
+    rem = K > a.fill_min ? K : a.fill_min;
+  } else {
+    if (a.schedule == 0) {
+      tb = t + 1;
+    } else {
+      int B = 1;
+      while (B <= t) B <<= 1;
+      tb = B < np ? B : np;
     }
-    t1 = tt;
-    off1 = oo;
-  } else if (schedule != 0) {
-    int B = 1;
-    while (B <= t) B <<= 1;
-    t1 = B < np ? B : np;
+    rem = a.growth > 0 ? int64_t(a.growth) * pos : INT64_MAX;
   }
+  int tt = t, oo = off;
+  int64_t took = 0;
+  while (tt < tb && rem > 0) {
+    const int avail = len_of(tt) - oo;
+    if (avail > rem) {
+      oo += int(rem);
+      took += rem;
+      rem = 0;
+    } else {
+      rem -= avail;
+      took += avail;
+      ++tt;
+      oo = 0;
+    }
+  }
+  t1 = tt;
+  off1 = oo;
+  return took;
 }
 
-// Queue the work items of query q's round [(t, off), (t1, off1)).  One thread.
+// Work items of query q's round [(t, off), (t1, off1)): every list segment of the round cut
+// into items of at most kItem candidates.  With items == nullptr only counts them.
 template <typename LenFn, typename PosFn>
-__device__ void queue_items(const RoundArgs& a, int buf, int q, int t, int off, int t1, int off1,
-                            LenFn len_of, PosFn pos_of) {
+__device__ int round_items(const RoundArgs& a, int4* items, int cap, int slot, int q, int t, int off, int t1,
+                           int off1, int per, LenFn len_of, PosFn pos_of) {
   const int t_last = off1 > 0 ? t1 : t1 - 1;
   int n = 0;
   for (int tt = t; tt <= t_last; ++tt) {
     const int s0 = tt == t ? off : 0;
     const int s1 = tt == t1 ? off1 : len_of(tt);
-    if (s1 > s0) n += (s1 - s0 + kItem - 1) / kItem;
-  }
-  if (n == 0) return;
-  int slot = atomicAdd(a.n_items + buf, n);
-  int4* items = a.items[buf];
-  for (int tt = t; tt <= t_last; ++tt) {
-    const int s0 = tt == t ? off : 0;
-    const int s1 = tt == t1 ? off1 : len_of(tt);
+    if (s1 <= s0) continue;
+    if (!items) {
+      n += (s1 - s0 + per - 1) / per;
+      continue;
+    }
     const int p0 = int(pos_of(tt));
-    for (int s = s0; s < s1; s += kItem) {
-      if (slot < a.items_cap) items[slot] = make_int4(q, s1 - s < kItem ? s1 - s : kItem, p0 + s, 0);
+    for (int ss = s0; ss < s1; ss += per, ++n) {
+      if (slot + n < cap) items[slot + n] = make_int4(q, s1 - ss < per ? s1 - ss : per, p0 + ss, 0);
       else atomicOr(a.overflow, 2);
-      ++slot;
     }
   }
+  return n;
 }
 
 // ------------------------------------------------------------------------------------------------
-// merge_round: per query, merge the round's queued keys, then set up its next round (or write
-// its result).  With init set it only sets up the first round.
-template <bool RERANK>
-__global__ __launch_bounds__(kThreads) void merge_round_kernel(RoundArgs a, int buf_out, int init) {
-  extern __shared__ float qo[];   // [dp] original query (RERANK)
-  __shared__ unsigned long long topk[kMaxK];
-  __shared__ unsigned long long newk[kMaxK];
-  __shared__ unsigned long long fk[RERANK ? kMaxK : 1];
-  __shared__ unsigned long long cand[kMergeChunk + kMaxK];
-  __shared__ int s_nc, s_fin;
-  __shared__ unsigned long long s_b;
+// plan: the round cuts of every query's whole candidate sequence (they depend only on the list
+// sizes, K and the schedule), and each round's work items in that round's region.  Three
+// passes without atomics: per query, its item count in every round; per round, an exclusive
+// prefix sum over the queries; per query, its items written at its offsets.  The first pass
+// also sets the query's heap state to empty.
+constexpr int kPlanLists = 2048;   // probed lists whose (position, length) are staged in LDS
 
+constexpr int kPlanRounds = 1024;  // rounds whose cuts are staged in LDS for the writing pass
+
+template <bool WRITE>
+__global__ __launch_bounds__(64) void plan_kernel(RoundArgs a, int* counts) {
+  __shared__ int2 lst[kPlanLists];
+  __shared__ int4 cuts[WRITE ? kPlanRounds : 1];
+  __shared__ int s_nr;
   const int q = blockIdx.x;
-  const int tid = threadIdx.x;
-  const int dp = a.dp, dim = a.dim;
+  const int lane = threadIdx.x;
   int K = a.k_pq ? a.k_pq[q] : a.k_max;
   K = K < 1 ? 1 : (K > a.k_max ? a.k_max : K);
   int np = a.nprobe_pq ? a.nprobe_pq[q] : a.nprobe_max;
   np = np < 1 ? 1 : (np > a.nprobe_max ? a.nprobe_max : np);
   const int32_t* pr = a.probes + int64_t(q) * a.nprobe_max;
-  auto len_of = [&](int tt) { return int(a.list_off[pr[tt] + 1] - a.list_off[pr[tt]]); };
-  auto pos_of = [&](int tt) { return a.list_off[pr[tt]]; };
-  int* cur = a.q_cur + 4 * int64_t(q);
-  unsigned long long* gtop = a.q_topk + int64_t(q) * a.k_max;
-
-  if (init) {
-    if (tid == 0) {
+  for (int t = lane; t < np && t < kPlanLists; t += 64) {
+    const int l = pr[t];
+    const int64_t o = a.list_off[l];
+    lst[t] = make_int2(int(o), int(a.list_off[l + 1] - o));
+  }
+  __syncthreads();
+  auto len_of = [&](int tt) {
+    return tt < kPlanLists ? lst[tt].y : int(a.list_off[pr[tt] + 1] - a.list_off[pr[tt]]);
+  };
+  auto pos_of = [&](int tt) { return tt < kPlanLists ? int64_t(lst[tt].x) : a.list_off[pr[tt]]; };
+  if (lane == 0) {
+    int t = 0, off = 0, r = 0;
+    int64_t pos = 0;
+    while (t < np && r < a.rounds) {
+      int t1, off1;
+      // rounds that start before K candidates have been merged hold few candidates and read
+      // whole rows: smaller items spread them over more waves
+      const int per = pos < K ? kDenseItem : kItem;
+      pos += round_end(a, t, off, pos, r == 0, K, np, len_of, t1, off1);
+      if (!WRITE) {
+        counts[int64_t(r) * a.nq + q] = round_items(a, nullptr, 0, 0, q, t, off, t1, off1, per, len_of, pos_of);
+      } else if (r < kPlanRounds) {
+        cuts[r] = make_int4(t, off, t1, off1 | (per == kDenseItem ? int(0x80000000u) : 0));
+      } else {
+        round_items(a, a.items + int64_t(r) * a.items_cap, a.items_cap, counts[int64_t(r) * a.nq + q], q, t, off,
+                    t1, off1, per, len_of, pos_of);
+      }
+      t = t1;
+      off = off1;
+      ++r;
+    }
+    if (WRITE) {
+      s_nr = r < kPlanRounds ? r : kPlanRounds;
+    } else {
+      for (int rr = r; rr < a.rounds; ++rr) counts[int64_t(rr) * a.nq + q] = 0;
+      if (t < np) atomicOr(a.overflow, 4);   // more rounds than the launch sequence holds
+      a.q_rounds[q] = r;
       a.q_topn[q] = 0;
       a.q_kc[q] = 0;
       a.q_keyr[q] = ~0ull;
       a.q_r2[q] = __builtin_inff();
-      int t1, off1;
-      round_end(0, 0, true, K, np, a.schedule, len_of, t1, off1);
-      cur[0] = 0;
-      cur[1] = 0;
-      cur[2] = t1;
-      cur[3] = off1;
-      queue_items(a, buf_out, q, 0, 0, t1, off1, len_of, pos_of);
       if (a.stats)
         for (int i = 0; i < 4; ++i) a.stats[int64_t(q) * 4 + i] = 0;
     }
-    return;
   }
-  if (cur[0] >= np) return;   // finished in an earlier round
+  if (!WRITE) return;
+  __syncthreads();
+  // the staged rounds' items, one round per lane
+  for (int r = lane; r < s_nr; r += 64) {
+    const int4 c = cuts[r];
+    round_items(a, a.items + int64_t(r) * a.items_cap, a.items_cap, counts[int64_t(r) * a.nq + q], q, c.x, c.y,
+                c.z, c.w & 0x7FFFFFFF, c.w < 0 ? kDenseItem : kItem, len_of, pos_of);
+  }
+}
+
+// counts[r][0..nq) -> exclusive prefix sums in place, n_items[r] = the total.  One workgroup per
+// round.
+constexpr int kScanThreads = 1024;
+__global__ __launch_bounds__(kScanThreads) void plan_offsets_kernel(RoundArgs a, int* counts) {
+  __shared__ int part[kScanThreads / 64];
+  __shared__ int s_carry;
+  int* c = counts + int64_t(blockIdx.x) * a.nq;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (tid == 0) s_carry = 0;
+  __syncthreads();
+  for (int base = 0; base < a.nq; base += kScanThreads) {
+    const int i = base + tid;
+    const int v = i < a.nq ? c[i] : 0;
+    int x = v;   // inclusive scan within the wave
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int y = __shfl_up(x, o, 64);
+      if (lane >= o) x += y;
+    }
+    if (lane == 63) part[wave] = x;
+    __syncthreads();
+    int before = s_carry;
+    for (int w = 0; w < wave; ++w) before += part[w];
+    if (i < a.nq) c[i] = before + x - v;
+    __syncthreads();
+    if (tid == kScanThreads - 1) s_carry = before + x;
+    __syncthreads();
+  }
+  if (tid == 0) a.n_items[blockIdx.x] = s_carry;
+}
+
+// ------------------------------------------------------------------------------------------------
+// merge_round: per query, merge round r's queued keys into the top-K and take the snapshot for
+// the next round; after the query's last round, write its result.
+template <bool RERANK>
+__global__ __launch_bounds__(kThreads) void merge_round_kernel(RoundArgs a, int r) {
+  extern __shared__ float qo[];   // [dp] original query (RERANK)
+  __shared__ unsigned long long topk[kMaxK];
+  __shared__ unsigned long long newk[kMaxK];
+  __shared__ unsigned long long fk[RERANK ? kMaxK : 1];
+  __shared__ unsigned long long cand[kMergeChunk + kMaxK];
+  __shared__ int s_nc;
+  __shared__ unsigned long long s_b;
+
+  const int q = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int dp = a.dp, dim = a.dim;
+  const int rq = a.q_rounds[q];
+  if (r >= rq) return;                    // finished in an earlier round
+  const int kc = a.q_kc[q];
+  const bool last = r == rq - 1;
+  if (kc == 0 && !last) return;           // nothing queued: heap and snapshot stay as they are
+  int K = a.k_pq ? a.k_pq[q] : a.k_max;
+  K = K < 1 ? 1 : (K > a.k_max ? a.k_max : K);
+  unsigned long long* gtop = a.q_topk + int64_t(q) * a.k_max;
 
   int topk_n = a.q_topn[q];
   for (int i = tid; i < topk_n; i += kThreads) topk[i] = gtop[i];
@@ -499,7 +655,6 @@ __global__ __launch_bounds__(kThreads) void merge_round_kernel(RoundArgs a, int 
     for (int c = tid; c < dp; c += kThreads) qo[c] = a.qorig[int64_t(q) * dp + c];
   const unsigned long long keyr = a.q_keyr[q];
   const bool full = keyr != ~0ull;
-  const int kc = a.q_kc[q];
   const int m = kc < a.kb_cap ? kc : int(a.kb_cap);
   const unsigned long long* kb = a.kb + int64_t(q) * a.kb_cap;
   unsigned st_kept = 0, st_rr = 0;
@@ -594,7 +749,7 @@ __global__ __launch_bounds__(kThreads) void merge_round_kernel(RoundArgs a, int 
     }
   }
 
-  // ---- store the heap, advance the cursor, queue the next round or write the result
+  // ---- store the heap and the next round's snapshot, or write the result
   for (int i = tid; i < topk_n; i += kThreads) gtop[i] = topk[i];
   if (a.stats) {
     if (st_kept)
@@ -605,24 +760,12 @@ __global__ __launch_bounds__(kThreads) void merge_round_kernel(RoundArgs a, int 
   if (tid == 0) {
     a.q_topn[q] = topk_n;
     a.q_kc[q] = 0;
-    const int t = cur[2], off = cur[3];
-    cur[0] = t;
-    cur[1] = off;
-    s_fin = t >= np;
-    if (t < np) {
-      const bool nfull = topk_n == K;
-      const unsigned long long nkey = nfull ? topk[K - 1] : ~0ull;
-      a.q_keyr[q] = nkey;
-      a.q_r2[q] = nfull ? key_dist(nkey) : __builtin_inff();
-      int t1, off1;
-      round_end(t, off, false, K, np, a.schedule, len_of, t1, off1);
-      cur[2] = t1;
-      cur[3] = off1;
-      queue_items(a, buf_out, q, t, off, t1, off1, len_of, pos_of);
-    }
+    const bool nfull = topk_n == K;
+    const unsigned long long nkey = nfull ? topk[K - 1] : ~0ull;
+    a.q_keyr[q] = nkey;
+    a.q_r2[q] = nfull ? key_dist(nkey) : __builtin_inff();
   }
-  __syncthreads();
-  if (s_fin) {
+  if (last) {
     for (int j = tid; j < a.k_max; j += kThreads) {
       const int64_t o = int64_t(q) * a.k_max + j;
       if (j < topk_n) {
@@ -637,27 +780,35 @@ __global__ __launch_bounds__(kThreads) void merge_round_kernel(RoundArgs a, int 
 }
 
 template <typename ST, bool DADE, bool RERANK>
-hipError_t launch_round_typed(const RoundArgs& a, int buf, hipStream_t s) {
+hipError_t launch_round_typed(const RoundArgs& a, int r, hipStream_t s) {
   if (DADE && a.delta_d % 8 != 0)
-    hipLaunchKernelGGL((scan_round_kernel<ST, DADE, RERANK, true>), dim3(a.grid), dim3(kThreads), 0, s, a, buf);
+    hipLaunchKernelGGL((scan_round_kernel<ST, DADE, RERANK, true>), dim3(a.grid), dim3(kThreads), 0, s, a, r);
   else
-    hipLaunchKernelGGL((scan_round_kernel<ST, DADE, RERANK, false>), dim3(a.grid), dim3(kThreads), 0, s, a, buf);
+    hipLaunchKernelGGL((scan_round_kernel<ST, DADE, RERANK, false>), dim3(a.grid), dim3(kThreads), 0, s, a, r);
   return hipGetLastError();
 }
 
 template <typename ST, bool RERANK>
-hipError_t launch_round_mode(const RoundArgs& a, int buf, hipStream_t s) {
-  return a.mode == 0 ? launch_round_typed<ST, true, RERANK>(a, buf, s)
-                     : launch_round_typed<ST, false, RERANK>(a, buf, s);
+hipError_t launch_round_mode(const RoundArgs& a, int r, hipStream_t s) {
+  return a.mode == 0 ? launch_round_typed<ST, true, RERANK>(a, r, s)
+                     : launch_round_typed<ST, false, RERANK>(a, r, s);
 }
 
 }  // namespace
 
-hipError_t launch_round(const RoundArgs& a, int buf, hipStream_t s) {
+hipError_t launch_round(const RoundArgs& a, int r, hipStream_t s) {
   if (a.nq == 0) return hipSuccess;
-  if (a.dtype == 0) return launch_round_mode<float, false>(a, buf, s);
-  if (a.dtype == 1) return launch_round_mode<__hip_bfloat16, true>(a, buf, s);
-  return launch_round_mode<__half, true>(a, buf, s);
+  if (a.dtype == 0) return launch_round_mode<float, false>(a, r, s);
+  if (a.dtype == 1) return launch_round_mode<__hip_bfloat16, true>(a, r, s);
+  return launch_round_mode<__half, true>(a, r, s);
+}
+
+hipError_t launch_plan(const RoundArgs& a, int* counts, hipStream_t s) {
+  if (a.nq == 0) return hipSuccess;
+  hipLaunchKernelGGL((plan_kernel<false>), dim3(a.nq), dim3(64), 0, s, a, counts);
+  hipLaunchKernelGGL(plan_offsets_kernel, dim3(a.rounds), dim3(kScanThreads), 0, s, a, counts);
+  hipLaunchKernelGGL((plan_kernel<true>), dim3(a.nq), dim3(64), 0, s, a, counts);
+  return hipGetLastError();
 }
 
 int round_blocks_per_cu(int dtype, int mode, int delta_d) {
@@ -682,13 +833,13 @@ int round_blocks_per_cu(int dtype, int mode, int delta_d) {
   return (e == hipSuccess && n > 0) ? n : 1;
 }
 
-hipError_t launch_merge(const RoundArgs& a, int buf_out, int init, hipStream_t s) {
+hipError_t launch_merge(const RoundArgs& a, int r, hipStream_t s) {
   if (a.nq == 0) return hipSuccess;
   const size_t lds = a.dtype == 0 ? 0 : sizeof(float) * size_t(a.dp);
   if (a.dtype == 0)
-    hipLaunchKernelGGL((merge_round_kernel<false>), dim3(a.nq), dim3(kThreads), lds, s, a, buf_out, init);
+    hipLaunchKernelGGL((merge_round_kernel<false>), dim3(a.nq), dim3(kThreads), lds, s, a, r);
   else
-    hipLaunchKernelGGL((merge_round_kernel<true>), dim3(a.nq), dim3(kThreads), lds, s, a, buf_out, init);
+    hipLaunchKernelGGL((merge_round_kernel<true>), dim3(a.nq), dim3(kThreads), lds, s, a, r);
   return hipGetLastError();
 }
 

@@ -21,7 +21,7 @@ DTYPES = {"f32": 0, "bf16": 1, "f16": 2}
 MODES = {"dade": 0, "full_d": 1}
 SCHEDULES = {"per_rank": 0, "doubling": 1}
 STATE_BUILT, STATE_ROTATED, STATE_CALIBRATED = 1, 2, 3
-EXPORTED = ("dade_build_index", "dade_rotate", "dade_calibrate", "dade_search", "dade_index_info",
+EXPORTED = ("dade_build_index", "dade_rotate", "dade_calibrate", "dade_search", "dade_check", "dade_index_info",
             "dade_export", "dade_import", "dade_stage_times", "dade_destroy", "dade_last_error")
 
 
@@ -40,7 +40,8 @@ class BuildOpts(ctypes.Structure):
 class SearchOpts(ctypes.Structure):
     _fields_ = [("delta_d", ctypes.c_int32), ("mode", ctypes.c_int32), ("schedule", ctypes.c_int32),
                 ("rerank_delta", ctypes.c_float), ("stats", ctypes.c_void_p),
-                ("record_times", ctypes.c_int32)]
+                ("record_times", ctypes.c_int32), ("fill_min", ctypes.c_int32), ("growth", ctypes.c_int32),
+                ("use_graph", ctypes.c_int32)]
 
 
 class Artifacts(ctypes.Structure):
@@ -67,6 +68,7 @@ def lib():
         L.dade_rotate.argtypes = [vp, vp]
         L.dade_calibrate.argtypes = [vp, ctypes.c_double, vp, i64, u64, vp]
         L.dade_search.argtypes = [vp, vp, i64, i32, i32, vp, vp, ctypes.POINTER(SearchOpts), vp, vp, vp]
+        L.dade_check.argtypes = [vp, vp]
         L.dade_index_info.argtypes = [vp] + [ctypes.POINTER(t) for t in (i64, i32, i32, i32, i32)]
         L.dade_export.argtypes = [vp, ctypes.POINTER(Artifacts)]
         L.dade_import.argtypes = [ctypes.POINTER(Artifacts), vp, ctypes.POINTER(BuildOpts), vp, pp]
@@ -160,7 +162,7 @@ def dade_calibrate(ix: Index, alpha=0.1, pairs=None, n_pairs=100_000, seed=0, st
 
 def dade_search(ix: Index, Q, k, nprobe, k_per_query=None, nprobe_per_query=None, delta_d=0,
                 mode="dade", schedule="per_rank", rerank_delta=-1.0, stats=None, record_times=False,
-                out_ids=None, out_dist2=None, stream=None):
+                out_ids=None, out_dist2=None, stream=None, fill_min=32, growth=4, use_graph=True):
     """Returns (ids [nq, k] int64, dist2 [nq, k] float32) device tensors (asynchronous)."""
     import torch
     qp = _dev(Q, torch.float32, "Q")
@@ -174,12 +176,18 @@ def dade_search(ix: Index, Q, k, nprobe, k_per_query=None, nprobe_per_query=None
     o.rerank_delta = rerank_delta
     o.stats = None if stats is None else _dev(stats, torch.int64, "stats").value
     o.record_times = int(bool(record_times))
+    o.fill_min, o.growth, o.use_graph = fill_min, growth, int(bool(use_graph))
     kp = None if k_per_query is None else _dev(k_per_query, torch.int32, "k_per_query")
     npp = None if nprobe_per_query is None else _dev(nprobe_per_query, torch.int32, "nprobe_per_query")
     _check(lib().dade_search(ix.handle, qp, nq, k, nprobe, kp, npp, ctypes.byref(o),
                              _dev(out_ids, torch.int64, "out_ids"),
                              _dev(out_dist2, torch.float32, "out_dist2"), _stream(stream)))
     return out_ids, out_dist2
+
+
+def dade_check(ix: Index, stream=None):
+    """Raises DadeError if a search on this index exceeded a list-scan capacity (synchronises)."""
+    _check(lib().dade_check(ix.handle, _stream(stream)))
 
 
 def dade_index_info(ix: Index):

@@ -68,4 +68,5 @@ def gpu_search(gi, Qd, K, nprobe, **kw):
     import torch
     ids, d2 = dade.dade_search(gi, Qd, K, nprobe, **kw)
     torch.cuda.synchronize()
+    dade.dade_check(gi)
     return to_np(ids), to_np(d2)

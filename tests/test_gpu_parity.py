@@ -54,6 +54,43 @@ def test_dade_matches_oracle(small, schedule):
     assert st[:, 1].sum() < 0.8 * st[:, 0].sum() * w.dim   # the test really exits early
 
 
+@pytest.mark.parametrize("fill_min,growth,schedule", [(0, 0, "per_rank"), (0, 1, "per_rank"), (8, 2, "doubling"),
+                                                      (200, 4, "per_rank")])
+def test_round_size_options(small, fill_min, growth, schedule):
+    """First-round minimum and growth cap: the same round cuts as the oracle's, so DCO counts
+    agree exactly and results agree up to near ties."""
+    w, oi = small["w"], small["oi"]
+    o_ids, _, logs = ivf.search(oi, small["Q"], w.k, w.nprobe, w.delta_d, schedule=schedule, log=True,
+                                fill_min=fill_min, growth=growth)
+    stats = torch.zeros((w.n_queries, 4), dtype=torch.int64, device="cuda")
+    g_ids, g_d2 = gpu_search(small["gi"], small["Qd"], w.k, w.nprobe, delta_d=w.delta_d, schedule=schedule,
+                             stats=stats, fill_min=fill_min, growth=growth)
+    compare(o_ids, logs, g_ids, g_d2, small["X"], small["Q"], w.k)
+    st = to_np(stats)
+    np.testing.assert_array_equal(st[:, 0], logs["dcos"].astype(np.int64))
+    rel = np.abs(st[:, 1] - logs["dims"]) / logs["dims"]
+    assert np.median(rel) == 0.0 and rel.max() < 0.02
+
+
+@pytest.mark.parametrize("schedule", ["per_rank", "doubling"])
+def test_graph_replays_match_eager(small, schedule):
+    """The captured launch sequence, replayed several times with eager searches and
+    synchronisations in between, gives the eager result bit for bit every time."""
+    w, gi, Qd = small["w"], small["gi"], small["Qd"]
+    kw = dict(delta_d=w.delta_d, schedule=schedule)
+    ref_i, ref_d = gpu_search(gi, Qd, w.k, w.nprobe, use_graph=False, **kw)
+    out_i = torch.empty((w.n_queries, w.k), dtype=torch.int64, device="cuda")
+    out_d = torch.empty((w.n_queries, w.k), dtype=torch.float32, device="cuda")
+    for _ in range(4):
+        out_i.fill_(-7)
+        out_d.fill_(0.0)
+        dade.dade_search(gi, Qd, w.k, w.nprobe, out_ids=out_i, out_dist2=out_d, use_graph=True, **kw)
+        torch.cuda.synchronize()
+        assert np.array_equal(to_np(out_i), ref_i)
+        assert np.array_equal(to_np(out_d).view(np.uint32), ref_d.view(np.uint32))
+        gpu_search(gi, Qd[:7].contiguous(), 5, 3, use_graph=False)   # eager work between replays
+
+
 def test_all_lists_full_d_is_brute_force(small):
     w = small["w"]
     g_ids, g_d2 = gpu_search(small["gi"], small["Qd"][:20], 10, w.nlist, mode="full_d")

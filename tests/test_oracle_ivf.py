@@ -139,14 +139,34 @@ def test_uneven_k_and_nprobe(setup):
 
 
 def test_round_starts_fill_then_schedule():
-    # lists of sizes 5, 7, 3, 4; K = 3: fill [0,3), rest of list 0, then each list
-    assert ivf.round_starts(np.array([5, 7, 3, 4]), 3, "per_rank") == [0, 3, 5, 12, 15, 19]
+    rs = ivf.round_starts
+    # lists of sizes 5, 7, 3, 4; K = 3, no fill minimum, no growth cap: fill [0,3), rest of
+    # list 0, then each list
+    assert rs(np.array([5, 7, 3, 4]), 3, "per_rank", 0, 0) == [0, 3, 5, 12, 15, 19]
     # K = 6 crosses into list 1: fill [0,6), then the rest of list 1
-    assert ivf.round_starts(np.array([5, 7, 3, 4]), 6, "per_rank") == [0, 6, 12, 15, 19]
+    assert rs(np.array([5, 7, 3, 4]), 6, "per_rank", 0, 0) == [0, 6, 12, 15, 19]
     # doubling: ranks end after lists 1, 2, 4 -> positions 5, 12, 19
-    assert ivf.round_starts(np.array([5, 7, 3, 4]), 3, "doubling") == [0, 3, 5, 12, 19]
+    assert rs(np.array([5, 7, 3, 4]), 3, "doubling", 0, 0) == [0, 3, 5, 12, 19]
     # K larger than everything: one round
-    assert ivf.round_starts(np.array([2, 2]), 10, "per_rank") == [0, 4]
+    assert rs(np.array([2, 2]), 10, "per_rank", 0, 0) == [0, 4]
+
+
+def test_round_starts_fill_minimum_and_growth_cap():
+    rs = ivf.round_starts
+    sizes = np.array([5, 7, 3, 4])
+    # growth 1: a round holds at most as many candidates as came before it
+    #   3 -> min(cut 5, 6) = 5 -> min(12, 10) = 10 -> min(12, 20) = 12 -> 15 -> 19
+    assert rs(sizes, 3, "per_rank", 0, 1) == [0, 3, 5, 10, 12, 15, 19]
+    #   2 -> min(5, 4) = 4 -> min(5, 8) = 5 -> 10 -> 12 -> 15 -> 19
+    assert rs(sizes, 2, "per_rank", 0, 1) == [0, 2, 4, 5, 10, 12, 15, 19]
+    # doubling cuts 5, 12, 19 with growth 2: 1 -> min(5, 3) = 3 -> min(5, 9) = 5 -> 12 -> 19
+    assert rs(sizes, 1, "doubling", 0, 2) == [0, 1, 3, 5, 12, 19]
+    # a fill minimum of 8 makes the first round [0, 8), then the cuts after 8
+    assert rs(sizes, 3, "per_rank", 8, 0) == [0, 8, 12, 15, 19]
+    # the defaults (at least 32 in the first round) take all 19 candidates at once
+    assert rs(sizes, 3, "per_rank") == [0, 19]
+    # nothing to scan
+    assert rs(np.array([0, 0]), 3, "per_rank") == [0]
 
 
 def test_round_bounds():
@@ -207,8 +227,12 @@ def test_keep_rule_breaks_distance_ties_by_id():
     q = np.zeros((1, 2))
     ids, d2, logs = ivf.search(index, q, 1, 1, 1, mode="exact", schedule="sequential", log=True)
     assert ids[0, 0] == 0 and logs["accepted"][0] == 1
-    ids, d2, logs = ivf.search(index, q, 1, 1, 1, mode="exact", schedule="per_rank", log=True)
+    ids, d2, logs = ivf.search(index, q, 1, 1, 1, mode="exact", schedule="per_rank", log=True,
+                               fill_min=0, growth=0)
     assert ids[0, 0] == 0 and logs["accepted"][0] == 1
+    # with the default fill minimum all three rows fill the heap in one round; id 0 wins the tie
+    ids, d2, logs = ivf.search(index, q, 1, 1, 1, mode="exact", schedule="per_rank", log=True)
+    assert ids[0, 0] == 0 and logs["accepted"][0] == 3
 
 
 @pytest.mark.parametrize("delta", [0.0, 0.01, 1e9])
@@ -253,7 +277,8 @@ def _two_list_index(stored, exact, n0, delta=0.1):
 
 
 def _search2(index, nprobe):
-    ids, d2 = ivf.search(index, np.zeros((1, 2)), 2, nprobe, 1, mode="exact")
+    """K = 2, first round = the first K candidates, then one round per list."""
+    ids, d2 = ivf.search(index, np.zeros((1, 2)), 2, nprobe, 1, mode="exact", fill_min=0, growth=0)
     return list(ids[0]), d2[0]
 
 
