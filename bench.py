@@ -1,12 +1,18 @@
 """Benchmark of the DADE-IVF search path on one MI355X.
 
 Workload (default): 1M x 960 Gaussian mixture (2048 components, lam_i ~ i^-1.5), BF16 store
-with FP32 rerank, 1000 queries, K = 10, nlist = 4096, Delta_d = 32, P_s = 0.1.
+with FP32 rerank, 1000 queries, K = 10, nlist = 4096, Delta_d = 32.
 A step is one dade_search of the whole query batch (query rotation, probe selection and the
 list scan with top-K merge and rerank), inputs already resident in HBM.
 
-The metric is QPS at recall@10 >= 0.95: nprobe is swept for DADE and for the full-D exact
-scan (FDScanning) on the same index; each is timed at the smallest nprobe reaching the target.
+The metric is QPS at recall@10 >= 0.95.  FDScanning (full-D exact DCOs) on the same index is
+swept over nprobe; DADE over P_s (the significance level of the hypothesis test) and nprobe.
+Each is timed at the fastest configuration reaching the target:
+  * throughput: `--warmup` untimed searches, then `--steps` searches back to back between two
+    device synchronisations (the list scan replays a captured HIP graph);
+  * latency: `--steps` searches, each synchronised (p50 / p99);
+  * kernel times: searches with HIP events around every kernel of the scan (launched without the
+    graph), for the roofline of the DCO kernel.
 Prints one JSON line.
 """
 from __future__ import annotations
@@ -26,7 +32,7 @@ sys.path.insert(0, ROOT)
 METRIC = "QPS at recall@10≥0.95, DADE vs full-D exact DCO, 1 GPU; p50/p99 latency"
 PEAK_HBM_GBS = 8000.0
 NPROBE_SWEEP = (8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256)
-PS_SWEEP = (0.1, 0.05, 0.02, 0.01, 0.005, 0.002, 0.001)
+PS_SWEEP = (0.1, 0.05, 0.02, 0.01, 0.005, 0.002, 0.001, 0.0005)
 
 
 def log(*a):
@@ -45,46 +51,63 @@ def scan_source_sha():
     return h.hexdigest()[:16]
 
 
-def traffic_from_profile(workload, store, nprobe):
-    """HBM bytes per scan launch from the committed rocprofv3 counter summary, if it was taken on
-    the current scan kernel source and the same operating point; else None."""
+def traffic_from_profile(workload, store, nprobe, p_s):
+    """HBM bytes per DCO-kernel launch from the committed rocprofv3 counter summary, if it was taken
+    on the current scan source at the same operating point; else None."""
     path = os.path.join(ROOT, "profiles", "scan_traffic.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    key = f"{workload}/{store}/nprobe{nprobe}"
-    e = rec.get(key)
+    e = rec.get(f"{workload}/{store}/nprobe{nprobe}/p_s{p_s}")
     if not e or e.get("scan_sha") != scan_source_sha():
         return None
-    return e["fetch_bytes"] + e["write_bytes"]
+    return e["fetch_bytes_per_launch"] + e["write_bytes_per_launch"]
 
 
-def time_steps(dade, torch, ix, Qd, k, nprobe, steps, warmup, **kw):
-    """Warm-up, then `steps` timed searches; returns wall ms per step and the scan kernel's
-    HIP-event duration (ms) of every timed step."""
+SCHEDULE = dict(schedule="doubling", fill_min=32, growth=16)   # round schedule of the timed runs
+
+
+def throughput(dade, torch, ix, Qd, k, nprobe, steps, warmup, **kw):
+    """`warmup` untimed searches, then exactly `steps` searches back to back, bracketed by
+    device synchronisation; returns ms per step."""
     for _ in range(warmup):
         dade.dade_search(ix, Qd, k, nprobe, **kw)
     torch.cuda.synchronize()
-    walls, scans, probes, rots = [], [], [], []
-    t_all = time.perf_counter()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        dade.dade_search(ix, Qd, k, nprobe, **kw)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / steps
+
+
+def latencies(dade, torch, ix, Qd, k, nprobe, steps, **kw):
+    """Wall time of each search from enqueue to completion (one batch at a time)."""
+    walls = []
     for _ in range(steps):
         t0 = time.perf_counter()
-        dade.dade_search(ix, Qd, k, nprobe, record_times=True, **kw)
-        st = dade.dade_stage_times(ix)       # waits for this step's last event
+        dade.dade_search(ix, Qd, k, nprobe, **kw)
+        torch.cuda.synchronize()
         walls.append((time.perf_counter() - t0) * 1e3)
-        scans.append(st["scan_ms"])
-        probes.append(st["probe_ms"])
-        rots.append(st["rotate_ms"])
-    torch.cuda.synchronize()
-    total = (time.perf_counter() - t_all) * 1e3
-    return total / steps, np.array(walls), np.array(scans), np.array(probes), np.array(rots)
+    return np.array(walls)
 
 
-def cpu_baseline(w, X, Q, seconds=20.0):
-    """The FP64 oracle timed on this host's cores on a bounded sample: an oracle-built index over
-    a 5% row subsample with nlist scaled by the same factor (so lists keep the workload's size
-    and a query scans the same number of candidates of the same dimension), DADE mode,
-    per-rank schedule, queries until ~`seconds` of CPU time."""
+def kernel_times(dade, torch, ix, Qd, k, nprobe, steps, **kw):
+    """Per-stage and per-kernel times (HIP events on the kernels' stream), averaged over steps."""
+    acc = {}
+    for _ in range(steps):
+        dade.dade_search(ix, Qd, k, nprobe, record_times=True, **kw)
+        for key, v in dade.dade_stage_times(ix).items():
+            acc[key] = acc.get(key, 0.0) + v
+    return {key: v / steps for key, v in acc.items()}
+
+
+def cpu_baseline(w, X, Q, nprobe, p_s, seconds=20.0):
+    """The FP64 oracle timed on one host core (BLAS limited to one thread) on a bounded sample:
+    an oracle-built index over a 5% row subsample with nlist scaled by the same factor (so lists
+    keep the workload's size and a query scans the same number of candidates of the same
+    dimension), DADE mode with the timed runs' round schedule and P_s, queries until ~`seconds`."""
+    from threadpoolctl import threadpool_limits
+
     from oracle import ivf
     from paper_2411_17229_amd import workloads
     frac = 20
@@ -94,18 +117,19 @@ def cpu_baseline(w, X, Q, seconds=20.0):
     Xs = np.ascontiguousarray(X[rows])
     t0 = time.perf_counter()
     oi = ivf.build(Xs, nl_s, workloads.kmeans_init_rows(n_s, nl_s, 0),
-                   workloads.calibration_pairs(n_s, 100_000, 0), p_s=w.alpha, iters=10)
+                   workloads.calibration_pairs(n_s, 100_000, 0), p_s=p_s, iters=10)
     build_s = time.perf_counter() - t0
-    done, t0 = 0, time.perf_counter()
-    while done < len(Q) and time.perf_counter() - t0 < seconds:
-        ivf.search(oi, Q[done:done + 1], w.k, w.nprobe, w.delta_d)
-        done += 1
-    el = time.perf_counter() - t0
-    threads = os.environ.get("OPENBLAS_NUM_THREADS") or os.environ.get("OMP_NUM_THREADS") or str(os.cpu_count())
-    return {"value": done / el, "unit": "queries/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"{done} queries, DADE per-rank, nprobe {w.nprobe}, K {w.k}, over an oracle-built "
-                      f"index of a {n_s}-row subsample with nlist {nl_s} (same list size and D as the "
-                      f"workload); index build {build_s:.1f} s not timed"}
+    with threadpool_limits(limits=1):
+        done, t0 = 0, time.perf_counter()
+        while done < len(Q) and time.perf_counter() - t0 < seconds:
+            ivf.search(oi, Q[done:done + 1], w.k, nprobe, w.delta_d, **SCHEDULE)
+            done += 1
+        el = time.perf_counter() - t0
+    return {"value": done / el, "unit": "queries/s", "cores": 1, "kind": "oracle",
+            "sample": f"{done} queries, DADE {SCHEDULE['schedule']} schedule, P_s {p_s}, nprobe {nprobe}, "
+                      f"K {w.k}, over an oracle-built index of a {n_s}-row subsample with nlist {nl_s} "
+                      f"(same list size and D as the workload); one thread; index build {build_s:.1f} s "
+                      f"not timed"}
 
 
 def main():
@@ -163,10 +187,9 @@ def main():
 
     if args.profile_only:
         npb = args.nprobe or w.nprobe
-        ms, walls, scans, _, _ = time_steps(dade, torch, ix, Qd, w.k, npb, args.steps, args.warmup,
-                                            delta_d=w.delta_d, mode=args.mode)
-        log(f"[bench] profile run ({args.mode}, nprobe {npb}, P_s {args.p_s or w.alpha}): {ms:.3f} ms/step, "
-            f"scan {scans.mean():.3f} ms")
+        kw = dict(delta_d=w.delta_d, mode=args.mode, **SCHEDULE)
+        ms = throughput(dade, torch, ix, Qd, w.k, npb, args.steps, args.warmup, **kw)
+        log(f"[bench] profile run ({args.mode}, nprobe {npb}, P_s {args.p_s or w.alpha}): {ms:.3f} ms/step")
         return
 
     from oracle import knn
@@ -176,13 +199,13 @@ def main():
 
     pairs = workloads.calibration_pairs(w.n, 100_000, w.seed)
 
-    def first_reaching(mode):
+    def first_reaching(mode, kw):
         """(nprobe, recall, curve): smallest swept nprobe with recall >= target (else best)."""
         curve = {}
         for npb in NPROBE_SWEEP:
             if npb > w.nlist:
                 break
-            ids, _ = dade.dade_search(ix, Qd, w.k, npb, delta_d=w.delta_d, mode=mode)
+            ids, _ = dade.dade_search(ix, Qd, w.k, npb, delta_d=w.delta_d, mode=mode, **kw)
             torch.cuda.synchronize()
             curve[npb] = recall_at(ids.cpu().numpy(), gt, w.k)
             if curve[npb] >= args.target:
@@ -196,17 +219,17 @@ def main():
     # fastest configuration that reaches the target
     sweep = {"full_d": {}, "dade": {}}
     chosen = {}
-    npb, r, sweep["full_d"] = first_reaching("full_d")
+    npb, r, sweep["full_d"] = first_reaching("full_d", SCHEDULE)
     chosen["full_d"] = (None, npb, r)
     log(f"[bench] full_d: nprobe {npb} recall {r:.4f}")
     cands = []
     for ps in PS_SWEEP:
         dade.dade_calibrate(ix, ps, pairs=pairs)
-        npb, r, curve = first_reaching("dade")
+        npb, r, curve = first_reaching("dade", SCHEDULE)
         sweep["dade"][str(ps)] = curve
         log(f"[bench] dade P_s {ps}: nprobe {npb} recall {r:.4f}")
         if r >= args.target:
-            ms, _, _, _, _ = time_steps(dade, torch, ix, Qd, w.k, npb, 3, 1, delta_d=w.delta_d)
+            ms = throughput(dade, torch, ix, Qd, w.k, npb, 5, 2, delta_d=w.delta_d, **SCHEDULE)
             cands.append((ms, ps, npb, r))
             if len(cands) >= 2 and cands[-1][0] > cands[-2][0]:
                 break   # smaller P_s reads more dimensions; past the best already
@@ -218,32 +241,40 @@ def main():
         r = sweep["dade"][str(ps)][npb]
     chosen["dade"] = (ps, npb, r)
     dade.dade_calibrate(ix, ps, pairs=pairs)
+    s_bytes = 2 if store in ("bf16", "f16") else 4
     res = {}
     for mode in ("dade", "full_d"):
         ps_m, npb, r_m = chosen[mode]
+        kw = dict(delta_d=w.delta_d, mode=mode, **SCHEDULE)
         stats = torch.zeros((nq, 4), dtype=torch.int64, device=dev)
-        ids, d2 = dade.dade_search(ix, Qd, w.k, npb, delta_d=w.delta_d, mode=mode, stats=stats)
+        ids, d2 = dade.dade_search(ix, Qd, w.k, npb, stats=stats, **kw)
         torch.cuda.synchronize()
+        dade.dade_check(ix)
         st = stats.cpu().numpy().sum(0)
-        ms, walls, scans, probes, rots = time_steps(dade, torch, ix, Qd, w.k, npb, args.steps, args.warmup,
-                                                    delta_d=w.delta_d, mode=mode)
-        s_bytes = 2 if store in ("bf16", "f16") else 4
-        alg_bytes = s_bytes * st[1] + 4 * st[2] + (4 * w.dim * st[3] if store != "f32" else 0)
+        ms = throughput(dade, torch, ix, Qd, w.k, npb, args.steps, args.warmup, **kw)
+        walls = latencies(dade, torch, ix, Qd, w.k, npb, args.steps, **kw)
+        kt = kernel_times(dade, torch, ix, Qd, w.k, npb, max(3, args.steps // 4), **kw)
+        # algorithmic bytes of the DCO kernel: stored coordinates up to each DCO's exit, plus the
+        # id read and the key written for each kept candidate
+        alg_round = s_bytes * int(st[1]) + 12 * int(st[2])
         ids_np, d2_np = ids.cpu().numpy(), d2.cpu().numpy()
         ex = np.array([[np.sum((X[i].astype(np.float64) - Q[q]) ** 2) for i in ids_np[q]] for q in range(nq)])
         rel = np.abs(d2_np - ex) / np.maximum(ex, 1e-30)
         res[mode] = dict(nprobe=npb, p_s=ps_m, recall=r_m, qps=nq / (ms / 1e3), ms_per_step=ms,
                          p50_ms=float(np.percentile(walls, 50)), p99_ms=float(np.percentile(walls, 99)),
-                         scan_ms=float(scans.mean()), probe_ms=float(probes.mean()), rotate_ms=float(rots.mean()),
-                         dcos=int(st[0]), dims_frac=float(st[1]) / max(1, st[0] * w.dim),
-                         kept=int(st[2]), reranked=int(st[3]), alg_bytes=int(alg_bytes),
+                         times=kt, dcos=int(st[0]), dims_frac=float(st[1]) / max(1, st[0] * w.dim),
+                         kept=int(st[2]), reranked=int(st[3]), alg_round=alg_round,
                          max_rel_err=float(rel.max()), mean_rel_err=float(rel.mean()))
-        log(f"[bench] {mode}: nprobe {npb} recall {res[mode]['recall']:.4f} {res[mode]['qps']:.0f} QPS "
-            f"scan {res[mode]['scan_ms']:.3f} ms dims {res[mode]['dims_frac']:.3f}")
+        log(f"[bench] {mode}: nprobe {npb} recall {r_m:.4f} {res[mode]['qps']:.0f} QPS ({ms:.3f} ms/step) "
+            f"round kernels {kt['round_kernel_ms']:.3f} ms over {kt['round_launches']:.0f} launches, "
+            f"dims {res[mode]['dims_frac']:.4f}")
 
     d = res["dade"]
-    achieved = d["alg_bytes"] / (d["scan_ms"] * 1e-3) / 1e9
-    traffic = traffic_from_profile(w.name, store, d["nprobe"])
+    kt = d["times"]
+    launches = kt["round_launches"]
+    avg_ms = kt["round_kernel_ms"] / launches
+    achieved = d["alg_round"] / (kt["round_kernel_ms"] * 1e-3) / 1e9
+    traffic = traffic_from_profile(w.name, store, d["nprobe"], d["p_s"])
     out = {
         "metric": METRIC, "value": round(d["qps"], 1), "unit": "queries/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(d["ms_per_step"], 4),
@@ -251,48 +282,50 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "n": w.n, "dim": w.dim, "nlist": w.nlist, "k": w.k,
                    "queries_per_step": nq, "nprobe": d["nprobe"], "delta_d": w.delta_d, "p_s": d["p_s"],
-                   "store": store, "schedule": "per_rank", "recall@10": round(d["recall"], 4)},
+                   "store": store, "schedule": SCHEDULE["schedule"], "fill_min": SCHEDULE["fill_min"],
+                   "growth": SCHEDULE["growth"], "recall@10": round(d["recall"], 4)},
         "p50_ms": round(d["p50_ms"], 4), "p99_ms": round(d["p99_ms"], 4),
         "full_d": {"qps": round(res["full_d"]["qps"], 1), "nprobe": res["full_d"]["nprobe"],
-                   "recall@10": round(res["full_d"]["recall"], 4), "scan_ms": round(res["full_d"]["scan_ms"], 4),
+                   "recall@10": round(res["full_d"]["recall"], 4),
+                   "ms_per_step": round(res["full_d"]["ms_per_step"], 4),
                    "p50_ms": round(res["full_d"]["p50_ms"], 4), "p99_ms": round(res["full_d"]["p99_ms"], 4)},
         "speedup_vs_full_d": round(d["qps"] / res["full_d"]["qps"], 3),
-        "stages_ms": {"rotate": round(d["rotate_ms"], 4), "probe": round(d["probe_ms"], 4),
-                      "scan": round(d["scan_ms"], 4)},
+        "stages_ms": {k_: round(v, 4) for k_, v in kt.items()},
         "dims_read_frac": round(d["dims_frac"], 4),
         "dist2_rel_err_vs_fp64": {"max": d["max_rel_err"], "mean": d["mean_rel_err"]},
-        "recall_sweep": {"full_d": {str(k): round(v, 4) for k, v in sweep["full_d"].items()},
-                         "dade_by_p_s": {ps_: {str(k): round(v, 4) for k, v in c.items()}
+        "recall_sweep": {"full_d": {str(k_): round(v, 4) for k_, v in sweep["full_d"].items()},
+                         "dade_by_p_s": {ps_: {str(k_): round(v, 4) for k_, v in c.items()}
                                          for ps_, c in sweep["dade"].items()}},
-        "roofline": {"bound": "hbm", "kernel": "dade scan", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
-                     "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
-                     "traffic": (round(traffic / (d["scan_ms"] * 1e-3) / 1e9, 1) if traffic else None),
-                     "alg_bytes_per_launch": d["alg_bytes"], "scan_ms": round(d["scan_ms"], 4)},
+        "roofline": {"bound": "hbm", "kernel": "scan_round_kernel", "achieved": round(achieved, 1),
+                     "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
+                     "traffic": (round(traffic / (avg_ms * 1e-3) / 1e9, 1) if traffic else None),
+                     "alg_bytes_per_launch": round(d["alg_round"] / launches), "launches_per_step": launches,
+                     "avg_launch_ms": round(avg_ms, 5)},
     }
     if not args.no_variants and store != "f32":
         # the same lists and transform with the other 16-bit store and with FP32 (recall vs FP32)
         art = dade.dade_export(ix)
         variants = {}
-        ids_main, _ = dade.dade_search(ix, Qd, w.k, d["nprobe"], delta_d=w.delta_d)
+        ids_main, _ = dade.dade_search(ix, Qd, w.k, d["nprobe"], delta_d=w.delta_d, **SCHEDULE)
         for vs in ("f16" if store == "bf16" else "bf16", "f32"):
-            vi = dade.dade_import({k: v for k, v in art.items() if k not in ("T",)}, Xd, store=vs)
+            vi = dade.dade_import({k_: v for k_, v in art.items() if k_ not in ("T",)}, Xd, store=vs)
             dade.dade_calibrate(vi, d["p_s"], pairs=pairs)
-            ms, walls, scans, _, _ = time_steps(dade, torch, vi, Qd, w.k, d["nprobe"], max(3, args.steps // 4), 1,
-                                                delta_d=w.delta_d)
-            ids_v, d2_v = dade.dade_search(vi, Qd, w.k, d["nprobe"], delta_d=w.delta_d)
+            ms = throughput(dade, torch, vi, Qd, w.k, d["nprobe"], max(3, args.steps // 4), 1,
+                            delta_d=w.delta_d, **SCHEDULE)
+            ids_v, d2_v = dade.dade_search(vi, Qd, w.k, d["nprobe"], delta_d=w.delta_d, **SCHEDULE)
             torch.cuda.synchronize()
             ids_v, d2_v = ids_v.cpu().numpy(), d2_v.cpu().numpy()
             ex = np.array([[np.sum((X[i].astype(np.float64) - Q[q]) ** 2) for i in ids_v[q]] for q in range(nq)])
             rel = np.abs(d2_v - ex) / np.maximum(ex, 1e-30)
             variants[vs] = {"qps": round(nq / (ms / 1e3), 1), "recall@10": round(recall_at(ids_v, gt, w.k), 4),
-                            "scan_ms": round(float(scans.mean()), 4), "dist2_rel_err_max": float(rel.max())}
+                            "dist2_rel_err_max": float(rel.max())}
             if vs == "f32":
                 out["recall@10_vs_f32_path"] = round(recall_at(ids_main.cpu().numpy(), ids_v, w.k), 4)
             vi.close()
         out["variants"] = variants
     if not args.no_cpu:
         log("[bench] CPU oracle baseline ...")
-        out["cpu_baseline"] = cpu_baseline(w, X, Q, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(w, X, Q, d["nprobe"], d["p_s"], args.cpu_seconds)
     print(json.dumps(out), flush=True)
 
 

@@ -86,7 +86,8 @@ typedef struct {
   int64_t* stats;             /* device, nullable: [nq x 4] int64 per query: DCOs, dimensions
                                  read (sum of the d at which each DCO ended), candidates kept,
                                  candidates reranked */
-  int32_t record_times;       /* nonzero: time the stages with HIP events (dade_stage_times) */
+  int32_t record_times;       /* nonzero: time the stages and kernels with HIP events
+                                 (dade_stage_times) */
   int32_t fill_min;           /* >= 0: the first round holds at least this many candidates */
   int32_t growth;             /* >= 0: cap on a later round's size, as a multiple of the
                                  candidates scanned before it; 0 means no cap */
@@ -160,7 +161,7 @@ int dade_calibrate(dade_index* ix, double alpha, const int64_t* pairs, int64_t n
  * ascending by (squared distance, id), padded with (-1, +inf) after the query's K results.
  * Requires state CALIBRATED for DADE mode and >= ROTATED for FULL_D; 1 <= k <= 128;
  * nprobe >= 1; nq >= 0 (nq == 0 is a no-op).  opts may be NULL: delta_d 32, DADE mode,
- * PER_RANK, the calibrated rerank_delta, no stats or timing, fill_min 32, growth 4, graph.
+ * PER_RANK, the calibrated rerank_delta, no stats or timing, fill_min 32, growth 16, graph.
  * Asynchronous on `stream`.
  */
 int dade_search(dade_index* ix, const float* Q, int64_t nq, int32_t k, int32_t nprobe,
@@ -191,9 +192,21 @@ int dade_export(const dade_index* ix, dade_artifacts* out);
 int dade_import(const dade_artifacts* a, const float* X, const dade_build_opts* opts,
                 void* stream, dade_index** out);
 
-/* dade_stage_times -- after a dade_search with record_times set, wait for it and return the
- * elapsed milliseconds of its stages: [0] query rotation, [1] probe selection, [2] list scan. */
-int dade_stage_times(dade_index* ix, float* ms3);
+/* Stage and kernel times of the last dade_search run with record_times set (HIP events on the
+ * stream each kernel ran on).  With record_times the scan's kernels are launched one by one (not
+ * from a graph), with events around every round's kernels. */
+typedef struct {
+  float rotate_ms;          /* query centring + rotation GEMM */
+  float probe_ms;           /* centroid distances + probe selection */
+  float scan_ms;            /* the whole list scan: planning, rounds and merges */
+  float round_kernel_ms;    /* sum over rounds of the DCO kernel's duration */
+  float merge_kernel_ms;    /* sum over rounds of the merge kernel's duration */
+  float plan_ms;            /* work-item planning */
+  int32_t round_launches;   /* DCO kernel launches summed in round_kernel_ms */
+} dade_times;
+
+/* dade_stage_times -- wait for the last timed dade_search and report its times. */
+int dade_stage_times(dade_index* ix, dade_times* out);
 
 /* dade_destroy -- free the index and all its device memory (NULL is a no-op). */
 void dade_destroy(dade_index* ix);

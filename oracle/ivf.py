@@ -19,10 +19,12 @@ Readings where the paper is silent (each is a parameter or stated rule here):
 * Round schedule (fixes the threshold each DCO sees): the candidate sequence (probed lists
   concatenated in probe order) is split into rounds; every candidate of a round is compared
   against the heap as it was when the round started, and the round's accepted candidates
-  are merged in at its end.  The first round is the first K candidates (they fill the heap);
-  after it, ``per_rank`` ends a round at every list end and ``doubling`` at the ends of
-  probe ranks 1, 2, 4, 8, ...; ``sequential`` = one candidate per round in list order, i.e.
-  the heap is updated after every DCO exactly as the paper describes.
+  are merged in at its end.  The first round is the first max(K, fill_min) candidates (they
+  fill the heap); after it, ``per_rank`` ends a round at every list end and ``doubling`` at
+  the ends of probe ranks 1, 2, 4, 8, ..., and a round is also cut once it holds growth
+  times the candidates scanned before it (``round_starts``); ``sequential`` = one candidate
+  per round in list order, i.e. the heap is updated after every DCO exactly as the paper
+  describes.
 
 Low-precision index (not in the paper): tests use the stored coordinates; a survivor whose
 stored-precision S_D exceeds (1 + delta) r^2 is dropped; of the rest, the K smallest are
@@ -180,7 +182,7 @@ def round_bounds(nprobe: int, schedule: str):
 # Round-size defaults shared with the GPU path's search options (they are part of what a
 # search computes, so both sides take them as parameters).
 FILL_MIN = 32   # the first round holds at least this many candidates
-GROWTH = 4      # a later round holds at most GROWTH times the candidates before it
+GROWTH = 16     # a later round holds at most GROWTH times the candidates before it
 
 
 def round_starts(sizes, K: int, schedule: str, fill_min: int = FILL_MIN, growth: int = GROWTH) -> list:

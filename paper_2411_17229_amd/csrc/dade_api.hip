@@ -89,6 +89,10 @@ struct dade_index {
   int scan_occ[3][2][2] = {};                        // resident scan workgroups per CU
   hipEvent_t ev[4] = {};
   bool ev_made = false, ev_used = false;
+  // per-kernel events of a timed search: plan (2 per group), then per round and group
+  // (before the DCO kernel, between it and the merge, after the merge)
+  std::vector<hipEvent_t> kev;
+  int kev_rounds = 0, kev_groups = 0;
   int cus = 256;
   // query groups of a search run their rounds on their own streams (default priority), so one
   // group's merge overlaps another group's scan
@@ -296,6 +300,7 @@ void dade_destroy(dade_index* ix) {
     (void)hipStreamDestroy(ix->cap);
     (void)hipEventDestroy(ix->fork);
   }
+  for (hipEvent_t e : ix->kev) (void)hipEventDestroy(e);
   if (ix->ev_made)
     for (auto& e : ix->ev) (void)hipEventDestroy(e);
   delete ix;
@@ -650,17 +655,26 @@ int dade_import(const dade_artifacts* a, const float* X, const dade_build_opts* 
 
 // The round launches of one pass: groups on their own streams, forked from and joined to s.
 static hipError_t enqueue_rounds(dade_index* ix, const RoundArgs* ga, const hipStream_t* gs, int ng, int rounds,
-                                 int64_t gsz, hipStream_t s) {
+                                 int64_t gsz, bool timed, hipStream_t s) {
   hipError_t e;
 #define ENQ(x) \
   if ((e = (x)) != hipSuccess) return e
   if (ng > 1) ENQ(hipEventRecord(ix->fork, s));
   for (int g = 1; g < ng; ++g) ENQ(hipStreamWaitEvent(gs[g], ix->fork, 0));
-  for (int g = 0; g < ng; ++g) ENQ(launch_plan(ga[g], ix->w_counts + int64_t(rounds) * g * gsz, gs[g]));
+  hipEvent_t* kev = timed ? ix->kev.data() : nullptr;   // layout: see dade_index::kev
+  for (int g = 0; g < ng; ++g) {
+    if (kev) ENQ(hipEventRecord(kev[2 * g], gs[g]));
+    ENQ(launch_plan(ga[g], ix->w_counts + int64_t(rounds) * g * gsz, gs[g]));
+    if (kev) ENQ(hipEventRecord(kev[2 * g + 1], gs[g]));
+  }
   for (int r = 0; r < rounds; ++r)
     for (int g = 0; g < ng; ++g) {
+      hipEvent_t* ke = kev ? kev + 2 * ng + 3 * (int64_t(r) * ng + g) : nullptr;
+      if (ke) ENQ(hipEventRecord(ke[0], gs[g]));
       ENQ(launch_round(ga[g], r, gs[g]));
+      if (ke) ENQ(hipEventRecord(ke[1], gs[g]));
       ENQ(launch_merge(ga[g], r, gs[g]));
+      if (ke) ENQ(hipEventRecord(ke[2], gs[g]));
     }
   for (int g = 1; g < ng; ++g) {
     ENQ(hipEventRecord(ix->join[g], gs[g]));
@@ -679,7 +693,7 @@ int dade_search(dade_index* ix, const float* Q, int64_t nq, int32_t k, int32_t n
   if (nprobe < 1) FAIL(DADE_EINVAL, "nprobe must be >= 1");
   dade_search_opts o{};
   o.delta_d = 0; o.mode = DADE_MODE_DADE; o.schedule = DADE_SCHED_PER_RANK; o.rerank_delta = -1.f;
-  o.fill_min = 32; o.growth = 4; o.use_graph = 1;
+  o.fill_min = 32; o.growth = 16; o.use_graph = 1;
   if (opts) o = *opts;
   if (o.fill_min < 0 || o.growth < 0) FAIL(DADE_EINVAL, "fill_min and growth must be >= 0");
   const int dd = o.delta_d > 0 ? o.delta_d : std::min(32, ix->dim);
@@ -828,7 +842,17 @@ int dade_search(dade_index* ix, const float* Q, int64_t nq, int32_t k, int32_t n
     }
     // the launch sequence of this pass; replayed from a captured graph when it is the same as
     // the last captured one (a whole batch in one pass)
-    const bool graph = o.use_graph && chunk >= nq;
+    const bool graph = o.use_graph && !o.record_times && chunk >= nq;
+    if (o.record_times) {   // events for this pass (the last pass's times are reported)
+      const size_t need = size_t(2 * ng + 3 * rounds * ng);
+      while (ix->kev.size() < need) {
+        hipEvent_t e;
+        HIPC(hipEventCreate(&e));
+        ix->kev.push_back(e);
+      }
+      ix->kev_rounds = rounds;
+      ix->kev_groups = ng;
+    }
     std::vector<unsigned char> key;
     if (graph) {
       key.resize(sizeof(RoundArgs) * ng + 3 * sizeof(int));
@@ -842,7 +866,7 @@ int dade_search(dade_index* ix, const float* Q, int64_t nq, int32_t k, int32_t n
       gstream[0] = ix->cap;
       HIPC(hipStreamBeginCapture(ix->cap, hipStreamCaptureModeRelaxed));
     }
-    hipError_t e = enqueue_rounds(ix, ga, gstream, ng, rounds, gsz, gstream[0]);
+    hipError_t e = enqueue_rounds(ix, ga, gstream, ng, rounds, gsz, o.record_times != 0, gstream[0]);
     if (graph) {
       hipGraph_t g = nullptr;
       const hipError_t e2 = hipStreamEndCapture(ix->cap, &g);
@@ -877,11 +901,32 @@ int dade_check(dade_index* ix, void* stream) {
   return DADE_OK;
 }
 
-int dade_stage_times(dade_index* ix, float* ms3) {
-  if (!ix || !ms3) FAIL(DADE_EINVAL, "index or output is NULL");
+int dade_stage_times(dade_index* ix, dade_times* out) {
+  if (!ix || !out) FAIL(DADE_EINVAL, "index or output is NULL");
   if (!ix->ev_used) FAIL(DADE_ESTATE, "no timed search was recorded");
   HIPC(hipEventSynchronize(ix->ev[3]));
-  for (int i = 0; i < 3; ++i) HIPC(hipEventElapsedTime(&ms3[i], ix->ev[i], ix->ev[i + 1]));
+  float ms[3];
+  for (int i = 0; i < 3; ++i) HIPC(hipEventElapsedTime(&ms[i], ix->ev[i], ix->ev[i + 1]));
+  *out = dade_times{};
+  out->rotate_ms = ms[0];
+  out->probe_ms = ms[1];
+  out->scan_ms = ms[2];
+  const int ng = ix->kev_groups;
+  for (int g = 0; g < ng; ++g) {
+    float t;
+    HIPC(hipEventElapsedTime(&t, ix->kev[2 * g], ix->kev[2 * g + 1]));
+    out->plan_ms += t;
+  }
+  for (int r = 0; r < ix->kev_rounds; ++r)
+    for (int g = 0; g < ng; ++g) {
+      const hipEvent_t* e = ix->kev.data() + 2 * ng + 3 * (int64_t(r) * ng + g);
+      float t1, t2;
+      HIPC(hipEventElapsedTime(&t1, e[0], e[1]));
+      HIPC(hipEventElapsedTime(&t2, e[1], e[2]));
+      out->round_kernel_ms += t1;
+      out->merge_kernel_ms += t2;
+      ++out->round_launches;
+    }
   return DADE_OK;
 }
 

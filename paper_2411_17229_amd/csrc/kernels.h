@@ -91,7 +91,7 @@ struct RoundArgs {
   int delta_d = 32;
   int schedule = 0;     // 0 per-rank, 1 doubling
   int fill_min = 32;    // the first round holds at least this many candidates
-  int growth = 4;       // a later round holds at most growth x the candidates before it (0: any)
+  int growth = 16;      // a later round holds at most growth x the candidates before it (0: any)
   int mode = 0;         // 0 DADE, 1 FULL_D
   int dtype = 0;        // stored coordinates: 0 f32, 1 bf16, 2 f16
   int k_max = 0;

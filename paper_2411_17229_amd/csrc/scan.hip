@@ -357,7 +357,6 @@ __global__ __launch_bounds__(kThreads) void scan_round_kernel(RoundArgs a, int r
     }
     const bool has = lane < cnt;
     const int p = it.z + (has ? lane : 0);
-    const uint32_t rid = uint32_t(a.ids[p]);
     float S = 0.f;
     bool rej = false, done = true;
     int dexit = dim;
@@ -376,6 +375,7 @@ __global__ __launch_bounds__(kThreads) void scan_round_kernel(RoundArgs a, int r
       done = rej || nb0 >= nblk;
     }
     const bool fin = has && done;
+    const uint32_t rid = fin && !rej ? uint32_t(a.ids[p]) : 0u;   // ids only of finished DCOs
     append_keys(a, q, fin && !rej && passes<RERANK>(S, rid, full, keyr, gate_f * r2), make_key(S, rid), lane);
     if (a.stats) add_stats(a, q, fin, dexit, lane);
     const bool deep = has && !done;

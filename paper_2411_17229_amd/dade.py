@@ -44,6 +44,12 @@ class SearchOpts(ctypes.Structure):
                 ("use_graph", ctypes.c_int32)]
 
 
+class Times(ctypes.Structure):
+    _fields_ = [("rotate_ms", ctypes.c_float), ("probe_ms", ctypes.c_float), ("scan_ms", ctypes.c_float),
+                ("round_kernel_ms", ctypes.c_float), ("merge_kernel_ms", ctypes.c_float),
+                ("plan_ms", ctypes.c_float), ("round_launches", ctypes.c_int32)]
+
+
 class Artifacts(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("dim", ctypes.c_int32), ("nlist", ctypes.c_int32),
                 ("store_dtype", ctypes.c_int32), ("state", ctypes.c_int32),
@@ -72,7 +78,7 @@ def lib():
         L.dade_index_info.argtypes = [vp] + [ctypes.POINTER(t) for t in (i64, i32, i32, i32, i32)]
         L.dade_export.argtypes = [vp, ctypes.POINTER(Artifacts)]
         L.dade_import.argtypes = [ctypes.POINTER(Artifacts), vp, ctypes.POINTER(BuildOpts), vp, pp]
-        L.dade_stage_times.argtypes = [vp, ctypes.POINTER(ctypes.c_float)]
+        L.dade_stage_times.argtypes = [vp, ctypes.POINTER(Times)]
         L.dade_destroy.argtypes = [vp]
         L.dade_destroy.restype = None
         L.dade_last_error.restype = ctypes.c_char_p
@@ -162,7 +168,7 @@ def dade_calibrate(ix: Index, alpha=0.1, pairs=None, n_pairs=100_000, seed=0, st
 
 def dade_search(ix: Index, Q, k, nprobe, k_per_query=None, nprobe_per_query=None, delta_d=0,
                 mode="dade", schedule="per_rank", rerank_delta=-1.0, stats=None, record_times=False,
-                out_ids=None, out_dist2=None, stream=None, fill_min=32, growth=4, use_graph=True):
+                out_ids=None, out_dist2=None, stream=None, fill_min=32, growth=16, use_graph=True):
     """Returns (ids [nq, k] int64, dist2 [nq, k] float32) device tensors (asynchronous)."""
     import torch
     qp = _dev(Q, torch.float32, "Q")
@@ -239,9 +245,9 @@ def dade_import(art: dict, X, store="f32", hbm_budget_bytes=0, stream=None) -> I
 
 
 def dade_stage_times(ix: Index):
-    ms = (ctypes.c_float * 3)()
-    _check(lib().dade_stage_times(ix.handle, ms))
-    return {"rotate_ms": ms[0], "probe_ms": ms[1], "scan_ms": ms[2]}
+    t = Times()
+    _check(lib().dade_stage_times(ix.handle, ctypes.byref(t)))
+    return {name: getattr(t, name) for name, _ in Times._fields_}
 
 
 def dade_destroy(ix: Index):
