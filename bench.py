@@ -148,6 +148,9 @@ def main():
     ap.add_argument("--nprobe", type=int, default=None)
     ap.add_argument("--p-s", type=float, default=None)
     ap.add_argument("--mode", default="dade")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="with --profile-only: launch the scan kernels one by one (counter collection "
+                         "does not see kernels replayed from a graph)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy 5 times (HBM counter calibration)")
     args = ap.parse_args()
@@ -187,7 +190,7 @@ def main():
 
     if args.profile_only:
         npb = args.nprobe or w.nprobe
-        kw = dict(delta_d=w.delta_d, mode=args.mode, **SCHEDULE)
+        kw = dict(delta_d=w.delta_d, mode=args.mode, use_graph=not args.no_graph, **SCHEDULE)
         ms = throughput(dade, torch, ix, Qd, w.k, npb, args.steps, args.warmup, **kw)
         log(f"[bench] profile run ({args.mode}, nprobe {npb}, P_s {args.p_s or w.alpha}): {ms:.3f} ms/step")
         return

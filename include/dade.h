@@ -196,8 +196,8 @@ int dade_import(const dade_artifacts* a, const float* X, const dade_build_opts* 
  * stream each kernel ran on).  With record_times the scan's kernels are launched one by one (not
  * from a graph), with events around every round's kernels. */
 typedef struct {
-  float rotate_ms;          /* query centring + rotation GEMM */
-  float probe_ms;           /* centroid distances + probe selection */
+  float query_gemm_ms;      /* one GEMM: rotated queries and query-centroid distances */
+  float select_ms;          /* probe selection */
   float scan_ms;            /* the whole list scan: planning, rounds and merges */
   float round_kernel_ms;    /* sum over rounds of the DCO kernel's duration */
   float merge_kernel_ms;    /* sum over rounds of the merge kernel's duration */

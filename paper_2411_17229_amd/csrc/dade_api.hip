@@ -63,10 +63,9 @@ struct dade_index {
   int64_t* d_off = nullptr;    // [nlist + 1]
   int32_t* d_ids = nullptr;    // [n] packed position -> row id
   int64_t* d_pos = nullptr;    // [n] row id -> packed position
-  float* d_W = nullptr;        // [dp x dp] FP32 copy of W (zero padded)
+  float* d_B = nullptr;        // [dp x (dp + nlist)] FP32 [W | (C - mu)^T] (zero padded)
   float* d_mu = nullptr;       // [dp]
-  float* d_cent_rot = nullptr; // [nlist x dp]
-  float* d_cent_norm = nullptr;// [nlist]
+  float* d_cent_norm = nullptr;// [nlist] ||c - mu||^2
   void* d_store = nullptr;     // rotated coordinates in list order, head/tail layout (stored_index)
   float* d_T = nullptr;        // [dim]
   // host artifacts
@@ -89,19 +88,12 @@ struct dade_index {
   int scan_occ[3][2][2] = {};                        // resident scan workgroups per CU
   hipEvent_t ev[4] = {};
   bool ev_made = false, ev_used = false;
-  // per-kernel events of a timed search: plan (2 per group), then per round and group
-  // (before the DCO kernel, between it and the merge, after the merge)
+  // per-kernel events of a timed search: plan (before, after), then per round (before the DCO
+  // kernel, between it and the merge, after the merge)
   std::vector<hipEvent_t> kev;
-  int kev_rounds = 0, kev_groups = 0;
+  int kev_rounds = 0;
   int cus = 256;
-  // query groups of a search run their rounds on their own streams (default priority), so one
-  // group's merge overlaps another group's scan
-  static constexpr int kGroups = 4;
-  int n_groups = 1;   // groups a search uses (1 .. kGroups)
-  hipStream_t grp[kGroups] = {};
   hipStream_t cap = nullptr;   // origin stream of graph captures (the caller's may be the null stream)
-  hipEvent_t fork = nullptr, join[kGroups] = {};
-  bool grp_made = false;
   // the last captured round-launch sequence and the argument bytes it was captured with
   hipGraphExec_t graph_exec = nullptr;
   std::vector<unsigned char> graph_key;
@@ -222,49 +214,39 @@ int set_lists(dade_index* ix, const std::vector<int32_t>& lab, hipStream_t s) {
   return DADE_OK;
 }
 
-// Store W (host FP64) on the device, rotate the centroids, pack the store.
+// Store [W | (C - mu)^T] (host FP64 -> FP32) and ||c - mu||^2 on the device, pack the store.
+// The query GEMM multiplies (q - mu) by this matrix: its first dp columns give q' = W^T (q - mu),
+// the others (q - mu).(c - mu); W is orthogonal, so ||q' - c'||^2 = ||q - c||^2 (Lemma 1).
 int apply_transform(dade_index* ix, hipStream_t s) {
   const int dim = ix->dim, dp = ix->dp, nl = ix->nlist;
+  const int64_t ldb = int64_t(dp) + nl;
   int rc;
-  std::vector<float> Wf(size_t(dp) * dp, 0.f), muf(dp, 0.f);
+  std::vector<float> Bf(size_t(dp) * ldb, 0.f), muf(dp, 0.f), cn(nl, 0.f);
   for (int i = 0; i < dim; ++i)
-    for (int k = 0; k < dim; ++k) Wf[size_t(i) * dp + k] = float(ix->W[size_t(i) * dim + k]);
+    for (int k = 0; k < dim; ++k) Bf[size_t(i) * ldb + k] = float(ix->W[size_t(i) * dim + k]);
+  for (int l = 0; l < nl; ++l) {
+    double nrm = 0.0;
+    for (int i = 0; i < dim; ++i) {
+      const double v = ix->cent_h[size_t(l) * dim + i] - ix->mu[i];
+      Bf[size_t(i) * ldb + dp + l] = float(v);
+      nrm += v * v;
+    }
+    cn[l] = float(nrm);
+  }
   for (int i = 0; i < dim; ++i) muf[i] = float(ix->mu[i]);
-  if (!ix->d_W && (rc = alloc_t(ix, &ix->d_W, size_t(dp) * dp))) return rc;
+  if (!ix->d_B && (rc = alloc_t(ix, &ix->d_B, Bf.size()))) return rc;
   if (!ix->d_mu && (rc = alloc_t(ix, &ix->d_mu, dp))) return rc;
-  HIPC(hipMemcpyAsync(ix->d_W, Wf.data(), sizeof(float) * Wf.size(), hipMemcpyHostToDevice, s));
-  HIPC(hipMemcpyAsync(ix->d_mu, muf.data(), sizeof(float) * dp, hipMemcpyHostToDevice, s));
-
-  // rotated centroids c' = W^T (c - mu) in FP64 on the device
-  double *dA = nullptr, *dWd = nullptr, *dC = nullptr;
-  std::vector<double> A(size_t(nl) * dim);
-  for (int l = 0; l < nl; ++l)
-    for (int i = 0; i < dim; ++i) A[size_t(l) * dim + i] = ix->cent_h[size_t(l) * dim + i] - ix->mu[i];
-  if ((rc = alloc_t(ix, &dA, A.size()))) return rc;
-  if ((rc = alloc_t(ix, &dWd, size_t(dim) * dim))) { dev_free(ix, dA, A.size() * 8); return rc; }
-  if ((rc = alloc_t(ix, &dC, A.size()))) { dev_free(ix, dA, A.size() * 8); dev_free(ix, dWd, size_t(dim) * dim * 8); return rc; }
-  HIPC(hipMemcpyAsync(dA, A.data(), sizeof(double) * A.size(), hipMemcpyHostToDevice, s));
-  HIPC(hipMemcpyAsync(dWd, ix->W.data(), sizeof(double) * size_t(dim) * dim, hipMemcpyHostToDevice, s));
-  HIPC(launch_dgemm(dA, dim, dWd, dim, dC, dim, nl, dim, dim, s));
-  HIPC(hipMemcpyAsync(A.data(), dC, sizeof(double) * A.size(), hipMemcpyDeviceToHost, s));
-  HIPC(hipStreamSynchronize(s));
-  dev_free(ix, dA, A.size() * 8);
-  dev_free(ix, dWd, size_t(dim) * dim * 8);
-  dev_free(ix, dC, A.size() * 8);
-  std::vector<float> cr(size_t(nl) * dp, 0.f);
-  for (int l = 0; l < nl; ++l)
-    for (int i = 0; i < dim; ++i) cr[size_t(l) * dp + i] = float(A[size_t(l) * dim + i]);
-  if (!ix->d_cent_rot && (rc = alloc_t(ix, &ix->d_cent_rot, cr.size()))) return rc;
   if (!ix->d_cent_norm && (rc = alloc_t(ix, &ix->d_cent_norm, nl))) return rc;
-  HIPC(hipMemcpyAsync(ix->d_cent_rot, cr.data(), sizeof(float) * cr.size(), hipMemcpyHostToDevice, s));
-  HIPC(launch_row_norms(ix->d_cent_rot, nl, dp, ix->d_cent_norm, s));
+  HIPC(hipMemcpyAsync(ix->d_B, Bf.data(), sizeof(float) * Bf.size(), hipMemcpyHostToDevice, s));
+  HIPC(hipMemcpyAsync(ix->d_mu, muf.data(), sizeof(float) * dp, hipMemcpyHostToDevice, s));
+  HIPC(hipMemcpyAsync(ix->d_cent_norm, cn.data(), sizeof(float) * nl, hipMemcpyHostToDevice, s));
 
   // packed store: row p = W^T (X[ids[p]] - mu), in list order
   if (!ix->d_store && (rc = dev_alloc(ix, &ix->d_store, size_t(ix->n) * dp * dtype_size(ix->store)))) return rc;
   GemmArgs g;
   g.M = int(ix->n); g.N = dp; g.K = dp;
   g.A = ix->X; g.lda = dp; g.a_rows = ix->d_ids; g.a_shift = ix->d_mu;
-  g.B = ix->d_W; g.ldb = dp; g.C = ix->d_store; g.ldc = dp; g.split_rows = ix->n;
+  g.B = ix->d_B; g.ldb = int(ldb); g.C = ix->d_store; g.ldc = dp; g.split_rows = ix->n;
   const GemmEpilogue epi = ix->store == DADE_F32 ? kEpiPackF32 : (ix->store == DADE_BF16 ? kEpiPackBF16 : kEpiPackF16);
   HIPC(launch_gemm(g, epi, s));
   HIPC(hipStreamSynchronize(s));
@@ -292,14 +274,7 @@ void dade_destroy(dade_index* ix) {
   (void)hipDeviceSynchronize();
   for (void* p : ix->owned) (void)hipFree(p);
   if (ix->graph_exec) (void)hipGraphExecDestroy(ix->graph_exec);
-  if (ix->grp_made) {
-    for (int g = 1; g < dade_index::kGroups; ++g) {
-      (void)hipStreamDestroy(ix->grp[g]);
-      (void)hipEventDestroy(ix->join[g]);
-    }
-    (void)hipStreamDestroy(ix->cap);
-    (void)hipEventDestroy(ix->fork);
-  }
+  if (ix->cap) (void)hipStreamDestroy(ix->cap);
   for (hipEvent_t e : ix->kev) (void)hipEventDestroy(e);
   if (ix->ev_made)
     for (auto& e : ix->ev) (void)hipEventDestroy(e);
@@ -653,32 +628,22 @@ int dade_import(const dade_artifacts* a, const float* X, const dade_build_opts* 
   return DADE_OK;
 }
 
-// The round launches of one pass: groups on their own streams, forked from and joined to s.
-static hipError_t enqueue_rounds(dade_index* ix, const RoundArgs* ga, const hipStream_t* gs, int ng, int rounds,
-                                 int64_t gsz, bool timed, hipStream_t s) {
+// The launches of one pass of the list scan: planning, then each round's DCO and merge kernels.
+static hipError_t enqueue_rounds(dade_index* ix, const RoundArgs& a, int rounds, bool timed, hipStream_t s) {
   hipError_t e;
 #define ENQ(x) \
   if ((e = (x)) != hipSuccess) return e
-  if (ng > 1) ENQ(hipEventRecord(ix->fork, s));
-  for (int g = 1; g < ng; ++g) ENQ(hipStreamWaitEvent(gs[g], ix->fork, 0));
   hipEvent_t* kev = timed ? ix->kev.data() : nullptr;   // layout: see dade_index::kev
-  for (int g = 0; g < ng; ++g) {
-    if (kev) ENQ(hipEventRecord(kev[2 * g], gs[g]));
-    ENQ(launch_plan(ga[g], ix->w_counts + int64_t(rounds) * g * gsz, gs[g]));
-    if (kev) ENQ(hipEventRecord(kev[2 * g + 1], gs[g]));
-  }
-  for (int r = 0; r < rounds; ++r)
-    for (int g = 0; g < ng; ++g) {
-      hipEvent_t* ke = kev ? kev + 2 * ng + 3 * (int64_t(r) * ng + g) : nullptr;
-      if (ke) ENQ(hipEventRecord(ke[0], gs[g]));
-      ENQ(launch_round(ga[g], r, gs[g]));
-      if (ke) ENQ(hipEventRecord(ke[1], gs[g]));
-      ENQ(launch_merge(ga[g], r, gs[g]));
-      if (ke) ENQ(hipEventRecord(ke[2], gs[g]));
-    }
-  for (int g = 1; g < ng; ++g) {
-    ENQ(hipEventRecord(ix->join[g], gs[g]));
-    ENQ(hipStreamWaitEvent(s, ix->join[g], 0));
+  if (kev) ENQ(hipEventRecord(kev[0], s));
+  ENQ(launch_plan(a, ix->w_counts, s));
+  if (kev) ENQ(hipEventRecord(kev[1], s));
+  for (int r = 0; r < rounds; ++r) {
+    hipEvent_t* ke = kev ? kev + 2 + 3 * r : nullptr;
+    if (ke) ENQ(hipEventRecord(ke[0], s));
+    ENQ(launch_round(a, r, s));
+    if (ke) ENQ(hipEventRecord(ke[1], s));
+    ENQ(launch_merge(a, r, s));
+    if (ke) ENQ(hipEventRecord(ke[2], s));
   }
 #undef ENQ
   return hipSuccess;
@@ -733,12 +698,9 @@ int dade_search(dade_index* ix, const float* Q, int64_t nq, int32_t k, int32_t n
   // work items of one query in one round: its segments cut at 16 candidates (whole-row rounds;
   // other rounds use 64)
   const int64_t items_pq = std::max<int64_t>((kb_cap + 15) / 16 + widest + 1, (first + 15) / 16 + npm);
-  // queries per pass: the round workspace stays under 1 GiB; a pass is split into groups
+  // queries per pass: the round workspace stays under 1 GiB
   const int64_t per_q = kb_cap * 8 + rounds * (items_pq * 16 + 4) + int64_t(k) * 8 + 48;
   const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(nq, (int64_t(1) << 30) / per_q));
-  const int groups = int(std::min<int64_t>(ix->n_groups, chunk));
-  const int64_t gsz = (chunk + groups - 1) / groups;
-  const int cstride = (rounds + 63) / 64 * 64;   // per group: n_items[rounds]
   // workspace
   if (nq > ix->w_nq || npm > ix->w_np) {
     const int64_t new_nq = std::max(nq, ix->w_nq), new_np = std::max<int64_t>(npm, ix->w_np);
@@ -758,23 +720,15 @@ int dade_search(dade_index* ix, const float* Q, int64_t nq, int32_t k, int32_t n
   if ((rc = grow(ix, &ix->w_topk, ix->w_topk_n, chunk * k, s)) || (rc = grow(ix, &ix->w_keyr, ix->w_keyr_n, chunk, s)) ||
       (rc = grow(ix, &ix->w_r2, ix->w_r2_n, chunk, s)) || (rc = grow(ix, &ix->w_qint, ix->w_qint_n, chunk * 3, s)) ||
       (rc = grow(ix, &ix->w_kb, ix->w_kb_n, chunk * kb_cap, s)) ||
-      (rc = grow(ix, &ix->w_items, ix->w_items_n, int64_t(rounds) * groups * gsz * items_pq, s)) ||
-      (rc = grow(ix, &ix->w_counter, ix->w_counter_n, int64_t(cstride) * groups, s)) ||
-      (rc = grow(ix, &ix->w_counts, ix->w_counts_n, int64_t(rounds) * groups * gsz, s)))
+      (rc = grow(ix, &ix->w_items, ix->w_items_n, int64_t(rounds) * chunk * items_pq, s)) ||
+      (rc = grow(ix, &ix->w_counter, ix->w_counter_n, rounds, s)) ||
+      (rc = grow(ix, &ix->w_counts, ix->w_counts_n, int64_t(rounds) * chunk, s)))
     return rc;
   if (!ix->w_flags) {
     if ((rc = alloc_t(ix, &ix->w_flags, 1))) return rc;
     HIPC(launch_fill_i32(ix->w_flags, 1, 0, s));
   }
-  if (!ix->grp_made) {
-    HIPC(hipEventCreateWithFlags(&ix->fork, hipEventDisableTiming));
-    for (int g = 1; g < dade_index::kGroups; ++g) {
-      HIPC(hipStreamCreateWithFlags(&ix->grp[g], hipStreamNonBlocking));
-      HIPC(hipEventCreateWithFlags(&ix->join[g], hipEventDisableTiming));
-    }
-    HIPC(hipStreamCreateWithFlags(&ix->cap, hipStreamNonBlocking));
-    ix->grp_made = true;
-  }
+  if (!ix->cap) HIPC(hipStreamCreateWithFlags(&ix->cap, hipStreamNonBlocking));
   int& occ = ix->scan_occ[ix->store][o.mode][dd % 8 != 0];
   if (occ == 0) occ = round_blocks_per_cu(ix->store, o.mode, dd);
   if (o.record_times && !ix->ev_made) {
@@ -782,21 +736,17 @@ int dade_search(dade_index* ix, const float* Q, int64_t nq, int32_t k, int32_t n
     ix->ev_made = true;
   }
   if (o.record_times) HIPC(hipEventRecord(ix->ev[0], s));
-  // a1: q' = W^T (q - mu)
+  // a1 + a2: one GEMM gives q' = W^T (q - mu) and the centroid distances (up to ||q - mu||^2,
+  // the same for every list); then the probe order by (distance, list id)
   HIPC(launch_pad_rows(Q, nq, ix->dim, ix->w_qpad, dp, s));
   GemmArgs g;
-  g.M = int(nq); g.N = dp; g.K = dp;
+  g.M = int(nq); g.N = dp + nl; g.K = dp;
   g.A = ix->w_qpad; g.lda = dp; g.a_shift = ix->d_mu;
-  g.B = ix->d_W; g.ldb = dp; g.C = ix->w_qrot; g.ldc = dp;
-  HIPC(launch_gemm(g, kEpiStore, s));
+  g.B = ix->d_B; g.ldb = dp + nl; g.C = ix->w_qrot; g.ldc = dp;
+  g.split_col = dp; g.C2 = ix->w_pd; g.ldc2 = nl; g.col_norm = ix->d_cent_norm;
+  HIPC(launch_gemm(g, kEpiRotateProbe, s));
   if (o.record_times) HIPC(hipEventRecord(ix->ev[1], s));
-  // a2: probe order by (squared centroid distance, list id)
-  GemmArgs p;
-  p.M = int(nq); p.N = nl; p.K = dp;
-  p.A = ix->w_qrot; p.lda = dp; p.B = ix->d_cent_rot; p.ldb = dp; p.b_trans = true;
-  p.C = ix->w_pd; p.ldc = nl; p.col_norm = ix->d_cent_norm;
-  HIPC(launch_gemm(p, kEpiProbe, s));
-  HIPC(launch_select_probes(ix->w_pd, nl, ix->w_qrot, dp, int(nq), dp, nl, npm, ix->w_probes, s));
+  HIPC(launch_select_probes(ix->w_pd, nl, int(nq), nl, npm, ix->w_probes, s));
   if (o.record_times) HIPC(hipEventRecord(ix->ev[2], s));
   // a3-a6: the list scan, in rounds, `chunk` queries at a time
   RoundArgs ra;
@@ -813,60 +763,48 @@ int dade_search(dade_index* ix, const float* Q, int64_t nq, int32_t k, int32_t n
   ra.kb_cap = kb_cap;
   ra.rounds = rounds;
   ra.grid = ix->cus * occ;
-  RoundArgs ga[dade_index::kGroups];
-  hipStream_t gstream[dade_index::kGroups];
   for (int64_t c0 = 0; c0 < nq; c0 += chunk) {
     const int64_t cn = std::min(chunk, nq - c0);
-    int ng = 0;
-    for (int g = 0; g < groups; ++g) {
-      const int64_t g0 = std::min(cn, g * gsz), gn = std::min(cn, g0 + gsz) - g0;
-      if (gn <= 0) continue;
-      RoundArgs& a = ga[ng];
-      std::memcpy(&a, &ra, sizeof ra);
-      const int64_t q0 = c0 + g0;
-      a.nq = int(gn);
-      a.k_pq = k_per_query ? k_per_query + q0 : nullptr;
-      a.nprobe_pq = nprobe_per_query ? nprobe_per_query + q0 : nullptr;
-      a.qrot = ix->w_qrot + q0 * dp; a.qorig = ix->w_qpad + q0 * dp;
-      a.probes = ix->w_probes + q0 * npm;
-      a.out_ids = out_ids + q0 * k; a.out_d2 = out_dist2 + q0 * k;
-      a.stats = o.stats ? o.stats + q0 * 4 : nullptr;
-      a.q_topk = ix->w_topk + g0 * k; a.q_keyr = ix->w_keyr + g0; a.q_r2 = ix->w_r2 + g0;
-      a.q_topn = ix->w_qint + 3 * g0; a.q_kc = a.q_topn + gn; a.q_rounds = a.q_topn + 2 * gn;
-      a.kb = ix->w_kb + g0 * kb_cap;
-      a.items_cap = int(std::min<int64_t>(gsz * items_pq, INT32_MAX));
-      a.items = ix->w_items + int64_t(rounds) * g * a.items_cap;
-      a.n_items = ix->w_counter + int64_t(cstride) * g; a.overflow = ix->w_flags;
-      gstream[ng] = ng == 0 ? s : ix->grp[ng];
-      ++ng;
-    }
-    // the launch sequence of this pass; replayed from a captured graph when it is the same as
-    // the last captured one (a whole batch in one pass)
-    const bool graph = o.use_graph && !o.record_times && chunk >= nq;
+    RoundArgs a;
+    std::memcpy(&a, &ra, sizeof ra);
+    a.nq = int(cn);
+    a.k_pq = k_per_query ? k_per_query + c0 : nullptr;
+    a.nprobe_pq = nprobe_per_query ? nprobe_per_query + c0 : nullptr;
+    a.qrot = ix->w_qrot + c0 * dp; a.qorig = ix->w_qpad + c0 * dp;
+    a.probes = ix->w_probes + c0 * npm;
+    a.out_ids = out_ids + c0 * k; a.out_d2 = out_dist2 + c0 * k;
+    a.stats = o.stats ? o.stats + c0 * 4 : nullptr;
+    a.q_topk = ix->w_topk; a.q_keyr = ix->w_keyr; a.q_r2 = ix->w_r2;
+    a.q_topn = ix->w_qint; a.q_kc = a.q_topn + cn; a.q_rounds = a.q_topn + 2 * cn;
+    a.kb = ix->w_kb;
+    a.items_cap = int(std::min<int64_t>(chunk * items_pq, INT32_MAX));
+    a.items = ix->w_items;
+    a.n_items = ix->w_counter; a.overflow = ix->w_flags;
     if (o.record_times) {   // events for this pass (the last pass's times are reported)
-      const size_t need = size_t(2 * ng + 3 * rounds * ng);
-      while (ix->kev.size() < need) {
+      while (ix->kev.size() < size_t(2 + 3 * rounds)) {
         hipEvent_t e;
         HIPC(hipEventCreate(&e));
         ix->kev.push_back(e);
       }
       ix->kev_rounds = rounds;
-      ix->kev_groups = ng;
     }
+    // the launch sequence of this pass; replayed from a captured graph when it is the same as
+    // the last captured one (a whole batch in one pass).  Captures start on an internal stream
+    // (the caller's may be the null stream, which cannot be captured).
+    const bool graph = o.use_graph && !o.record_times && chunk >= nq;
     std::vector<unsigned char> key;
     if (graph) {
-      key.resize(sizeof(RoundArgs) * ng + 3 * sizeof(int));
-      std::memcpy(key.data(), ga, sizeof(RoundArgs) * ng);
-      const int tail[3] = {ng, rounds, ix->device};
-      std::memcpy(key.data() + sizeof(RoundArgs) * ng, tail, sizeof tail);
+      key.resize(sizeof(RoundArgs) + 2 * sizeof(int));
+      std::memcpy(key.data(), &a, sizeof(RoundArgs));
+      const int tail[2] = {rounds, ix->device};
+      std::memcpy(key.data() + sizeof(RoundArgs), tail, sizeof tail);
       if (ix->graph_exec && key == ix->graph_key) {
         HIPC(hipGraphLaunch(ix->graph_exec, s));
         continue;
       }
-      gstream[0] = ix->cap;
       HIPC(hipStreamBeginCapture(ix->cap, hipStreamCaptureModeRelaxed));
     }
-    hipError_t e = enqueue_rounds(ix, ga, gstream, ng, rounds, gsz, o.record_times != 0, gstream[0]);
+    hipError_t e = enqueue_rounds(ix, a, rounds, o.record_times != 0, graph ? ix->cap : s);
     if (graph) {
       hipGraph_t g = nullptr;
       const hipError_t e2 = hipStreamEndCapture(ix->cap, &g);
@@ -908,25 +846,19 @@ int dade_stage_times(dade_index* ix, dade_times* out) {
   float ms[3];
   for (int i = 0; i < 3; ++i) HIPC(hipEventElapsedTime(&ms[i], ix->ev[i], ix->ev[i + 1]));
   *out = dade_times{};
-  out->rotate_ms = ms[0];
-  out->probe_ms = ms[1];
+  out->query_gemm_ms = ms[0];
+  out->select_ms = ms[1];
   out->scan_ms = ms[2];
-  const int ng = ix->kev_groups;
-  for (int g = 0; g < ng; ++g) {
-    float t;
-    HIPC(hipEventElapsedTime(&t, ix->kev[2 * g], ix->kev[2 * g + 1]));
-    out->plan_ms += t;
+  HIPC(hipEventElapsedTime(&out->plan_ms, ix->kev[0], ix->kev[1]));
+  for (int r = 0; r < ix->kev_rounds; ++r) {
+    const hipEvent_t* e = ix->kev.data() + 2 + 3 * r;
+    float t1, t2;
+    HIPC(hipEventElapsedTime(&t1, e[0], e[1]));
+    HIPC(hipEventElapsedTime(&t2, e[1], e[2]));
+    out->round_kernel_ms += t1;
+    out->merge_kernel_ms += t2;
+    ++out->round_launches;
   }
-  for (int r = 0; r < ix->kev_rounds; ++r)
-    for (int g = 0; g < ng; ++g) {
-      const hipEvent_t* e = ix->kev.data() + 2 * ng + 3 * (int64_t(r) * ng + g);
-      float t1, t2;
-      HIPC(hipEventElapsedTime(&t1, e[0], e[1]));
-      HIPC(hipEventElapsedTime(&t2, e[1], e[2]));
-      out->round_kernel_ms += t1;
-      out->merge_kernel_ms += t2;
-      ++out->round_launches;
-    }
   return DADE_OK;
 }
 

@@ -1,14 +1,15 @@
 // FP32 GEMM on gfx950 matrix cores (v_mfma_f32_32x32x2_f32) with fused epilogues.
 //
-// Used for the dense contractions of the path: the query rotation Q' = (Q - mu) W, the
-// query-centroid distances of probe selection, the k-means assignment (argmin fused, no
+// Used for the dense contractions of the path: the query rotation Q' = (Q - mu) W fused with
+// the query-centroid distances of probe selection (one GEMM against [W | (C - mu)^T]; W is
+// orthogonal, so (q - mu).(c - mu) needs no rotation), the k-means assignment (argmin fused, no
 // distance matrix is written) and the packing of the rotated base (X[ids] - mu) W into the
 // list-ordered store.
 //
 // Tiling: a 256-thread workgroup (4 wave64s, 2 x 2) owns a BM x BN tile of C; each wave owns
 // (BM/2) x (BN/2) as a grid of 32 x 32 MFMA accumulators.  Each K-step stages a BK x BM slice
 // of A and a BK x BN slice of B in LDS, k-major, so that the MFMA operand reads of a half-wave
-// hit 32 consecutive floats.  The blockIdx -> tile mapping keeps consecutive N-tiles of one
+// hit 32 consecutive floats; the next slice is fetched into registers during the MFMAs.  The blockIdx -> tile mapping keeps consecutive N-tiles of one
 // M-tile on one XCD (blocks are dealt round-robin to the 8 XCDs).
 #include "kernels.h"
 
@@ -17,14 +18,16 @@ namespace {
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 
-constexpr int BK = 16;
 constexpr int kThreads = 256;
 
-template <int BM, int BN, int EPI, bool BT>
+template <int BM, int BN, int BK, int EPI, bool BT>
 __global__ __launch_bounds__(kThreads) void gemm_kernel(GemmArgs g) {
   constexpr int WM = BM / 2, WN = BN / 2;      // per-wave tile
   constexpr int TM = WM / 32, TN = WN / 32;    // MFMA tiles per wave
   constexpr int PA = BM + 4, PB = BN + 4;      // padded LDS rows
+  constexpr int LA = BM * (BK / 4) / kThreads; // float4 loads per thread per K-slice of A
+  constexpr int LB = BN * (BK / 4) / kThreads; // ... and of B
+  static_assert(LA >= 1 && LB >= 1, "tile too small for the thread count");
   __shared__ float As[BK * PA];
   __shared__ float Bs[BK * PB];
 
@@ -52,31 +55,38 @@ __global__ __launch_bounds__(kThreads) void gemm_kernel(GemmArgs g) {
 #pragma unroll
       for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.f;
 
-  for (int k0 = 0; k0 < g.K; k0 += BK) {
-    // ---- stage A: BM rows x BK columns, float4 along k, stored k-major.
-    for (int e = tid; e < BM * (BK / 4); e += kThreads) {
-      const int r = e / (BK / 4), q = e % (BK / 4);
-      const int gm = m0 + r;
+  // The K-slice [k0, k0 + BK) of A and B is fetched into registers one slice ahead of the
+  // MFMAs that use it, so global loads overlap the matrix work.
+  const float* arow[LA];
+#pragma unroll
+  for (int l = 0; l < LA; ++l) {
+    const int r = (tid + l * kThreads) / (BK / 4);
+    const int gm = m0 + r;
+    arow[l] = nullptr;
+    if (gm < g.M) arow[l] = g.A + (g.a_rows ? int64_t(g.a_rows[gm]) : int64_t(gm)) * g.lda;
+  }
+  float4 ra[LA], rb[LB];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int l = 0; l < LA; ++l) {
+      const int q = (tid + l * kThreads) % (BK / 4);
       float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (gm < g.M) {
-        const int64_t src = g.a_rows ? g.a_rows[gm] : gm;
-        v = *reinterpret_cast<const float4*>(g.A + src * g.lda + k0 + 4 * q);
+      if (arow[l]) {
+        v = *reinterpret_cast<const float4*>(arow[l] + k0 + 4 * q);
         if (g.a_shift) {
-          const float4 s = *reinterpret_cast<const float4*>(g.a_shift + k0 + 4 * q);
-          v.x -= s.x; v.y -= s.y; v.z -= s.z; v.w -= s.w;
+          const float4 sh = *reinterpret_cast<const float4*>(g.a_shift + k0 + 4 * q);
+          v.x -= sh.x; v.y -= sh.y; v.z -= sh.z; v.w -= sh.w;
         }
       }
-      As[(4 * q + 0) * PA + r] = v.x;
-      As[(4 * q + 1) * PA + r] = v.y;
-      As[(4 * q + 2) * PA + r] = v.z;
-      As[(4 * q + 3) * PA + r] = v.w;
+      ra[l] = v;
     }
-    // ---- stage B: BK x BN.
-    if (!BT) {
-      for (int e = tid; e < BK * (BN / 4); e += kThreads) {
+#pragma unroll
+    for (int l = 0; l < LB; ++l) {
+      const int e = tid + l * kThreads;
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (!BT) {
         const int kk = e / (BN / 4), q = e % (BN / 4);
         const int gn = n0 + 4 * q;
-        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
         const float* src = g.B + int64_t(k0 + kk) * g.ldb + gn;
         if (gn + 3 < g.N) {
           v = *reinterpret_cast<const float4*>(src);
@@ -85,21 +95,46 @@ __global__ __launch_bounds__(kThreads) void gemm_kernel(GemmArgs g) {
           if (gn + 1 < g.N) v.y = src[1];
           if (gn + 2 < g.N) v.z = src[2];
         }
-        *reinterpret_cast<float4*>(&Bs[kk * PB + 4 * q]) = v;
-      }
-    } else {
-      for (int e = tid; e < BN * (BK / 4); e += kThreads) {
+      } else {
         const int c = e / (BK / 4), q = e % (BK / 4);
         const int gn = n0 + c;
-        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
         if (gn < g.N) v = *reinterpret_cast<const float4*>(g.B + int64_t(gn) * g.ldb + k0 + 4 * q);
-        Bs[(4 * q + 0) * PB + c] = v.x;
-        Bs[(4 * q + 1) * PB + c] = v.y;
-        Bs[(4 * q + 2) * PB + c] = v.z;
-        Bs[(4 * q + 3) * PB + c] = v.w;
+      }
+      rb[l] = v;
+    }
+  };
+  auto stage = [&]() {
+#pragma unroll
+    for (int l = 0; l < LA; ++l) {
+      const int e = tid + l * kThreads;
+      const int r = e / (BK / 4), q = e % (BK / 4);
+      As[(4 * q + 0) * PA + r] = ra[l].x;
+      As[(4 * q + 1) * PA + r] = ra[l].y;
+      As[(4 * q + 2) * PA + r] = ra[l].z;
+      As[(4 * q + 3) * PA + r] = ra[l].w;
+    }
+#pragma unroll
+    for (int l = 0; l < LB; ++l) {
+      const int e = tid + l * kThreads;
+      if (!BT) {
+        const int kk = e / (BN / 4), q = e % (BN / 4);
+        *reinterpret_cast<float4*>(&Bs[kk * PB + 4 * q]) = rb[l];
+      } else {
+        const int c = e / (BK / 4), q = e % (BK / 4);
+        Bs[(4 * q + 0) * PB + c] = rb[l].x;
+        Bs[(4 * q + 1) * PB + c] = rb[l].y;
+        Bs[(4 * q + 2) * PB + c] = rb[l].z;
+        Bs[(4 * q + 3) * PB + c] = rb[l].w;
       }
     }
+  };
+
+  fetch(0);
+  for (int k0 = 0; k0 < g.K; k0 += BK) {
+    __syncthreads();   // the previous slice's MFMAs are done with the LDS tiles
+    stage();
     __syncthreads();
+    if (k0 + BK < g.K) fetch(k0 + BK);
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 2) {
       const int kr = kk + (lane >> 5);
@@ -114,7 +149,6 @@ __global__ __launch_bounds__(kThreads) void gemm_kernel(GemmArgs g) {
         for (int j = 0; j < TN; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[i], bv[j], acc[i][j], 0, 0, 0);
     }
-    __syncthreads();
   }
 
   // ---- epilogue.  Accumulator v of a lane holds C[row][col] with
@@ -139,6 +173,19 @@ __global__ __launch_bounds__(kThreads) void gemm_kernel(GemmArgs g) {
             key = o < key ? o : key;
           }
           if ((lane & 31) == 0 && row < g.M) atomicMin(g.row_best + row, key);
+        }
+      } else if (EPI == kEpiRotateProbe) {
+        // columns [0, split_col): the rotated query; the rest: ||c - mu||^2 - 2 (q - mu).(c - mu)
+        if (col >= g.N) continue;
+        const bool rot = col < g.split_col;
+        const float cn = rot ? 0.f : g.col_norm[col - g.split_col];
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          const int row = m0 + wm + 32 * i + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+          if (row >= g.M) continue;
+          const float x = acc[i][j][v];
+          if (rot) static_cast<float*>(g.C)[int64_t(row) * g.ldc + col] = x;
+          else g.C2[int64_t(row) * g.ldc2 + (col - g.split_col)] = cn - 2.f * x;
         }
       } else {
         if (col >= g.N) continue;
@@ -166,14 +213,14 @@ __global__ __launch_bounds__(kThreads) void gemm_kernel(GemmArgs g) {
   }
 }
 
-template <int BM, int BN, int EPI>
+template <int BM, int BN, int BK, int EPI>
 hipError_t launch_tile(const GemmArgs& a, hipStream_t s) {
   const int tiles = ((a.M + BM - 1) / BM) * ((a.N + BN - 1) / BN);
   if (tiles == 0) return hipSuccess;
   if (a.b_trans)
-    hipLaunchKernelGGL((gemm_kernel<BM, BN, EPI, true>), dim3(tiles), dim3(kThreads), 0, s, a);
+    hipLaunchKernelGGL((gemm_kernel<BM, BN, BK, EPI, true>), dim3(tiles), dim3(kThreads), 0, s, a);
   else
-    hipLaunchKernelGGL((gemm_kernel<BM, BN, EPI, false>), dim3(tiles), dim3(kThreads), 0, s, a);
+    hipLaunchKernelGGL((gemm_kernel<BM, BN, BK, EPI, false>), dim3(tiles), dim3(kThreads), 0, s, a);
   return hipGetLastError();
 }
 
@@ -182,14 +229,14 @@ hipError_t launch_epi(const GemmArgs& a, hipStream_t s) {
   // Large problems use 128 x 128 tiles (2 x 2 MFMA tiles per wave), small ones 64 x 64 so
   // that the grid still covers the 256 CUs.
   const int64_t big_tiles = int64_t((a.M + 127) / 128) * ((a.N + 127) / 128);
-  if (big_tiles >= 1024) return launch_tile<128, 128, EPI>(a, s);
-  return launch_tile<64, 64, EPI>(a, s);
+  if (big_tiles >= 1024) return launch_tile<128, 128, 16, EPI>(a, s);
+  return launch_tile<64, 64, 16, EPI>(a, s);
 }
 
 }  // namespace
 
 hipError_t launch_gemm(const GemmArgs& a, GemmEpilogue epi, hipStream_t s) {
-  if (a.K % BK != 0 || a.lda % 4 != 0 || a.ldb % 4 != 0) return hipErrorInvalidValue;
+  if (a.K % 16 != 0 || a.lda % 4 != 0 || a.ldb % 4 != 0) return hipErrorInvalidValue;
   switch (epi) {
     case kEpiStore: return launch_epi<kEpiStore>(a, s);
     case kEpiProbe: return launch_epi<kEpiProbe>(a, s);
@@ -197,6 +244,7 @@ hipError_t launch_gemm(const GemmArgs& a, GemmEpilogue epi, hipStream_t s) {
     case kEpiPackF32: return launch_epi<kEpiPackF32>(a, s);
     case kEpiPackBF16: return launch_epi<kEpiPackBF16>(a, s);
     case kEpiPackF16: return launch_epi<kEpiPackF16>(a, s);
+    case kEpiRotateProbe: return launch_epi<kEpiRotateProbe>(a, s);
   }
   return hipErrorInvalidValue;
 }

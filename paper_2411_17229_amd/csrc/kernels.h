@@ -16,6 +16,7 @@ enum GemmEpilogue {
   kEpiPackF32 = 3,  // C (float)   = acc
   kEpiPackBF16 = 4, // C (bf16)    = RNE(acc)
   kEpiPackF16 = 5,  // C (half)    = RNE(acc)
+  kEpiRotateProbe = 6,  // n < split_col: C (float) = acc; else C2[n - split_col] = col_norm - 2 acc
 };
 
 struct GemmArgs {
@@ -32,6 +33,9 @@ struct GemmArgs {
   const float* col_norm = nullptr;
   unsigned long long* row_best = nullptr;
   int64_t split_rows = 0;   // pack epilogues: > 0 writes the head/tail store of that many rows
+  int split_col = 0;        // kEpiRotateProbe: first column of the C2 part
+  float* C2 = nullptr;
+  int ldc2 = 0;
 };
 hipError_t launch_gemm(const GemmArgs& a, GemmEpilogue epi, hipStream_t s);
 
@@ -75,9 +79,8 @@ hipError_t launch_prefix_fraction(const double* Y, int ld, int64_t m, int dim,
                                   const double* dis2, double* f, double* rel, hipStream_t s);
 
 // ---------------------------------------------------------------- probe selection (select.hip)
-// probes[q][0..nprobe) = ids of the nprobe smallest (qn[q] + pd[q][c], c), ascending.
-hipError_t launch_select_probes(const float* pd, int ld_pd, const float* qrot, int ld_q, int nq,
-                                int dim_p, int nlist, int nprobe, int32_t* probes,
+// probes[q][0..nprobe) = ids of the nprobe smallest (pd[q][c], c), ascending.
+hipError_t launch_select_probes(const float* pd, int ld_pd, int nq, int nlist, int nprobe, int32_t* probes,
                                 hipStream_t s);
 
 // ---------------------------------------------------------------- the list scan (scan.hip)

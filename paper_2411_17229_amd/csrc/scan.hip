@@ -641,8 +641,8 @@ __global__ __launch_bounds__(kThreads) void merge_round_kernel(RoundArgs a, int 
   const int tid = threadIdx.x;
   const int dp = a.dp, dim = a.dim;
   const int rq = a.q_rounds[q];
-  if (r >= rq) return;                    // finished in an earlier round
   const int kc = a.q_kc[q];
+  if (r >= rq) return;                    // finished in an earlier round
   const bool last = r == rq - 1;
   if (kc == 0 && !last) return;           // nothing queued: heap and snapshot stay as they are
   int K = a.k_pq ? a.k_pq[q] : a.k_max;

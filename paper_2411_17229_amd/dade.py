@@ -45,7 +45,7 @@ class SearchOpts(ctypes.Structure):
 
 
 class Times(ctypes.Structure):
-    _fields_ = [("rotate_ms", ctypes.c_float), ("probe_ms", ctypes.c_float), ("scan_ms", ctypes.c_float),
+    _fields_ = [("query_gemm_ms", ctypes.c_float), ("select_ms", ctypes.c_float), ("scan_ms", ctypes.c_float),
                 ("round_kernel_ms", ctypes.c_float), ("merge_kernel_ms", ctypes.c_float),
                 ("plan_ms", ctypes.c_float), ("round_launches", ctypes.c_int32)]
 
