@@ -585,11 +585,28 @@ __global__ __launch_bounds__(64) void plan_kernel(RoundArgs a, int* counts) {
   }
   if (!WRITE) return;
   __syncthreads();
-  // the staged rounds' items, one round per lane
-  for (int r = lane; r < s_nr; r += 64) {
+  // the staged rounds' items: for each round and each list segment of it, the wave writes the
+  // segment's items in parallel (item j of a segment by lane j % 64)
+  for (int r = 0; r < s_nr; ++r) {
     const int4 c = cuts[r];
-    round_items(a, a.items + int64_t(r) * a.items_cap, a.items_cap, counts[int64_t(r) * a.nq + q], q, c.x, c.y,
-                c.z, c.w & 0x7FFFFFFF, c.w < 0 ? kDenseItem : kItem, len_of, pos_of);
+    const int t = c.x, off = c.y, t1 = c.z, off1 = c.w & 0x7FFFFFFF;
+    const int per = c.w < 0 ? kDenseItem : kItem;
+    int4* items = a.items + int64_t(r) * a.items_cap;
+    int slot = counts[int64_t(r) * a.nq + q];
+    const int t_last = off1 > 0 ? t1 : t1 - 1;
+    for (int tt = t; tt <= t_last; ++tt) {
+      const int s0 = tt == t ? off : 0;
+      const int s1 = tt == t1 ? off1 : len_of(tt);
+      if (s1 <= s0) continue;
+      const int n = (s1 - s0 + per - 1) / per;
+      const int p0 = int(pos_of(tt));
+      for (int j = lane; j < n; j += 64) {
+        const int ss = s0 + j * per;
+        if (slot + j < a.items_cap) items[slot + j] = make_int4(q, s1 - ss < per ? s1 - ss : per, p0 + ss, 0);
+        else atomicOr(a.overflow, 2);
+      }
+      slot += n;
+    }
   }
 }
 
@@ -634,6 +651,7 @@ __global__ __launch_bounds__(kThreads) void merge_round_kernel(RoundArgs a, int 
   __shared__ unsigned long long newk[kMaxK];
   __shared__ unsigned long long fk[RERANK ? kMaxK : 1];
   __shared__ unsigned long long cand[kMergeChunk + kMaxK];
+  __shared__ unsigned long long qk[kMergeChunk];   // the queued keys, when they fit
   __shared__ int s_nc;
   __shared__ unsigned long long s_b;
 
@@ -649,14 +667,20 @@ __global__ __launch_bounds__(kThreads) void merge_round_kernel(RoundArgs a, int 
   K = K < 1 ? 1 : (K > a.k_max ? a.k_max : K);
   unsigned long long* gtop = a.q_topk + int64_t(q) * a.k_max;
 
+  // every input of the merge is fetched at once: the heap (all k_max slots; those past its size
+  // are not used), the queued keys (into LDS when they fit), the original query
   int topk_n = a.q_topn[q];
-  for (int i = tid; i < topk_n; i += kThreads) topk[i] = gtop[i];
-  if (RERANK)
+  for (int i = tid; i < a.k_max; i += kThreads) topk[i] = gtop[i];
+  const int m = kc < a.kb_cap ? kc : int(a.kb_cap);
+  const unsigned long long* kb = a.kb + int64_t(q) * a.kb_cap;
+  const bool in_lds = m <= kMergeChunk;
+  if (in_lds)
+    for (int i = tid; i < m; i += kThreads) qk[i] = kb[i];
+  if (RERANK && m > 0)
     for (int c = tid; c < dp; c += kThreads) qo[c] = a.qorig[int64_t(q) * dp + c];
   const unsigned long long keyr = a.q_keyr[q];
   const bool full = keyr != ~0ull;
-  const int m = kc < a.kb_cap ? kc : int(a.kb_cap);
-  const unsigned long long* kb = a.kb + int64_t(q) * a.kb_cap;
+  auto queued = [&](int i) { return in_lds ? qk[i] : kb[i]; };
   unsigned st_kept = 0, st_rr = 0;
   __syncthreads();
 
@@ -667,7 +691,7 @@ __global__ __launch_bounds__(kThreads) void merge_round_kernel(RoundArgs a, int 
       if (tid == 0) s_nc = 0;
       __syncthreads();
       for (int i = tid; i < cnt; i += kThreads) {
-        const unsigned long long key = kb[base + i];
+        const unsigned long long key = queued(base + i);
         if (key < kth) cand[atomicAdd(&s_nc, 1)] = key;
       }
       __syncthreads();
@@ -679,7 +703,7 @@ __global__ __launch_bounds__(kThreads) void merge_round_kernel(RoundArgs a, int 
     int fn = 0;
     unsigned long long fmax = ~0ull;
     if (m <= K) {
-      for (int i = tid; i < m; i += kThreads) cand[i] = kb[i];
+      for (int i = tid; i < m; i += kThreads) cand[i] = queued(i);
       fn = m;
       __syncthreads();
     } else {
@@ -689,7 +713,7 @@ __global__ __launch_bounds__(kThreads) void merge_round_kernel(RoundArgs a, int 
         if (tid == 0) s_nc = 0;
         __syncthreads();
         for (int i = tid; i < cnt; i += kThreads) {
-          const unsigned long long key = kb[base + i];
+          const unsigned long long key = queued(base + i);
           if (key < kth) cand[atomicAdd(&s_nc, 1)] = key;
         }
         __syncthreads();
@@ -729,7 +753,7 @@ __global__ __launch_bounds__(kThreads) void merge_round_kernel(RoundArgs a, int 
       if (tid == 0) s_nc = 0;
       __syncthreads();
       for (int i = tid; i < cnt; i += kThreads) {
-        const unsigned long long key = kb[base + i];
+        const unsigned long long key = queued(base + i);
         if (key > fmax && key_dist(key) <= bound) cand[atomicAdd(&s_nc, 1)] = key;
       }
       __syncthreads();

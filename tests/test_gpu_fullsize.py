@@ -1,0 +1,110 @@
+"""Parity at full workload sizes, in the bench's launch configuration.
+
+The library builds, rotates and calibrates each index itself; the oracle imports its artifacts
+(lists, W, mu, lambda, T, delta) and scans a seeded sample of queries with rows rotated (and,
+for 16-bit stores, rounded) on demand.  Every query's returned distances are checked against
+FP64, and the sampled queries' ID sets and DCO counts against the oracle (near-tie decisions
+excused as in the small-size tests).
+"""
+import numpy as np
+import pytest
+
+from oracle import estimator, ivf, lowp
+from paper_2411_17229_amd import dade, workloads
+from gpu_helpers import DIST_RTOL, MARGIN_TOL, exact_d2, to_np
+
+pytestmark = pytest.mark.gpu
+
+SCHEDULE = dict(schedule="doubling", fill_min=32, growth=16)
+
+
+def _need_gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+
+
+def oracle_from_library(gi, X, store):
+    art = dade.dade_export(gi)
+    lam, T = art["lam"], art["T"]
+    eps = np.sqrt(np.maximum(T * estimator.scale(lam), 0.0)) - 1.0
+    rnd = None if store == "f32" else (lambda y: lowp.store(y, store))
+    Y = ivf.LazyRotated(X, art["mu"], art["W"], rnd)
+    Ye = ivf.LazyRotated(X, art["mu"], art["W"]) if rnd is not None else None
+    return ivf.Index(art["mu"], art["W"], lam, eps, art["centroids"], art["list_offsets"], art["list_ids"], Y,
+                     Y_exact=Ye, delta=art["delta"], T=T)
+
+
+def run_workload(name, p_s, nprobe, n_sample, k_per_query=None, nprobe_per_query=None, k=None):
+    import torch
+    _need_gpu()
+    w = workloads.WORKLOADS[name]
+    X, Q = workloads.make(w)
+    dev = torch.device("cuda:0")
+    Xd, Qd = torch.from_numpy(X).to(dev), torch.from_numpy(Q).to(dev)
+    gi = dade.dade_build_index(Xd, w.nlist, store=w.store, init_rows=workloads.kmeans_init_rows(w.n, w.nlist, w.seed))
+    dade.dade_rotate(gi)
+    dade.dade_calibrate(gi, p_s, pairs=workloads.calibration_pairs(w.n, 100_000, w.seed))
+    K = k or w.k
+    kw = dict(delta_d=w.delta_d, **SCHEDULE)
+    kp = None if k_per_query is None else torch.from_numpy(k_per_query).to(dev)
+    npp = None if nprobe_per_query is None else torch.from_numpy(nprobe_per_query).to(dev)
+    stats = torch.zeros((len(Q), 4), dtype=torch.int64, device=dev)
+    ids, d2 = dade.dade_search(gi, Qd, K, nprobe, k_per_query=kp, nprobe_per_query=npp, stats=stats, **kw)
+    # the graph-replayed launch (as timed) gives the same rows
+    ids2, d22 = dade.dade_search(gi, Qd, K, nprobe, k_per_query=kp, nprobe_per_query=npp, **kw)
+    torch.cuda.synchronize()
+    dade.dade_check(gi)
+    ids, d2, st = to_np(ids), to_np(d2), to_np(stats)
+    assert np.array_equal(ids, to_np(ids2)) and np.array_equal(d2.view(np.uint32), to_np(d22).view(np.uint32))
+    Ks = np.full(len(Q), K) if k_per_query is None else k_per_query
+    # every query: exact distances of the returned ids, rows ascending by (dist2, id)
+    ex = exact_d2(X, Q, ids)
+    for qi in range(len(Q)):
+        kq = int(Ks[qi])
+        assert np.all(ids[qi, :kq] >= 0) and np.all(ids[qi, kq:] == -1), qi
+        np.testing.assert_allclose(d2[qi, :kq], ex[qi, :kq], rtol=DIST_RTOL, err_msg=f"query {qi}")
+        keys = list(zip(d2[qi, :kq].tolist(), ids[qi, :kq].tolist()))
+        assert keys == sorted(keys), qi
+    # sampled queries: the oracle on the library's artifacts
+    oi = oracle_from_library(gi, X, w.store)
+    sample = np.sort(np.random.default_rng(7).choice(len(Q), n_sample, replace=False))
+    Ko = Ks[sample]
+    npo = nprobe if nprobe_per_query is None else nprobe_per_query[sample]
+    o_ids, _, logs = ivf.search(oi, Q[sample], Ko, npo, w.delta_d, log=True, **SCHEDULE)
+    excused = 0
+    same_probes = logs["probe_gap"] > MARGIN_TOL   # no near tie in the probe order
+    for j, qi in enumerate(sample):
+        kq = int(Ks[qi])
+        if same_probes[j]:   # the same candidates: one DCO each
+            assert st[qi, 0] == logs["dcos"][j], (qi, st[qi, 0], logs["dcos"][j])
+        if set(ids[qi, :kq].tolist()) == set(o_ids[j, :kq].tolist()):
+            continue
+        assert logs["min_margin"][j] <= MARGIN_TOL or not same_probes[j], \
+            f"query {qi}: gpu {ids[qi, :kq]} oracle {o_ids[j, :kq]} margin {logs['min_margin'][j]}"
+        excused += 1
+    assert excused <= max(1, n_sample // 4), excused
+    # dimensions read agree in aggregate (single decisions may differ at near ties)
+    dims_g, dims_o = st[sample, 1][same_probes].sum(), logs["dims"][same_probes].sum()
+    assert abs(dims_g - dims_o) <= 0.01 * dims_o, (dims_g, dims_o)
+    gi.close()
+    return ids, d2
+
+
+def test_fullsize_highd_bench_configuration():
+    """1M x 960, BF16 store + FP32 rerank, 1000 queries, K 10, nprobe 8, P_s 0.005: the bench's
+    operating point and launch configuration."""
+    run_workload("highd-1m-d960", p_s=0.005, nprobe=8, n_sample=6)
+
+
+def test_fullsize_scale_f32():
+    """1M x 128, FP32 store, 10,000 queries, nlist 1024, nprobe 16, Delta_d 16."""
+    run_workload("scale-1m-d128", p_s=0.1, nprobe=16, n_sample=8)
+
+
+def test_fullsize_uneven_batch():
+    """2M x 256, BF16 store, 4096 queries with per-query K in {1, 10, 50, 100} and nprobe in
+    8..128 (seeded), nlist 4096."""
+    w = workloads.WORKLOADS["uneven-2m-d256"]
+    K, npb = workloads.uneven_batch(w.n_queries, 8, 128, (1, 10, 50, 100), seed=w.seed)
+    run_workload("uneven-2m-d256", p_s=0.1, nprobe=128, n_sample=6, k_per_query=K, nprobe_per_query=npb, k=100)
