@@ -140,6 +140,32 @@ __device__ inline void advance(const Rows& rows, int64_t p, const float* qv, flo
 #pragma unroll
   for (int i = 0; i < NB; ++i) blk[i] = SS::load(rows, p, b + (i < nb ? i : nb - 1));
   int nt = tests ? (b * kBlock / dd + 1) * dd : 0x7fffffff;   // next tested d
+  if (!PER_DIM) {
+    // Branch-free: every unit of the loaded blocks is summed (its query and threshold loads
+    // can then all be issued ahead), and only the units the DCO reaches are accumulated and
+    // tested.  Padding units and clamped repeat blocks are loaded in bounds and not counted.
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+#pragma unroll
+      for (int j = 0; j < kBlock / 8; ++j) {
+        const int d0 = (b + i) * kBlock + 8 * j;
+        float v[8], qq[8];
+        SS::unit(blk[i], j, v);
+        q8(qv, d0, qq);
+        const float Sn = S + unit_sum(qq, v);
+        const bool act = i < nb && !rej && d0 < dim;
+        const int d = d0 + 8;
+        const float thr = T[(d < dim ? d : dim) - 1] * r2;
+        const bool at = act && d == nt;
+        const bool rj = at && d < dim && Sn > thr;
+        S = act ? Sn : S;
+        dexit = rj ? d : dexit;
+        rej = rej || rj;
+        nt = at ? nt + dd : nt;
+      }
+    }
+    return;
+  }
 #pragma unroll
   for (int i = 0; i < NB; ++i) {
 #pragma unroll
@@ -289,8 +315,27 @@ __global__ __launch_bounds__(kThreads) void scan_round_kernel(RoundArgs a, int r
   __syncthreads();
 
   int sn = 0;             // live stack entries (wave-uniform)
-  bool drained = false;   // no work item left in this round
+  // The next work item and its query's round snapshot are fetched one item ahead, so that their
+  // dependent loads overlap the current item's work.
+  auto claim = [&](int4& it) {
+    int k = 0;
+    if (lane == 0) k = atomicAdd(&s_claim, 1);
+    k = __shfl(k, 0);
+    const int64_t idx = int64_t(blockIdx.x) + int64_t(k) * gridDim.x;
+    if (idx >= n_items) return false;
+    it = items[idx];
+    return true;
+  };
+  int4 nit = make_int4(0, 0, 0, 0);
+  bool nvalid = claim(nit);
+  float nr2 = 0.f;
+  unsigned long long nkeyr = 0;
+  if (nvalid) {
+    nr2 = a.q_r2[nit.x];
+    nkeyr = a.q_keyr[nit.x];
+  }
   for (;;) {
+    const bool drained = !nvalid;   // no work item left in this round
     if (sn >= 64 || (drained && sn > 0)) {
       // ---- continue up to 64 stacked survivors by one level each
       const int take = sn < 64 ? sn : 64;
@@ -334,24 +379,21 @@ __global__ __launch_bounds__(kThreads) void scan_round_kernel(RoundArgs a, int r
     }
     if (drained) break;
 
-    // ---- claim a work item
-    int k = 0;
-    if (lane == 0) k = atomicAdd(&s_claim, 1);
-    k = __shfl(k, 0);
-    const int64_t item = int64_t(blockIdx.x) + int64_t(k) * gridDim.x;
-    if (item >= n_items) {
-      drained = true;
-      continue;
-    }
-    const int4 it = items[item];
+    // ---- the prefetched work item; claim the next one
+    const int4 it = nit;
+    const float r2 = nr2;
+    const unsigned long long keyr = nkeyr;
+    nvalid = claim(nit);
     const int q = it.x, cnt = it.y;
-    const float r2 = a.q_r2[q];
-    const unsigned long long keyr = a.q_keyr[q];
     const bool full = keyr != ~0ull;
     const float* qv = a.qrot + int64_t(q) * dp;
     const bool dense = !any_tests || !full;   // no test can reject: whole rows
     if (dense && cnt <= 16) {
       // few candidates (the rounds that fill the heap): four lanes per row
+      if (nvalid) {
+        nr2 = a.q_r2[nit.x];
+        nkeyr = a.q_keyr[nit.x];
+      }
       dense_item<ST, RERANK>(a, rows, q, cnt, it.z, qv, full, keyr, gate_f * r2, nblk, lane);
       continue;
     }
@@ -360,7 +402,46 @@ __global__ __launch_bounds__(kThreads) void scan_round_kernel(RoundArgs a, int r
     float S = 0.f;
     bool rej = false, done = true;
     int dexit = dim;
-    if (dense) {
+    if (!dense && !PER_DIM && nb0 == 1) {
+      // level 0 (the first test inside the head block): its loads go out before the next
+      // item's snapshot is fetched
+      if (has) {
+        const typename SS::Block blk = SS::load(rows, p, 0);
+        if (nvalid) {
+          nr2 = a.q_r2[nit.x];
+          nkeyr = a.q_keyr[nit.x];
+        }
+        int nt = dd;
+#pragma unroll
+        for (int j = 0; j < kBlock / 8; ++j) {   // branch-free, as in advance()
+          const int d = 8 * j + 8;
+          float v[8], qq[8];
+          SS::unit(blk, j, v);
+          q8(qv, 8 * j, qq);
+          const float Sn = S + unit_sum(qq, v);
+          const bool act = !rej && d - 8 < dim;
+          const float thr = a.T[(d < dim ? d : dim) - 1] * r2;
+          const bool at = act && d == nt;
+          const bool rj = at && d < dim && Sn > thr;
+          S = act ? Sn : S;
+          dexit = rj ? d : dexit;
+          rej = rej || rj;
+          nt = at ? nt + dd : nt;
+        }
+        done = rej || 1 >= nblk;
+      } else if (nvalid) {
+        nr2 = a.q_r2[nit.x];
+        nkeyr = a.q_keyr[nit.x];
+      }
+    } else {
+      if (nvalid) {
+        nr2 = a.q_r2[nit.x];
+        nkeyr = a.q_keyr[nit.x];
+      }
+    }
+    if (!dense && !PER_DIM && nb0 == 1) {
+      // done above
+    } else if (dense) {
       // one lane per row (FDScanning, or no d below D to test)
       if (has)
         for (int b = 0; b < nblk; b += MB)
