@@ -693,8 +693,14 @@ int dade_search(dade_index* ix, const float* Q, int64_t nq, int32_t k, int32_t n
   for (int i = 0; i < npm; ++i) most += sizes[i];
   const int64_t first = std::max<int64_t>(k, o.fill_min);
   kb_cap = std::max<int64_t>(kb_cap, std::min(first, most));
-  if (o.growth > 0)   // rounds cut short by the growth cap: positions grow by 1 + growth each
-    for (int64_t p = std::max<int64_t>(1, std::min<int64_t>(o.fill_min, most)); p < most; p *= 1 + o.growth) ++rounds;
+  // Rounds cut short by the growth cap: such a round at position p takes growth x p candidates,
+  // so it needs more than (1 + growth) p of them and leaves the position at (1 + growth) p.
+  // Every query's first round ends at p0 >= min(fill_min, most) or later, so its c-th capped
+  // round needs p0 (1 + growth)^c < most.
+  if (o.growth > 0)
+    for (int64_t p = std::max<int64_t>(1, std::min<int64_t>(o.fill_min, most)) * (1 + o.growth); p < most;
+         p *= 1 + o.growth)
+      ++rounds;
   // work items of one query in one round: its segments cut at 16 candidates (whole-row rounds;
   // other rounds use 64)
   const int64_t items_pq = std::max<int64_t>((kb_cap + 15) / 16 + widest + 1, (first + 15) / 16 + npm);

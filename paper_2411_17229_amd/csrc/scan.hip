@@ -40,6 +40,7 @@ constexpr int kStack = 128;        // deep-stack entries per wave (at most 127 a
 constexpr int kItem = 64;          // candidates per work item
 constexpr int kDenseItem = 16;     // candidates per work item of a whole-row round
 constexpr int kMergeChunk = 512;   // queued keys handled per LDS pass of the merge
+constexpr int kHeadKeys = 64;      // queued keys a merge fetches with the query's state
 constexpr int kBlock = kHead;      // coordinates per block; block 0 is the head
 constexpr int kGroup = 16;         // lanes per candidate in the exact rerank
 constexpr int kGroups = kThreads / kGroup;
@@ -469,19 +470,61 @@ __global__ __launch_bounds__(kThreads) void scan_round_kernel(RoundArgs a, int r
 // ------------------------------------------------------------------------------------------------
 // merge_round helpers (one workgroup per query, keys in LDS).
 
+__device__ inline int pad8(int n) { return (n + 7) & ~7; }
+
+// Number of keys of c[0..n8) below key, n8 a multiple of 8, c 16-byte aligned; entries past the
+// live ones hold ~0, which no key reaches.  Reads 8 keys per step as 16-byte LDS loads, so the
+// loads of a step are in flight together.
+__device__ inline int count_below(const unsigned long long* c, int n8, unsigned long long key) {
+  const ulonglong2* c2 = reinterpret_cast<const ulonglong2*>(c);
+  int r0 = 0, r1 = 0;
+  for (int j = 0; j < n8 / 2; j += 4) {
+    const ulonglong2 v0 = c2[j], v1 = c2[j + 1], v2 = c2[j + 2], v3 = c2[j + 3];
+    r0 += int(v0.x < key) + int(v0.y < key) + int(v1.x < key) + int(v1.y < key);
+    r1 += int(v2.x < key) + int(v2.y < key) + int(v3.x < key) + int(v3.y < key);
+  }
+  return r0 + r1;
+}
+
+// Appends key to c at a slot taken from *n (one LDS atomic per wave), for the lanes with take.
+__device__ inline void append_lds(unsigned long long* c, int* n, bool take, unsigned long long key, int lane) {
+  const unsigned long long m = __ballot(take);
+  if (m == 0) return;
+  int base = 0;
+  if (lane == 0) base = atomicAdd(n, __popcll(m));
+  base = __shfl(base, 0);
+  if (take) c[base + lanes_below(m)] = key;
+}
+
+// c[0..n) <- its keys below lim, in order (wave 0; the count goes to *cnt).  Ends with a barrier.
+__device__ inline void keep_below(unsigned long long* c, int n, unsigned long long lim, int* cnt, int tid) {
+  if (tid < 64) {
+    int w = 0;
+    for (int base = 0; base < n; base += 64) {
+      const int i = base + tid;
+      const unsigned long long key = i < n ? c[i] : ~0ull;
+      const bool keep = i < n && key < lim;
+      const unsigned long long m = __ballot(keep);
+      if (keep) c[w + lanes_below(m)] = key;
+      w += __popcll(m);
+    }
+    if (tid == 0) *cnt = w;
+  }
+  __syncthreads();
+}
+
 // heap[0..heap_n) (ascending keys) <- the K smallest of heap and cand[0..n); keys are unique,
-// so each key's rank is the count of smaller keys.  cand must have room for n + K entries.
-// Ends with a barrier.
+// so each key's rank is the count of smaller keys.  cand must have room for pad8(n + K)
+// entries.  Ends with a barrier.
 __device__ void merge_into(unsigned long long* heap, int& heap_n, unsigned long long* tmp,
                            unsigned long long* cand, int n, int K, int tid) {
   if (n > 0) {
-    for (int i = tid; i < heap_n; i += kThreads) cand[n + i] = heap[i];
+    const int tot = n + heap_n, tot8 = pad8(tot);
+    for (int i = tid; i < tot8 - n; i += kThreads) cand[n + i] = i < heap_n ? heap[i] : ~0ull;
     __syncthreads();
-    const int tot = n + heap_n;
     for (int i = tid; i < tot; i += kThreads) {
       const unsigned long long key = cand[i];
-      int rank = 0;
-      for (int j = 0; j < tot; ++j) rank += cand[j] < key;
+      const int rank = count_below(cand, tot8, key);
       if (rank < K) tmp[rank] = key;
     }
     __syncthreads();
@@ -728,38 +771,39 @@ __global__ __launch_bounds__(kScanThreads) void plan_offsets_kernel(RoundArgs a,
 template <bool RERANK>
 __global__ __launch_bounds__(kThreads) void merge_round_kernel(RoundArgs a, int r) {
   extern __shared__ float qo[];   // [dp] original query (RERANK)
-  __shared__ unsigned long long topk[kMaxK];
-  __shared__ unsigned long long newk[kMaxK];
-  __shared__ unsigned long long fk[RERANK ? kMaxK : 1];
-  __shared__ unsigned long long cand[kMergeChunk + kMaxK];
-  __shared__ unsigned long long qk[kMergeChunk];   // the queued keys, when they fit
+  __shared__ __align__(16) unsigned long long topk[kMaxK];
+  __shared__ __align__(16) unsigned long long newk[kMaxK];
+  __shared__ __align__(16) unsigned long long fk[RERANK ? kMaxK : 8];
+  __shared__ __align__(16) unsigned long long cand[kMergeChunk + kMaxK];
+  __shared__ __align__(16) unsigned long long qk[kMergeChunk];   // the queued keys, when they fit
   __shared__ int s_nc;
   __shared__ unsigned long long s_b;
 
   const int q = blockIdx.x;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63;
   const int dp = a.dp, dim = a.dim;
+  unsigned long long* gtop = a.q_topk + int64_t(q) * a.k_max;
+  const unsigned long long* kb = a.kb + int64_t(q) * a.kb_cap;
+  // the query's state, its heap (all k_max slots; those past its size are not used) and the
+  // head of its queue are fetched together, before it is known whether the round queued any key
   const int rq = a.q_rounds[q];
   const int kc = a.q_kc[q];
+  int topk_n = a.q_topn[q];
+  const unsigned long long keyr = a.q_keyr[q];
+  const int n_head = a.kb_cap < kHeadKeys ? int(a.kb_cap) : kHeadKeys;
+  for (int i = tid; i < a.k_max; i += kThreads) topk[i] = gtop[i];
+  if (tid < n_head) qk[tid] = kb[tid];
   if (r >= rq) return;                    // finished in an earlier round
   const bool last = r == rq - 1;
   if (kc == 0 && !last) return;           // nothing queued: heap and snapshot stay as they are
   int K = a.k_pq ? a.k_pq[q] : a.k_max;
   K = K < 1 ? 1 : (K > a.k_max ? a.k_max : K);
-  unsigned long long* gtop = a.q_topk + int64_t(q) * a.k_max;
-
-  // every input of the merge is fetched at once: the heap (all k_max slots; those past its size
-  // are not used), the queued keys (into LDS when they fit), the original query
-  int topk_n = a.q_topn[q];
-  for (int i = tid; i < a.k_max; i += kThreads) topk[i] = gtop[i];
   const int m = kc < a.kb_cap ? kc : int(a.kb_cap);
-  const unsigned long long* kb = a.kb + int64_t(q) * a.kb_cap;
   const bool in_lds = m <= kMergeChunk;
   if (in_lds)
-    for (int i = tid; i < m; i += kThreads) qk[i] = kb[i];
+    for (int i = n_head + tid; i < m; i += kThreads) qk[i] = kb[i];
   if (RERANK && m > 0)
     for (int c = tid; c < dp; c += kThreads) qo[c] = a.qorig[int64_t(q) * dp + c];
-  const unsigned long long keyr = a.q_keyr[q];
   const bool full = keyr != ~0ull;
   auto queued = [&](int i) { return in_lds ? qk[i] : kb[i]; };
   unsigned st_kept = 0, st_rr = 0;
@@ -771,9 +815,10 @@ __global__ __launch_bounds__(kThreads) void merge_round_kernel(RoundArgs a, int 
       const unsigned long long kth = topk_n == K ? topk[K - 1] : ~0ull;
       if (tid == 0) s_nc = 0;
       __syncthreads();
-      for (int i = tid; i < cnt; i += kThreads) {
-        const unsigned long long key = queued(base + i);
-        if (key < kth) cand[atomicAdd(&s_nc, 1)] = key;
+      for (int i0 = 0; i0 < cnt; i0 += kThreads) {
+        const int i = i0 + tid;
+        const unsigned long long key = i < cnt ? queued(base + i) : ~0ull;
+        append_lds(cand, &s_nc, i < cnt && key < kth, key, lane);
       }
       __syncthreads();
       if (tid == 0) st_kept += unsigned(s_nc);
@@ -793,9 +838,10 @@ __global__ __launch_bounds__(kThreads) void merge_round_kernel(RoundArgs a, int 
         const unsigned long long kth = fn == K ? fk[K - 1] : ~0ull;
         if (tid == 0) s_nc = 0;
         __syncthreads();
-        for (int i = tid; i < cnt; i += kThreads) {
-          const unsigned long long key = queued(base + i);
-          if (key < kth) cand[atomicAdd(&s_nc, 1)] = key;
+        for (int i0 = 0; i0 < cnt; i0 += kThreads) {
+          const int i = i0 + tid;
+          const unsigned long long key = i < cnt ? queued(base + i) : ~0ull;
+          append_lds(cand, &s_nc, i < cnt && key < kth, key, lane);
         }
         __syncthreads();
         merge_into(fk, fn, newk, cand, s_nc, K, tid);
@@ -807,49 +853,38 @@ __global__ __launch_bounds__(kThreads) void merge_round_kernel(RoundArgs a, int 
     exact_rerank(cand, fn, a.X, qo, dp, dim, tid, st_rr);
     // b = K-th smallest exact key of the heap snapshot and F
     if (tid == 0) s_b = ~0ull;
+    for (int i = topk_n + tid; i < pad8(topk_n); i += kThreads) topk[i] = ~0ull;
+    for (int i = fn + tid; i < pad8(fn); i += kThreads) cand[i] = ~0ull;
     __syncthreads();
     if (topk_n + fn >= K) {
       for (int i = tid; i < topk_n + fn; i += kThreads) {
         const unsigned long long key = i < topk_n ? topk[i] : cand[i - topk_n];
-        int rank = 0;
-        for (int j = 0; j < topk_n; ++j) rank += topk[j] < key;
-        for (int j = 0; j < fn; ++j) rank += cand[j] < key;
+        const int rank = count_below(topk, pad8(topk_n), key) + count_below(cand, pad8(fn), key);
         if (rank == K - 1) s_b = key;
       }
     }
     __syncthreads();
     const float bound = s_b == ~0ull ? __builtin_inff() : (1.f + a.rerank_delta) * key_dist(s_b);
-    if (tid == 0) {
-      int w = 0;
-      for (int i = 0; i < fn; ++i)
-        if (!full || cand[i] < keyr) cand[w++] = cand[i];
-      s_nc = w;
-      st_kept += unsigned(w);
-    }
-    __syncthreads();
+    keep_below(cand, fn, keyr, &s_nc, tid);   // keyr is ~0 while the heap is not full
+    if (tid == 0) st_kept += unsigned(s_nc);
     merge_into(topk, topk_n, newk, cand, s_nc, K, tid);
     // the rest of the queue, reranked only inside the bound
     for (int base = 0; m > K && base < m; base += kMergeChunk) {
       const int cnt = m - base < kMergeChunk ? m - base : kMergeChunk;
       if (tid == 0) s_nc = 0;
       __syncthreads();
-      for (int i = tid; i < cnt; i += kThreads) {
-        const unsigned long long key = queued(base + i);
-        if (key > fmax && key_dist(key) <= bound) cand[atomicAdd(&s_nc, 1)] = key;
+      for (int i0 = 0; i0 < cnt; i0 += kThreads) {
+        const int i = i0 + tid;
+        const unsigned long long key = i < cnt ? queued(base + i) : ~0ull;
+        append_lds(cand, &s_nc, i < cnt && key > fmax && key_dist(key) <= bound, key, lane);
       }
       __syncthreads();
       const int nr = s_nc;
       __syncthreads();
       if (nr == 0) continue;
       exact_rerank(cand, nr, a.X, qo, dp, dim, tid, st_rr);
-      if (tid == 0) {
-        int w = 0;
-        for (int i = 0; i < nr; ++i)
-          if (!full || cand[i] < keyr) cand[w++] = cand[i];
-        s_nc = w;
-        st_kept += unsigned(w);
-      }
-      __syncthreads();
+      keep_below(cand, nr, keyr, &s_nc, tid);
+      if (tid == 0) st_kept += unsigned(s_nc);
       merge_into(topk, topk_n, newk, cand, s_nc, K, tid);
     }
   }
