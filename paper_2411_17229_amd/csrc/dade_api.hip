@@ -706,7 +706,8 @@ int dade_search(dade_index* ix, const float* Q, int64_t nq, int32_t k, int32_t n
   const int64_t items_pq = std::max<int64_t>((kb_cap + 15) / 16 + widest + 1, (first + 15) / 16 + npm);
   // queries per pass: the round workspace stays under 1 GiB
   const int64_t per_q = kb_cap * 8 + rounds * (items_pq * 16 + 4) + int64_t(k) * 8 + 48;
-  const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(nq, (int64_t(1) << 30) / per_q));
+  const int64_t chunk =
+      std::max<int64_t>(1, std::min<int64_t>({nq, (int64_t(1) << 30) / per_q, int64_t(kMaxPassQueries)}));
   // workspace
   if (nq > ix->w_nq || npm > ix->w_np) {
     const int64_t new_nq = std::max(nq, ix->w_nq), new_np = std::max<int64_t>(npm, ix->w_np);
@@ -786,6 +787,7 @@ int dade_search(dade_index* ix, const float* Q, int64_t nq, int32_t k, int32_t n
     a.items_cap = int(std::min<int64_t>(chunk * items_pq, INT32_MAX));
     a.items = ix->w_items;
     a.n_items = ix->w_counter; a.overflow = ix->w_flags;
+    a.item_off = ix->w_counts;
     if (o.record_times) {   // events for this pass (the last pass's times are reported)
       while (ix->kev.size() < size_t(2 + 3 * rounds)) {
         hipEvent_t e;

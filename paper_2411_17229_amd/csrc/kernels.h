@@ -124,14 +124,21 @@ struct RoundArgs {
   int* q_rounds = nullptr;               // [nq] the query's round count
   unsigned long long* kb = nullptr;      // [nq x kb_cap] queued keys
   int64_t kb_cap = 0;
-  // work items {query, count, first packed position, 0}: round r's in items[r * items_cap ...]
+  // work items {query | count << kItemCountShift, first packed position, the query's K-th key at
+  // the round's start (high word, low word; ~0: heap not full)}: round r's in
+  // items[r * items_cap ...].  The plan writes them with an empty heap's key; the merge that ends
+  // round r writes its snapshot into the query's items of round r + 1.
   int4* items = nullptr;
   int items_cap = 0;
-  int* n_items = nullptr;   // [rounds]
+  int* n_items = nullptr;          // [rounds]
+  const int* item_off = nullptr;   // [rounds x nq] a query's first item in each round
   int* overflow = nullptr;  // [1] nonzero if a capacity was exceeded
   int grid = 0;
 };
-// counts: device scratch of rounds x nq ints.
+// Work items pack the query index below bit kItemCountShift and the candidate count (<= 64) above.
+constexpr int kItemCountShift = 25;
+constexpr int kMaxPassQueries = 1 << kItemCountShift;   // queries one pass of rounds may hold
+// counts: device scratch of rounds x nq ints; afterwards it holds item_off.
 hipError_t launch_plan(const RoundArgs& a, int* counts, hipStream_t s);
 hipError_t launch_round(const RoundArgs& a, int r, hipStream_t s);
 hipError_t launch_merge(const RoundArgs& a, int r, hipStream_t s);

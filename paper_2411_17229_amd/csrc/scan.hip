@@ -292,7 +292,9 @@ __device__ void dense_item(const RoundArgs& a, const Rows& rows, int q, int cnt,
 // ------------------------------------------------------------------------------------------------
 // scan_round: the DCOs of one round for every query.
 template <typename ST, bool DADE, bool RERANK, bool PER_DIM>
-__global__ __launch_bounds__(kThreads) void scan_round_kernel(RoundArgs a, int r) {
+// qrot is passed on its own, restrict-qualified: nothing the kernel stores aliases it, so the
+// reads of a work item's query (one query per item) can go through the scalar cache.
+__global__ __launch_bounds__(kThreads) void scan_round_kernel(RoundArgs a, int r, const float* __restrict__ qrot) {
   using SS = Store<ST>;
   constexpr int MB = SS::kMaxB;
   __shared__ int4 stack_lds[kWaves][kStack];
@@ -318,23 +320,19 @@ __global__ __launch_bounds__(kThreads) void scan_round_kernel(RoundArgs a, int r
   int sn = 0;             // live stack entries (wave-uniform)
   // The next work item and its query's round snapshot are fetched one item ahead, so that their
   // dependent loads overlap the current item's work.
+  // (an item carries its query's snapshot, so it is all a DCO needs besides the rows; it is
+  // fetched together with the round's item count, inside the region's capacity)
   auto claim = [&](int4& it) {
     int k = 0;
     if (lane == 0) k = atomicAdd(&s_claim, 1);
-    k = __shfl(k, 0);
+    k = __builtin_amdgcn_readfirstlane(k);   // every lane is active here
     const int64_t idx = int64_t(blockIdx.x) + int64_t(k) * gridDim.x;
-    if (idx >= n_items) return false;
+    if (idx >= a.items_cap) return false;
     it = items[idx];
-    return true;
+    return idx < n_items;
   };
   int4 nit = make_int4(0, 0, 0, 0);
   bool nvalid = claim(nit);
-  float nr2 = 0.f;
-  unsigned long long nkeyr = 0;
-  if (nvalid) {
-    nr2 = a.q_r2[nit.x];
-    nkeyr = a.q_keyr[nit.x];
-  }
   for (;;) {
     const bool drained = !nvalid;   // no work item left in this round
     if (sn >= 64 || (drained && sn > 0)) {
@@ -357,7 +355,7 @@ __global__ __launch_bounds__(kThreads) void scan_round_kernel(RoundArgs a, int r
         nb = nb > nblk - b ? nblk - b : nb;
         bool rej = false;
         int dexit = dim;
-        advance<ST, PER_DIM, MB>(rows, p, a.qrot + int64_t(q) * dp, r2, a.T, dim, dd, true, b, nb, S,
+        advance<ST, PER_DIM, MB>(rows, p, qrot + int64_t(q) * dp, r2, a.T, dim, dd, true, b, nb, S,
                                  rej, dexit);
         b += nb;
         if (rej || b >= nblk) {
@@ -382,36 +380,31 @@ __global__ __launch_bounds__(kThreads) void scan_round_kernel(RoundArgs a, int r
 
     // ---- the prefetched work item; claim the next one
     const int4 it = nit;
-    const float r2 = nr2;
-    const unsigned long long keyr = nkeyr;
     nvalid = claim(nit);
-    const int q = it.x, cnt = it.y;
+    // an item's fields are the same in every lane
+    const uint32_t qc = uint32_t(__builtin_amdgcn_readfirstlane(it.x));
+    const int q = int(qc & ((1u << kItemCountShift) - 1)), cnt = int(qc >> kItemCountShift);
+    const int p_item = __builtin_amdgcn_readfirstlane(it.y);
+    const unsigned long long keyr = (static_cast<unsigned long long>(uint32_t(__builtin_amdgcn_readfirstlane(it.z))) << 32) |
+                                    uint32_t(__builtin_amdgcn_readfirstlane(it.w));
     const bool full = keyr != ~0ull;
-    const float* qv = a.qrot + int64_t(q) * dp;
+    const float r2 = full ? key_dist(keyr) : __builtin_inff();
+    const float* qv = qrot + int64_t(q) * dp;
     const bool dense = !any_tests || !full;   // no test can reject: whole rows
     if (dense && cnt <= 16) {
       // few candidates (the rounds that fill the heap): four lanes per row
-      if (nvalid) {
-        nr2 = a.q_r2[nit.x];
-        nkeyr = a.q_keyr[nit.x];
-      }
-      dense_item<ST, RERANK>(a, rows, q, cnt, it.z, qv, full, keyr, gate_f * r2, nblk, lane);
+      dense_item<ST, RERANK>(a, rows, q, cnt, p_item, qv, full, keyr, gate_f * r2, nblk, lane);
       continue;
     }
     const bool has = lane < cnt;
-    const int p = it.z + (has ? lane : 0);
+    const int p = p_item + (has ? lane : 0);
     float S = 0.f;
     bool rej = false, done = true;
     int dexit = dim;
     if (!dense && !PER_DIM && nb0 == 1) {
-      // level 0 (the first test inside the head block): its loads go out before the next
-      // item's snapshot is fetched
+      // level 0 (the first test inside the head block)
       if (has) {
         const typename SS::Block blk = SS::load(rows, p, 0);
-        if (nvalid) {
-          nr2 = a.q_r2[nit.x];
-          nkeyr = a.q_keyr[nit.x];
-        }
         int nt = dd;
 #pragma unroll
         for (int j = 0; j < kBlock / 8; ++j) {   // branch-free, as in advance()
@@ -430,14 +423,6 @@ __global__ __launch_bounds__(kThreads) void scan_round_kernel(RoundArgs a, int r
           nt = at ? nt + dd : nt;
         }
         done = rej || 1 >= nblk;
-      } else if (nvalid) {
-        nr2 = a.q_r2[nit.x];
-        nkeyr = a.q_keyr[nit.x];
-      }
-    } else {
-      if (nvalid) {
-        nr2 = a.q_r2[nit.x];
-        nkeyr = a.q_keyr[nit.x];
       }
     }
     if (!dense && !PER_DIM && nb0 == 1) {
@@ -575,6 +560,11 @@ __device__ void exact_rerank(unsigned long long* keys, int n, const float* __res
   __syncthreads();
 }
 
+// A work item of cnt candidates from packed position p, with an empty heap's snapshot.
+__device__ inline int4 make_item(int q, int cnt, int p) {
+  return make_int4(int(uint32_t(q) | (uint32_t(cnt) << kItemCountShift)), p, -1, -1);
+}
+
 // End (t1, off1) of the round that starts at (t, off) after pos candidates; returns its
 // candidate count.  The first round holds the first max(K, fill_min) candidates; a later round
 // ends at the schedule's next probe-rank boundary (every rank, or ranks 1, 2, 4, ...) or after
@@ -633,7 +623,7 @@ __device__ int round_items(const RoundArgs& a, int4* items, int cap, int slot, i
     }
     const int p0 = int(pos_of(tt));
     for (int ss = s0; ss < s1; ss += per, ++n) {
-      if (slot + n < cap) items[slot + n] = make_int4(q, s1 - ss < per ? s1 - ss : per, p0 + ss, 0);
+      if (slot + n < cap) items[slot + n] = make_item(q, s1 - ss < per ? s1 - ss : per, p0 + ss);
       else atomicOr(a.overflow, 2);
     }
   }
@@ -726,7 +716,7 @@ __global__ __launch_bounds__(64) void plan_kernel(RoundArgs a, int* counts) {
       const int p0 = int(pos_of(tt));
       for (int j = lane; j < n; j += 64) {
         const int ss = s0 + j * per;
-        if (slot + j < a.items_cap) items[slot + j] = make_int4(q, s1 - ss < per ? s1 - ss : per, p0 + ss, 0);
+        if (slot + j < a.items_cap) items[slot + j] = make_item(q, s1 - ss < per ? s1 - ss : per, p0 + ss);
         else atomicOr(a.overflow, 2);
       }
       slot += n;
@@ -793,9 +783,22 @@ __global__ __launch_bounds__(kThreads) void merge_round_kernel(RoundArgs a, int 
   const int n_head = a.kb_cap < kHeadKeys ? int(a.kb_cap) : kHeadKeys;
   for (int i = tid; i < a.k_max; i += kThreads) topk[i] = gtop[i];
   if (tid < n_head) qk[tid] = kb[tid];
+  // the query's items of round r + 1 (they get the snapshot its scan tests against)
+  const bool has_next = r + 1 < a.rounds;
+  const int64_t ro = int64_t(r + 1) * a.nq;
+  const int it_b = has_next ? a.item_off[ro + q] : 0;
+  const int it_e = !has_next ? 0 : (q + 1 < a.nq ? a.item_off[ro + q + 1] : a.n_items[r + 1]);
+  auto put_snapshot = [&](unsigned long long key) {
+    int2* nx = reinterpret_cast<int2*>(a.items + int64_t(r + 1) * a.items_cap);
+    const int e = it_e < a.items_cap ? it_e : a.items_cap;
+    for (int i = it_b + tid; i < e; i += kThreads) nx[2 * i + 1] = make_int2(int(key >> 32), int(uint32_t(key)));
+  };
   if (r >= rq) return;                    // finished in an earlier round
   const bool last = r == rq - 1;
-  if (kc == 0 && !last) return;           // nothing queued: heap and snapshot stay as they are
+  if (kc == 0 && !last) {                 // nothing queued: heap and snapshot stay as they are
+    put_snapshot(keyr);
+    return;
+  }
   int K = a.k_pq ? a.k_pq[q] : a.k_max;
   K = K < 1 ? 1 : (K > a.k_max ? a.k_max : K);
   const int m = kc < a.kb_cap ? kc : int(a.kb_cap);
@@ -897,14 +900,15 @@ __global__ __launch_bounds__(kThreads) void merge_round_kernel(RoundArgs a, int 
     if (st_rr)
       atomicAdd(reinterpret_cast<unsigned long long*>(a.stats + int64_t(q) * 4 + 3), (unsigned long long)st_rr);
   }
+  const bool nfull = topk_n == K;
+  const unsigned long long nkey = nfull ? topk[K - 1] : ~0ull;
   if (tid == 0) {
     a.q_topn[q] = topk_n;
     a.q_kc[q] = 0;
-    const bool nfull = topk_n == K;
-    const unsigned long long nkey = nfull ? topk[K - 1] : ~0ull;
     a.q_keyr[q] = nkey;
     a.q_r2[q] = nfull ? key_dist(nkey) : __builtin_inff();
   }
+  if (!last) put_snapshot(nkey);
   if (last) {
     for (int j = tid; j < a.k_max; j += kThreads) {
       const int64_t o = int64_t(q) * a.k_max + j;
@@ -922,9 +926,9 @@ __global__ __launch_bounds__(kThreads) void merge_round_kernel(RoundArgs a, int 
 template <typename ST, bool DADE, bool RERANK>
 hipError_t launch_round_typed(const RoundArgs& a, int r, hipStream_t s) {
   if (DADE && a.delta_d % 8 != 0)
-    hipLaunchKernelGGL((scan_round_kernel<ST, DADE, RERANK, true>), dim3(a.grid), dim3(kThreads), 0, s, a, r);
+    hipLaunchKernelGGL((scan_round_kernel<ST, DADE, RERANK, true>), dim3(a.grid), dim3(kThreads), 0, s, a, r, a.qrot);
   else
-    hipLaunchKernelGGL((scan_round_kernel<ST, DADE, RERANK, false>), dim3(a.grid), dim3(kThreads), 0, s, a, r);
+    hipLaunchKernelGGL((scan_round_kernel<ST, DADE, RERANK, false>), dim3(a.grid), dim3(kThreads), 0, s, a, r, a.qrot);
   return hipGetLastError();
 }
 
