@@ -72,6 +72,18 @@ struct Store<float> {
     const float4 a = b.x[2 * j], c = b.x[2 * j + 1];
     v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w; v[4] = c.x; v[5] = c.y; v[6] = c.z; v[7] = c.w;
   }
+  // one unit (8 coordinates) of a block, for the quad-per-row levels
+  static constexpr int kQuadMaxB = 4;   // blocks per quad level: 128 bytes of rows per lane
+  struct Unit { float4 a, b; };
+  __device__ static inline Unit load_unit(const Rows& r, int64_t p, int bi, int j) {
+    const float* base = bi == 0 ? static_cast<const float*>(r.head) + p * kBlock
+                                : static_cast<const float*>(r.tail) + p * r.tw + (bi - 1) * kBlock;
+    const float4* v = reinterpret_cast<const float4*>(base + 8 * j);
+    return Unit{v[0], v[1]};
+  }
+  __device__ static inline void unit_of(const Unit& u, float* v) {
+    v[0] = u.a.x; v[1] = u.a.y; v[2] = u.a.z; v[3] = u.a.w; v[4] = u.b.x; v[5] = u.b.y; v[6] = u.b.z; v[7] = u.b.w;
+  }
 };
 
 template <bool BF16>
@@ -87,8 +99,17 @@ struct Store16 {
     for (int i = 0; i < 4; ++i) b.x[i] = v[i];
     return b;
   }
-  __device__ static inline void unit(const Block& b, int j, float* v) {
-    const uint32_t w[4] = {b.x[j].x, b.x[j].y, b.x[j].z, b.x[j].w};
+  __device__ static inline void unit(const Block& b, int j, float* v) { unit_of(Unit{b.x[j]}, v); }
+  // one unit (8 coordinates) of a block, for the quad-per-row levels
+  static constexpr int kQuadMaxB = 8;   // blocks per quad level: 128 bytes of rows per lane
+  struct Unit { uint4 x; };
+  __device__ static inline Unit load_unit(const Rows& r, int64_t p, int bi, int j) {
+    const uint16_t* base = bi == 0 ? static_cast<const uint16_t*>(r.head) + p * kBlock
+                                   : static_cast<const uint16_t*>(r.tail) + p * r.tw + (bi - 1) * kBlock;
+    return Unit{*reinterpret_cast<const uint4*>(base + 8 * j)};
+  }
+  __device__ static inline void unit_of(const Unit& u, float* v) {
+    const uint32_t w[4] = {u.x.x, u.x.y, u.x.z, u.x.w};
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       if (BF16) {
@@ -124,6 +145,12 @@ __device__ inline void q8(const float* qs, int d, float* q) {
   q[0] = a.x; q[1] = a.y; q[2] = a.z; q[3] = a.w; q[4] = b.x; q[5] = b.y; q[6] = b.z; q[7] = b.w;
 }
 
+// Lane J's value of this lane's quad (a DPP quad broadcast).
+template <int J>
+__device__ inline float quad_get(float x) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), J * 0x55, 0xF, 0xF, false));
+}
+
 // Bits of m set below this lane.
 __device__ inline int lanes_below(unsigned long long m) {
   return int(__builtin_amdgcn_mbcnt_hi(uint32_t(m >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(m), 0u)));
@@ -156,6 +183,7 @@ __device__ inline void advance(const Rows& rows, int64_t p, const float* qv, flo
         const float Sn = S + unit_sum(qq, v);
         const bool act = i < nb && !rej && d0 < dim;
         const int d = d0 + 8;
+        // with dd a multiple of kBlock only a block's last unit can end at a tested d
         const float thr = T[(d < dim ? d : dim) - 1] * r2;
         const bool at = act && d == nt;
         const bool rj = at && d < dim && Sn > thr;
@@ -204,6 +232,48 @@ __device__ inline void advance(const Rows& rows, int64_t p, const float* qv, flo
           }
         }
       }
+    }
+  }
+}
+
+// One level of a DCO worked by a quad of lanes (tests at multiples of dd, itself a multiple of 8):
+// lane j of the quad reads unit j of blocks [b, b + nb) (nb <= NB) and the query coordinates it
+// meets, all loads first; the quad exchanges its unit sums and every lane adds them to S unit by
+// unit, so S and the test decisions are those of advance() with the same arguments.  All four
+// lanes of a quad must be active.
+template <typename ST, int NB>
+__device__ inline void advance_quad(const Rows& rows, int64_t p, const float* qv, float r2,
+                                    const float* __restrict__ T, int dim, int dd, int b, int nb, float& S,
+                                    bool& rej, int& dexit, int j) {
+  using SS = Store<ST>;
+  typename SS::Unit u[NB];
+  float qq[NB][8];
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    const int bi = b + (i < nb ? i : nb - 1);   // clamped repeats are loaded in bounds, not counted
+    u[i] = SS::load_unit(rows, p, bi, j);
+    q8(qv, bi * kBlock + 8 * j, qq[i]);
+  }
+  int nt = (b * kBlock / dd + 1) * dd;   // next tested d
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    float v[8];
+    SS::unit_of(u[i], v);
+    const float us = unit_sum(qq[i], v);
+    const float su[4] = {quad_get<0>(us), quad_get<1>(us), quad_get<2>(us), quad_get<3>(us)};
+#pragma unroll
+    for (int jj = 0; jj < kBlock / 8; ++jj) {
+      const int d0 = (b + i) * kBlock + 8 * jj;
+      const float Sn = S + su[jj];
+      const bool act = i < nb && !rej && d0 < dim;
+      const int d = d0 + 8;
+      const bool at = act && d == nt;
+      const float thr = (dd % kBlock != 0 || jj == kBlock / 8 - 1) ? T[(d < dim ? d : dim) - 1] * r2 : 0.f;
+      const bool rj = at && d < dim && Sn > thr;
+      S = act ? Sn : S;
+      dexit = rj ? d : dexit;
+      rej = rej || rj;
+      nt = at ? nt + dd : nt;
     }
   }
 }
@@ -292,9 +362,11 @@ __device__ void dense_item(const RoundArgs& a, const Rows& rows, int q, int cnt,
 // ------------------------------------------------------------------------------------------------
 // scan_round: the DCOs of one round for every query.
 template <typename ST, bool DADE, bool RERANK, bool PER_DIM>
-// qrot is passed on its own, restrict-qualified: nothing the kernel stores aliases it, so the
-// reads of a work item's query (one query per item) can go through the scalar cache.
-__global__ __launch_bounds__(kThreads) void scan_round_kernel(RoundArgs a, int r, const float* __restrict__ qrot) {
+// qrot and T are passed on their own, restrict-qualified: nothing the kernel stores aliases them,
+// so the reads of a work item's query (one query per item) and of the thresholds of its first
+// test can go through the scalar cache.
+__global__ __launch_bounds__(kThreads) void scan_round_kernel(RoundArgs a, int r, const float* __restrict__ qrot,
+                                                              const float* __restrict__ T) {
   using SS = Store<ST>;
   constexpr int MB = SS::kMaxB;
   __shared__ int4 stack_lds[kWaves][kStack];
@@ -335,6 +407,51 @@ __global__ __launch_bounds__(kThreads) void scan_round_kernel(RoundArgs a, int r
   bool nvalid = claim(nit);
   for (;;) {
     const bool drained = !nvalid;   // no work item left in this round
+    if ((sn >= 64 || (drained && sn > 0)) && !PER_DIM && sn <= 16) {
+      // ---- continue the (at most 16) stacked survivors by one level each, a quad of lanes per
+      //      survivor: fewer, larger levels for the few survivors left once the items are done
+      constexpr int QB = SS::kQuadMaxB;
+      const int take = sn < 16 ? sn : 16;
+      const int base = sn - take;
+      const int slot = lane >> 2, j = lane & 3;
+      const bool act = slot < take;
+      int4 e = make_int4(0, 0, 0, 0);
+      if (act) e = stk[base + slot];
+      sn = base;
+      const int q = e.x, p = e.y, lev = e.w & 255;
+      int b = e.w >> 8;
+      float S = __int_as_float(e.z);
+      bool cont = false;
+      if (act) {
+        const float r2 = a.q_r2[q];
+        int nb = 1 << (lev - 1 < 4 ? lev - 1 : 4);
+        nb = nb < nb0 ? nb0 : nb;
+        nb = nb > QB ? QB : nb;
+        nb = nb > nblk - b ? nblk - b : nb;
+        bool rej = false;
+        int dexit = dim;
+        advance_quad<ST, QB>(rows, p, qrot + int64_t(q) * dp, r2, T, dim, dd, b, nb, S, rej, dexit, j);
+        b += nb;
+        if (rej || b >= nblk) {
+          if (j == 0) {
+            if (a.stats) {
+              atomicAdd(reinterpret_cast<unsigned long long*>(a.stats + int64_t(q) * 4 + 0), 1ull);
+              atomicAdd(reinterpret_cast<unsigned long long*>(a.stats + int64_t(q) * 4 + 1),
+                        (unsigned long long)dexit);
+            }
+            const uint32_t rid = uint32_t(a.ids[p]);
+            if (!rej && passes<RERANK>(S, rid, true, a.q_keyr[q], gate_f * r2))
+              put_key(a, q, atomicAdd(a.q_kc + q, 1), make_key(S, rid));
+          }
+        } else {
+          cont = j == 0;
+        }
+      }
+      const unsigned long long m = __ballot(cont);
+      if (cont) stk[sn + lanes_below(m)] = make_int4(q, p, __float_as_int(S), (b << 8) | (lev < 255 ? lev + 1 : 255));
+      sn += __popcll(m);
+      continue;
+    }
     if (sn >= 64 || (drained && sn > 0)) {
       // ---- continue up to 64 stacked survivors by one level each
       const int take = sn < 64 ? sn : 64;
@@ -355,7 +472,7 @@ __global__ __launch_bounds__(kThreads) void scan_round_kernel(RoundArgs a, int r
         nb = nb > nblk - b ? nblk - b : nb;
         bool rej = false;
         int dexit = dim;
-        advance<ST, PER_DIM, MB>(rows, p, qrot + int64_t(q) * dp, r2, a.T, dim, dd, true, b, nb, S,
+        advance<ST, PER_DIM, MB>(rows, p, qrot + int64_t(q) * dp, r2, T, dim, dd, true, b, nb, S,
                                  rej, dexit);
         b += nb;
         if (rej || b >= nblk) {
@@ -414,7 +531,7 @@ __global__ __launch_bounds__(kThreads) void scan_round_kernel(RoundArgs a, int r
           q8(qv, 8 * j, qq);
           const float Sn = S + unit_sum(qq, v);
           const bool act = !rej && d - 8 < dim;
-          const float thr = a.T[(d < dim ? d : dim) - 1] * r2;
+          const float thr = T[(d < dim ? d : dim) - 1] * r2;
           const bool at = act && d == nt;
           const bool rj = at && d < dim && Sn > thr;
           S = act ? Sn : S;
@@ -431,14 +548,14 @@ __global__ __launch_bounds__(kThreads) void scan_round_kernel(RoundArgs a, int r
       // one lane per row (FDScanning, or no d below D to test)
       if (has)
         for (int b = 0; b < nblk; b += MB)
-          advance<ST, false, MB>(rows, p, qv, r2, a.T, dim, dd, false, b, nblk - b < MB ? nblk - b : MB, S,
+          advance<ST, false, MB>(rows, p, qv, r2, T, dim, dd, false, b, nblk - b < MB ? nblk - b : MB, S,
                                  rej, dexit);
     } else if (has) {
       // level 0: up to the first test
       if (nb0 == 1)
-        advance<ST, PER_DIM, 1>(rows, p, qv, r2, a.T, dim, dd, true, 0, 1, S, rej, dexit);
+        advance<ST, PER_DIM, 1>(rows, p, qv, r2, T, dim, dd, true, 0, 1, S, rej, dexit);
       else
-        advance<ST, PER_DIM, MB>(rows, p, qv, r2, a.T, dim, dd, true, 0, nb0, S, rej, dexit);
+        advance<ST, PER_DIM, MB>(rows, p, qv, r2, T, dim, dd, true, 0, nb0, S, rej, dexit);
       done = rej || nb0 >= nblk;
     }
     const bool fin = has && done;
@@ -926,9 +1043,9 @@ __global__ __launch_bounds__(kThreads) void merge_round_kernel(RoundArgs a, int 
 template <typename ST, bool DADE, bool RERANK>
 hipError_t launch_round_typed(const RoundArgs& a, int r, hipStream_t s) {
   if (DADE && a.delta_d % 8 != 0)
-    hipLaunchKernelGGL((scan_round_kernel<ST, DADE, RERANK, true>), dim3(a.grid), dim3(kThreads), 0, s, a, r, a.qrot);
+    hipLaunchKernelGGL((scan_round_kernel<ST, DADE, RERANK, true>), dim3(a.grid), dim3(kThreads), 0, s, a, r, a.qrot, a.T);
   else
-    hipLaunchKernelGGL((scan_round_kernel<ST, DADE, RERANK, false>), dim3(a.grid), dim3(kThreads), 0, s, a, r, a.qrot);
+    hipLaunchKernelGGL((scan_round_kernel<ST, DADE, RERANK, false>), dim3(a.grid), dim3(kThreads), 0, s, a, r, a.qrot, a.T);
   return hipGetLastError();
 }
 
