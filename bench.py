@@ -44,10 +44,16 @@ def recall_at(ids, gt, k):
     return float(np.mean(hits)) / k
 
 
-def scan_source_sha():
+def scan_source_sha(src=None):
+    """Hash of the DCO kernel's sources with comments and blank lines left out (a comment edit
+    does not invalidate the counters)."""
     h = hashlib.sha256()
     for f in ("scan.hip", "kernels.h", "common.h"):
-        h.update(open(os.path.join(ROOT, "paper_2411_17229_amd", "csrc", f), "rb").read())
+        text = src[f] if src else open(os.path.join(ROOT, "paper_2411_17229_amd", "csrc", f)).read()
+        for line in text.splitlines():
+            code = line.split("//", 1)[0].rstrip()
+            if code:
+                h.update(code.encode() + b"\n")
     return h.hexdigest()[:16]
 
 

@@ -10,18 +10,22 @@
 // snapshot), and the round's kept candidates are merged at its end.  Queries never interact, so
 // a query's result does not depend on the batch or on how the work is spread over the GPU.
 //
-// The rounds run for all queries at once, two kernels per round:
+// A plan (count pass, per-round prefix sums, write pass) lays out every query's work items for
+// every round before the first DCO: round cuts depend only on list sizes, K and the schedule.
+// Then the rounds run for all queries at once, two kernels per round:
 //   * scan_round: a persistent grid whose waves pull work items (one query, up to 64
-//     consecutive candidates of one list).  One lane per candidate reads the head block
-//     (coordinates [0, 32), contiguous across a list) and tests S_d > T_d r^2 at d = Delta_d
-//     (Eq. (13) with the hypothesis test in reduced form); a far candidate stops there.  A
-//     survivor goes on a per-wave LDS stack and is continued later, 64 at a time, in levels of
-//     1, 1, 2, 4, ... blocks of 32 coordinates (all loads of a level in flight at once), each
-//     level replaying the tests it covers in order.  Rounds whose heap is not yet full (no test
-//     can reject) and FDScanning read whole rows.
+//     consecutive candidates of one list, and the query's snapshot).  One lane per candidate
+//     reads the head block (coordinates [0, 32), contiguous across a list) and tests
+//     S_d > T_d r^2 at d = Delta_d (Eq. (13) with the hypothesis test in reduced form); a far
+//     candidate stops there.  A survivor goes on a per-wave LDS stack and is continued later in
+//     levels of growing size (all loads of a level in flight at once), each level replaying the
+//     tests it covers in order: 64 survivors at a time, one lane each, while items remain; a
+//     quad of lanes per survivor once the items are done and at most 16 are left.  Rounds whose
+//     heap is not yet full (no test can reject) and FDScanning read whole rows.
 //   * merge_round: one workgroup per query merges the round's queued keys into its top-K (for
 //     low-precision stores through the rerank rule below), takes the snapshot for the next
-//     round, advances the query's cursor and queues the next round's work items.
+//     round and writes it into the query's work items of that round; after the query's last
+//     round it writes the output row.
 // A DCO's partial distance is summed in one order on every path: each 8-coordinate unit's
 // squared differences by an FMA chain from zero, then S_d = S_{d-8} + unit sum, unit after unit.
 // Low-precision stores: a survivor is queued with its stored-precision S_D when the heap is not
