@@ -96,6 +96,7 @@ struct dade_index {
   hipStream_t cap = nullptr;   // origin stream of graph captures (the caller's may be the null stream)
   // the last captured round-launch sequence and the argument bytes it was captured with
   hipGraphExec_t graph_exec = nullptr;
+  const float* last_q = nullptr;   // the query buffer of the last search
   std::vector<unsigned char> graph_key;
 
   std::vector<void*> owned;
@@ -745,10 +746,18 @@ int dade_search(dade_index* ix, const float* Q, int64_t nq, int32_t k, int32_t n
   if (o.record_times) HIPC(hipEventRecord(ix->ev[0], s));
   // a1 + a2: one GEMM gives q' = W^T (q - mu) and the centroid distances (up to ||q - mu||^2,
   // the same for every list); then the probe order by (distance, list id)
-  HIPC(launch_pad_rows(Q, nq, ix->dim, ix->w_qpad, dp, s));
+  // Queries already of the padded width (and float4-aligned) are read in place, without the
+  // padding copy.  The captured launch sequence holds the query pointer, so with graphs on only
+  // a buffer passed again (a serving loop's) is read in place; a new buffer is copied, which
+  // keeps the captured sequence valid.
+  const bool q_in_place = ix->dim == dp && reinterpret_cast<uintptr_t>(Q) % 16 == 0 &&
+                          (!o.use_graph || Q == ix->last_q);
+  ix->last_q = Q;
+  const float* qpad = q_in_place ? Q : ix->w_qpad;
+  if (!q_in_place) HIPC(launch_pad_rows(Q, nq, ix->dim, ix->w_qpad, dp, s));
   GemmArgs g;
   g.M = int(nq); g.N = dp + nl; g.K = dp;
-  g.A = ix->w_qpad; g.lda = dp; g.a_shift = ix->d_mu;
+  g.A = qpad; g.lda = dp; g.a_shift = ix->d_mu;
   g.B = ix->d_B; g.ldb = dp + nl; g.C = ix->w_qrot; g.ldc = dp;
   g.split_col = dp; g.C2 = ix->w_pd; g.ldc2 = nl; g.col_norm = ix->d_cent_norm;
   HIPC(launch_gemm(g, kEpiRotateProbe, s));
@@ -777,7 +786,7 @@ int dade_search(dade_index* ix, const float* Q, int64_t nq, int32_t k, int32_t n
     a.nq = int(cn);
     a.k_pq = k_per_query ? k_per_query + c0 : nullptr;
     a.nprobe_pq = nprobe_per_query ? nprobe_per_query + c0 : nullptr;
-    a.qrot = ix->w_qrot + c0 * dp; a.qorig = ix->w_qpad + c0 * dp;
+    a.qrot = ix->w_qrot + c0 * dp; a.qorig = qpad + c0 * dp;
     a.probes = ix->w_probes + c0 * npm;
     a.out_ids = out_ids + c0 * k; a.out_d2 = out_dist2 + c0 * k;
     a.stats = o.stats ? o.stats + c0 * 4 : nullptr;

@@ -240,39 +240,56 @@ __device__ inline void advance(const Rows& rows, int64_t p, const float* qv, flo
   }
 }
 
-// One level of a DCO worked by a quad of lanes (tests at multiples of dd, itself a multiple of 8):
-// lane j of the quad reads unit j of blocks [b, b + nb) (nb <= NB) and the query coordinates it
-// meets, all loads first; the quad exchanges its unit sums and every lane adds them to S unit by
-// unit, so S and the test decisions are those of advance() with the same arguments.  All four
-// lanes of a quad must be active.
-template <typename ST, int NB>
-__device__ inline void advance_quad(const Rows& rows, int64_t p, const float* qv, float r2,
-                                    const float* __restrict__ T, int dim, int dd, int b, int nb, float& S,
-                                    bool& rej, int& dexit, int j) {
+// Lane k's value of this lane's group of G lanes (G = 4: a DPP quad broadcast).
+template <int G>
+__device__ inline float group_get(float x, int k) {
+  return __shfl(x, (static_cast<int>(threadIdx.x) & 63 & ~(G - 1)) | k, 64);
+}
+
+// One level of a DCO worked by a group of G lanes (G = 4 or 16; tests at multiples of dd, itself a
+// multiple of 8).  Lane l of the group takes unit l % 4 of block offset l / 4 within each step of
+// G / 4 consecutive blocks: it reads that unit of the blocks b + i G/4 + l/4 (steps i < NB; blocks
+// below b + nb) and the query coordinates it meets, all loads first.  The group exchanges its unit
+// sums and every lane adds them to S unit by unit in coordinate order, so S and the test decisions
+// are those of advance() over the same blocks.  All lanes of a group must be active.
+template <typename ST, int NB, int G>
+__device__ inline void advance_group(const Rows& rows, int64_t p, const float* qv, float r2,
+                                     const float* __restrict__ T, int dim, int dd, int b, int nb, float& S,
+                                     bool& rej, int& dexit, int gl) {
   using SS = Store<ST>;
+  constexpr int BPS = G / 4;   // blocks per step
+  const int j = gl & 3, bo = gl >> 2;
   typename SS::Unit u[NB];
   float qq[NB][8];
 #pragma unroll
   for (int i = 0; i < NB; ++i) {
-    const int bi = b + (i < nb ? i : nb - 1);   // clamped repeats are loaded in bounds, not counted
+    int bi = b + i * BPS + bo;
+    bi = bi < b + nb ? bi : b + nb - 1;   // clamped repeats are loaded in bounds, not counted
     u[i] = SS::load_unit(rows, p, bi, j);
     q8(qv, bi * kBlock + 8 * j, qq[i]);
   }
   int nt = (b * kBlock / dd + 1) * dd;   // next tested d
 #pragma unroll
   for (int i = 0; i < NB; ++i) {
+    if (i * BPS >= nb) break;   // the same in every lane of the group
     float v[8];
     SS::unit_of(u[i], v);
     const float us = unit_sum(qq[i], v);
-    const float su[4] = {quad_get<0>(us), quad_get<1>(us), quad_get<2>(us), quad_get<3>(us)};
+    float su[G];
+    if (G == 4) {
+      su[0] = quad_get<0>(us); su[1] = quad_get<1>(us); su[2] = quad_get<2>(us); su[3] = quad_get<3>(us);
+    } else {
 #pragma unroll
-    for (int jj = 0; jj < kBlock / 8; ++jj) {
-      const int d0 = (b + i) * kBlock + 8 * jj;
-      const float Sn = S + su[jj];
-      const bool act = i < nb && !rej && d0 < dim;
+      for (int k = 0; k < G; ++k) su[k] = group_get<G>(us, k);
+    }
+#pragma unroll
+    for (int k = 0; k < G; ++k) {   // block i BPS + k / 4, unit k % 4
+      const int d0 = (b + i * BPS + (k >> 2)) * kBlock + 8 * (k & 3);
+      const float Sn = S + su[k];
+      const bool act = i * BPS + (k >> 2) < nb && !rej && d0 < dim;
       const int d = d0 + 8;
       const bool at = act && d == nt;
-      const float thr = (dd % kBlock != 0 || jj == kBlock / 8 - 1) ? T[(d < dim ? d : dim) - 1] * r2 : 0.f;
+      const float thr = (dd % kBlock != 0 || (k & 3) == 3) ? T[(d < dim ? d : dim) - 1] * r2 : 0.f;
       const bool rj = at && d < dim && Sn > thr;
       S = act ? Sn : S;
       dexit = rj ? d : dexit;
@@ -369,7 +386,7 @@ template <typename ST, bool DADE, bool RERANK, bool PER_DIM>
 // qrot and T are passed on their own, restrict-qualified: nothing the kernel stores aliases them,
 // so the reads of a work item's query (one query per item) and of the thresholds of its first
 // test can go through the scalar cache.
-__global__ __launch_bounds__(kThreads) void scan_round_kernel(RoundArgs a, int r, const float* __restrict__ qrot,
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) void scan_round_kernel(RoundArgs a, int r, const float* __restrict__ qrot,
                                                               const float* __restrict__ T) {
   using SS = Store<ST>;
   constexpr int MB = SS::kMaxB;
@@ -412,32 +429,36 @@ __global__ __launch_bounds__(kThreads) void scan_round_kernel(RoundArgs a, int r
   for (;;) {
     const bool drained = !nvalid;   // no work item left in this round
     if ((sn >= 64 || (drained && sn > 0)) && !PER_DIM && sn <= 16) {
-      // ---- continue the (at most 16) stacked survivors by one level each, a quad of lanes per
-      //      survivor: fewer, larger levels for the few survivors left once the items are done
+      // ---- the wave's items are done and at most 16 survivors are left: continue each by a
+      //      group of lanes (a quad, or 16 lanes when at most 4 are left), in levels of the
+      //      largest size the group's registers hold (QB blocks for a quad, 2 QB for 16 lanes)
       constexpr int QB = SS::kQuadMaxB;
-      const int take = sn < 16 ? sn : 16;
-      const int base = sn - take;
-      const int slot = lane >> 2, j = lane & 3;
+      const bool wide = sn <= 4;
+      const int G = wide ? 16 : 4;
+      const int take = sn;
+      const int slot = wide ? lane >> 4 : lane >> 2, gl = wide ? lane & 15 : lane & 3;
       const bool act = slot < take;
       int4 e = make_int4(0, 0, 0, 0);
-      if (act) e = stk[base + slot];
-      sn = base;
+      if (act) e = stk[slot];
+      sn = 0;
       const int q = e.x, p = e.y, lev = e.w & 255;
       int b = e.w >> 8;
       float S = __int_as_float(e.z);
       bool cont = false;
       if (act) {
         const float r2 = a.q_r2[q];
-        int nb = 1 << (lev - 1 < 4 ? lev - 1 : 4);
-        nb = nb < nb0 ? nb0 : nb;
-        nb = nb > QB ? QB : nb;
+        int nb = wide ? (QB / 2) * 4 : QB;
         nb = nb > nblk - b ? nblk - b : nb;
         bool rej = false;
         int dexit = dim;
-        advance_quad<ST, QB>(rows, p, qrot + int64_t(q) * dp, r2, T, dim, dd, b, nb, S, rej, dexit, j);
+        const float* qq = qrot + int64_t(q) * dp;
+        if (wide)
+          advance_group<ST, QB / 2, 16>(rows, p, qq, r2, T, dim, dd, b, nb, S, rej, dexit, gl);
+        else
+          advance_group<ST, QB, 4>(rows, p, qq, r2, T, dim, dd, b, nb, S, rej, dexit, gl);
         b += nb;
         if (rej || b >= nblk) {
-          if (j == 0) {
+          if (gl == 0) {
             if (a.stats) {
               atomicAdd(reinterpret_cast<unsigned long long*>(a.stats + int64_t(q) * 4 + 0), 1ull);
               atomicAdd(reinterpret_cast<unsigned long long*>(a.stats + int64_t(q) * 4 + 1),
@@ -448,7 +469,7 @@ __global__ __launch_bounds__(kThreads) void scan_round_kernel(RoundArgs a, int r
               put_key(a, q, atomicAdd(a.q_kc + q, 1), make_key(S, rid));
           }
         } else {
-          cont = j == 0;
+          cont = gl == 0;
         }
       }
       const unsigned long long m = __ballot(cont);
