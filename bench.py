@@ -59,18 +59,18 @@ def scan_source_sha(src=None):
 
 def traffic_from_profile(workload, store, nprobe, p_s):
     """HBM bytes per DCO-kernel launch from the committed rocprofv3 counter summary, if it was taken
-    on the current scan source at the same operating point; else None."""
+    on the current scan source at the same operating point and round schedule; else None."""
     path = os.path.join(ROOT, "profiles", "scan_traffic.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    e = rec.get(f"{workload}/{store}/nprobe{nprobe}/p_s{p_s}")
+    e = rec.get(f"{workload}/{store}/nprobe{nprobe}/p_s{p_s}/fill{SCHEDULE['fill_min']}/growth{SCHEDULE['growth']}")
     if not e or e.get("scan_sha") != scan_source_sha():
         return None
     return e["fetch_bytes_per_launch"] + e["write_bytes_per_launch"]
 
 
-SCHEDULE = dict(schedule="doubling", fill_min=32, growth=16)   # round schedule of the timed runs
+SCHEDULE = dict(schedule="doubling", fill_min=32, growth=0)   # round schedule of the timed runs (no growth cap)
 
 
 def throughput(dade, torch, ix, Qd, k, nprobe, steps, warmup, **kw):
