@@ -138,6 +138,47 @@ def cpu_baseline(w, X, Q, nprobe, p_s, seconds=20.0):
                       f"not timed"}
 
 
+ABL_PS = (0.3, 0.2, 0.1, 0.05, 0.02, 0.01, 0.005)   # P_s of the data-oblivious comparison
+
+
+def oblivious_ablation(dade, torch, ix, Xd, Qd, w, gt, store, pairs, nprobe, steps):
+    """The data-aware transform against a seeded data-oblivious one (the random orthogonal
+    projection of Figure 1): the same lists, store, schedule and calibration pairs; recall@10,
+    fraction of dimensions read and QPS over P_s, and the variance each captures in its first d
+    dimensions.  Leaves ix calibrated at the last P_s."""
+    from paper_2411_17229_amd import workloads
+    nq = Qd.shape[0]
+    art = dade.dade_export(ix)
+    W_r = workloads.oblivious_rotation(w.dim, w.seed)
+    # variance along each random axis, from the data-aware eigendecomposition (reported only;
+    # the test uses the calibrated T_d)
+    lam_r = ((art["W"].T @ W_r) ** 2 * art["lam"][:, None]).sum(0)
+    keep = {k: v for k, v in art.items() if k not in ("T", "delta", "W", "lam")}
+    rop = dade.dade_import({**keep, "W": W_r, "lam": lam_r}, Xd, store=store)
+    out = {"transform": "seeded Haar rotation", "nprobe": nprobe, "delta_d": w.delta_d,
+           "variance_frac": {}, "by_p_s": {}}
+    for name, lam in (("data_aware", art["lam"]), ("oblivious", lam_r)):
+        c = np.cumsum(lam) / lam.sum()
+        out["variance_frac"][name] = {str(dd): round(float(c[dd - 1]), 4) for dd in (32, 64, 128, 256, w.dim // 2)}
+    for ps in ABL_PS:
+        row = {}
+        for name, index in (("data_aware", ix), ("oblivious", rop)):
+            dade.dade_calibrate(index, ps, pairs=pairs)
+            stats = torch.zeros((nq, 4), dtype=torch.int64, device=Qd.device)
+            ids, _ = dade.dade_search(index, Qd, w.k, nprobe, stats=stats, delta_d=w.delta_d, **SCHEDULE)
+            torch.cuda.synchronize()
+            dade.dade_check(index)
+            st = stats.cpu().numpy().sum(0)
+            ms = throughput(dade, torch, index, Qd, w.k, nprobe, steps, 2, delta_d=w.delta_d, **SCHEDULE)
+            row[name] = {"recall@10": round(recall_at(ids.cpu().numpy(), gt, w.k), 4),
+                         "dims_frac": round(float(st[1]) / max(1, st[0] * w.dim), 4),
+                         "qps": round(nq / (ms / 1e3), 1)}
+        out["by_p_s"][str(ps)] = row
+        log(f"[bench] ablation P_s {ps}: {row}")
+    rop.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -149,6 +190,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--no-ablation", action="store_true",
+                    help="skip the data-aware vs data-oblivious transform comparison")
     ap.add_argument("--profile-only", action="store_true",
                     help="build, then only run timed DADE steps at --nprobe / --p-s (for profilers)")
     ap.add_argument("--nprobe", type=int, default=None)
@@ -332,6 +375,9 @@ def main():
                 out["recall@10_vs_f32_path"] = round(recall_at(ids_main.cpu().numpy(), ids_v, w.k), 4)
             vi.close()
         out["variants"] = variants
+    if not args.no_ablation:
+        out["ablation"] = oblivious_ablation(dade, torch, ix, Xd, Qd, w, gt, store, pairs, d["nprobe"],
+                                             max(3, args.steps // 4))
     if not args.no_cpu:
         log("[bench] CPU oracle baseline ...")
         out["cpu_baseline"] = cpu_baseline(w, X, Q, d["nprobe"], d["p_s"], args.cpu_seconds)

@@ -143,14 +143,20 @@ class LazyRotated:
         return self.rounding(y) if self.rounding is not None else y
 
 
-def build(X, nlist, init_rows, pairs, p_s=0.1, iters=10, store=None):
+def build(X, nlist, init_rows, pairs, p_s=0.1, iters=10, store=None, rotation=None):
     """Oracle index: transform, k-means lists and eps_d from the given pairs.
 
     ``store`` (callable on rotated rows, e.g. ``lowp`` rounding) makes a low-precision
     index: tests read the rounded coordinates, eps_d and delta are calibrated on them.
+    ``rotation`` (an orthogonal D x D matrix, columns the axes) replaces the data-aware W: the
+    data-oblivious comparison of Figure 1, with lambda_k the variance along each axis and the
+    same empirical calibration of eps_d.
     """
     from . import lowp
     mu, W, lam = pca.fit(X)
+    if rotation is not None:
+        W = np.asarray(rotation, dtype=np.float64)
+        lam = pca.axis_variances(X, mu, W)
     C = kmeans(X, init_rows, iters)
     offsets, ids = build_lists(assign(X, C), nlist)
     Y = pca.rotate(X, mu, W)

@@ -14,8 +14,13 @@ centred data; each eigenvector's sign is fixed so that its entry of largest
 magnitude is positive (the first such entry on ties).  Signs do not change any
 distance; the rule only makes artifacts comparable.
 
+Data-oblivious comparison (the random orthogonal projection of Figure 1): any orthogonal W
+with lambda_k = Var(w_k^T X), the variance along each axis (for the data-aware W these are the
+eigenvalues, Eq. (12)).
+
 Pins: orthonormality, distance preservation, trace identity (Lemma 2),
-diagonal rotated covariance (Eq. (12)), SVD of the centred data.
+diagonal rotated covariance (Eq. (12)), SVD of the centred data; axis variances equal the
+eigenvalues for the data-aware W and sum to the trace for any orthogonal W.
 """
 from __future__ import annotations
 
@@ -59,3 +64,9 @@ def fit(X):
 def rotate(X, mu, W) -> np.ndarray:
     """W^T (x - mu) for every row x (stored once; Lemma 1 makes the shift free)."""
     return (np.asarray(X, dtype=np.float64) - mu) @ W
+
+
+def axis_variances(X, mu, W) -> np.ndarray:
+    """Var(w_k^T X) for every column w_k of W: the mean square of the rotated, centred data."""
+    Y = rotate(X, mu, W)
+    return np.mean(Y * Y, axis=0)

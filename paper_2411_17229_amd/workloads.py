@@ -72,6 +72,12 @@ def haar_rotation(rng: np.random.Generator, dim: int) -> np.ndarray:
     return q * np.sign(np.diag(r))[None, :]
 
 
+def oblivious_rotation(dim: int, seed: int = 0) -> np.ndarray:
+    """A seeded Haar-random orthogonal matrix (columns are the axes), drawn from its own stream:
+    the data-oblivious transform that the data-aware one is compared with."""
+    return haar_rotation(np.random.default_rng(np.random.SeedSequence(entropy=seed, spawn_key=(7919,))), dim)
+
+
 def _mixture(rng_lab, rng_noise, centres, rot, sqrt_lam, count, chunk=1 << 16):
     """Rows drawn in float32 (noise, scaling and rotation), chunk by chunk."""
     dim = centres.shape[1]

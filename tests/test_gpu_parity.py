@@ -246,3 +246,31 @@ def test_low_precision_rerank_rule_parity(store, delta):
                                  rerank_delta=delta)
         compare(o_ids, logs, g_ids, g_d2, X, Q, K)
     gi.close()
+
+
+def test_data_oblivious_rotation_matches_oracle():
+    """The data-oblivious comparison (a seeded Haar rotation in place of the data-aware W, Figure 1)
+    through the same boundary: imported, calibrated on the GPU (T_d as the oracle's), and searched
+    as the oracle searches the same index."""
+    _need_gpu()
+    w = workloads.WORKLOADS["small-20k-d128"]
+    X, Q = workloads.make(w)
+    rot = workloads.oblivious_rotation(w.dim, w.seed)
+    init = workloads.kmeans_init_rows(len(X), w.nlist, w.seed)
+    pairs = workloads.calibration_pairs(len(X), 100_000, w.seed)
+    oi = ivf.build(X, w.nlist, init, pairs, p_s=w.alpha, iters=10, rotation=rot)
+    Xd, Qd = torch.from_numpy(X).cuda(), torch.from_numpy(Q).cuda()
+    art = artifacts(oi)
+    art["T"] = None
+    gi = dade.dade_import(art, Xd)
+    dade.dade_calibrate(gi, w.alpha, pairs=pairs)
+    assert np.max(np.abs(dade.dade_export(gi)["T"] - oi.T)) < 1e-9
+    o_ids, _, logs = ivf.search(oi, Q, w.k, w.nprobe, w.delta_d, schedule="doubling", log=True)
+    stats = torch.zeros((w.n_queries, 4), dtype=torch.int64, device="cuda")
+    g_ids, g_d2 = gpu_search(gi, Qd, w.k, w.nprobe, delta_d=w.delta_d, schedule="doubling", stats=stats)
+    compare(o_ids, logs, g_ids, g_d2, X, Q, w.k)
+    st = to_np(stats)
+    np.testing.assert_array_equal(st[:, 0], logs["dcos"].astype(np.int64))
+    rel = np.abs(st[:, 1] - logs["dims"]) / logs["dims"]
+    assert np.median(rel) == 0.0 and rel.max() < 0.02
+    gi.close()
