@@ -39,6 +39,23 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def ground_truth(torch, Xd, Qd, k, chunk=64):
+    """Exact k nearest rows of every query (measurement only): FP64 squared distances on the GPU,
+    ordered by (distance, id)."""
+    X64 = Xd.double()
+    xn = (X64 * X64).sum(1)
+    out = []
+    for s in range(0, Qd.shape[0], chunk):
+        q = Qd[s:s + chunk].double()
+        d2 = xn[None, :] - 2.0 * (q @ X64.T) + (q * q).sum(1, keepdim=True)
+        d, i = torch.topk(d2, k + 8, dim=1, largest=False)
+        d, i = d.cpu().numpy(), i.cpu().numpy()
+        for r in range(len(d)):
+            o = np.lexsort((i[r], d[r]))[:k]
+            out.append(i[r][o])
+    return np.stack(out).astype(np.int64)
+
+
 def recall_at(ids, gt, k):
     hits = [len(set(ids[i, :k].tolist()) & set(gt[i, :k].tolist())) for i in range(len(gt))]
     return float(np.mean(hits)) / k
@@ -179,6 +196,42 @@ def oblivious_ablation(dade, torch, ix, Xd, Qd, w, gt, store, pairs, nprobe, ste
     return out
 
 
+LIN_DD = (1, 2, 4, 8, 16, 32, 64)   # Delta_d of the linear-scan study
+LIN_SCHEDULE = dict(schedule="doubling", fill_min=32, growth=16)   # growth-capped rounds tighten r inside the one list
+
+
+def linear_scan(dade, torch, w, store, p_s, steps, n=100_000, nq=200):
+    """Linear-scan feasibility (one list holds every row, so every query scans all n rows): DADE
+    at each Delta_d against FDScanning on the same index; recall@10, fraction of dimensions read
+    and QPS.  Rows and queries come from the workload's generator (its first n rows)."""
+    from paper_2411_17229_amd import workloads
+    X, Q = workloads.make(w, n=n, n_queries=nq)
+    Xd, Qd = torch.from_numpy(X).to("cuda:0"), torch.from_numpy(Q).to("cuda:0")
+    ix = dade.dade_build_index(Xd, 1, store=store, init_rows=np.zeros(1, np.int64))
+    dade.dade_rotate(ix)
+    dade.dade_calibrate(ix, p_s, pairs=workloads.calibration_pairs(n, 100_000, w.seed))
+    gt = ground_truth(torch, Xd, Qd, w.k)
+    out = {"n": n, "dim": w.dim, "queries_per_step": nq, "store": store, "p_s": p_s, "nlist": 1,
+           "schedule": LIN_SCHEDULE, "by_delta_d": {}}
+    for mode, dds in (("full_d", (w.delta_d,)), ("dade", LIN_DD)):
+        for dd in dds:
+            stats = torch.zeros((nq, 4), dtype=torch.int64, device=Qd.device)
+            ids, _ = dade.dade_search(ix, Qd, w.k, 1, stats=stats, delta_d=dd, mode=mode, **LIN_SCHEDULE)
+            torch.cuda.synchronize()
+            dade.dade_check(ix)
+            st = stats.cpu().numpy().sum(0)
+            ms = throughput(dade, torch, ix, Qd, w.k, 1, steps, 1, delta_d=dd, mode=mode, **LIN_SCHEDULE)
+            row = {"recall@10": round(recall_at(ids.cpu().numpy(), gt, w.k), 4),
+                   "dims_frac": round(float(st[1]) / max(1, st[0] * w.dim), 4), "qps": round(nq / (ms / 1e3), 1)}
+            if mode == "full_d":
+                out["full_d"] = row
+            else:
+                out["by_delta_d"][str(dd)] = row
+            log(f"[bench] linear scan {mode} delta_d {dd}: {row}")
+    ix.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -192,6 +245,7 @@ def main():
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-ablation", action="store_true",
                     help="skip the data-aware vs data-oblivious transform comparison")
+    ap.add_argument("--no-linear", action="store_true", help="skip the linear-scan (one list) study")
     ap.add_argument("--profile-only", action="store_true",
                     help="build, then only run timed DADE steps at --nprobe / --p-s (for profilers)")
     ap.add_argument("--nprobe", type=int, default=None)
@@ -244,9 +298,8 @@ def main():
         log(f"[bench] profile run ({args.mode}, nprobe {npb}, P_s {args.p_s or w.alpha}): {ms:.3f} ms/step")
         return
 
-    from oracle import knn
     t0 = time.perf_counter()
-    gt, gt_d2 = knn.brute_force(X, Q, w.k)
+    gt = ground_truth(torch, Xd, Qd, w.k)
     log(f"[bench] FP64 ground truth in {time.perf_counter() - t0:.1f}s")
 
     pairs = workloads.calibration_pairs(w.n, 100_000, w.seed)
@@ -378,6 +431,8 @@ def main():
     if not args.no_ablation:
         out["ablation"] = oblivious_ablation(dade, torch, ix, Xd, Qd, w, gt, store, pairs, d["nprobe"],
                                              max(3, args.steps // 4))
+    if not args.no_linear:
+        out["linear_scan"] = linear_scan(dade, torch, w, store, d["p_s"], max(3, args.steps // 4))
     if not args.no_cpu:
         log("[bench] CPU oracle baseline ...")
         out["cpu_baseline"] = cpu_baseline(w, X, Q, d["nprobe"], d["p_s"], args.cpu_seconds)

@@ -63,7 +63,8 @@ struct dade_index {
   int64_t* d_off = nullptr;    // [nlist + 1]
   int32_t* d_ids = nullptr;    // [n] packed position -> row id
   int64_t* d_pos = nullptr;    // [n] row id -> packed position
-  float* d_B = nullptr;        // [dp x (dp + nlist)] FP32 [W | (C - mu)^T] (zero padded)
+  float* d_B = nullptr;        // [dp x ldB] FP32 [W | (C - mu)^T] (zero padded)
+  int ldB = 0;                 // dp + nlist rounded up to a multiple of 4 (float4 rows)
   float* d_mu = nullptr;       // [dp]
   float* d_cent_norm = nullptr;// [nlist] ||c - mu||^2
   void* d_store = nullptr;     // rotated coordinates in list order, head/tail layout (stored_index)
@@ -220,7 +221,8 @@ int set_lists(dade_index* ix, const std::vector<int32_t>& lab, hipStream_t s) {
 // the others (q - mu).(c - mu); W is orthogonal, so ||q' - c'||^2 = ||q - c||^2 (Lemma 1).
 int apply_transform(dade_index* ix, hipStream_t s) {
   const int dim = ix->dim, dp = ix->dp, nl = ix->nlist;
-  const int64_t ldb = int64_t(dp) + nl;
+  const int64_t ldb = (int64_t(dp) + nl + 3) / 4 * 4;   // the GEMM reads rows as float4
+  ix->ldB = int(ldb);
   int rc;
   std::vector<float> Bf(size_t(dp) * ldb, 0.f), muf(dp, 0.f), cn(nl, 0.f);
   for (int i = 0; i < dim; ++i)
@@ -758,7 +760,7 @@ int dade_search(dade_index* ix, const float* Q, int64_t nq, int32_t k, int32_t n
   GemmArgs g;
   g.M = int(nq); g.N = dp + nl; g.K = dp;
   g.A = qpad; g.lda = dp; g.a_shift = ix->d_mu;
-  g.B = ix->d_B; g.ldb = dp + nl; g.C = ix->w_qrot; g.ldc = dp;
+  g.B = ix->d_B; g.ldb = ix->ldB; g.C = ix->w_qrot; g.ldc = dp;
   g.split_col = dp; g.C2 = ix->w_pd; g.ldc2 = nl; g.col_norm = ix->d_cent_norm;
   HIPC(launch_gemm(g, kEpiRotateProbe, s));
   if (o.record_times) HIPC(hipEventRecord(ix->ev[1], s));

@@ -274,3 +274,25 @@ def test_data_oblivious_rotation_matches_oracle():
     rel = np.abs(st[:, 1] - logs["dims"]) / logs["dims"]
     assert np.median(rel) == 0.0 and rel.max() < 0.02
     gi.close()
+
+
+@pytest.mark.parametrize("dd", [1, 4, 16])
+def test_linear_scan_one_list(dd):
+    """One list holding every row (the linear-scan study): growth-capped rounds inside the list
+    and DADE at small Delta_d (per-dimension tests for 1 and 4), against the oracle."""
+    _need_gpu()
+    w = workloads.WORKLOADS["small-20k-d128"]
+    X, Q = workloads.make(w, n=4000, n_queries=24)
+    oi, _, _ = oracle_index(X, 1, w.seed, n_pairs=20000, alpha=w.alpha)
+    gi = dade.dade_import(artifacts(oi), torch.from_numpy(X).cuda())
+    Qd = torch.from_numpy(Q).cuda()
+    sched = dict(schedule="doubling", fill_min=32, growth=16)
+    o_ids, _, logs = ivf.search(oi, Q, w.k, 1, dd, log=True, **sched)
+    stats = torch.zeros((len(Q), 4), dtype=torch.int64, device="cuda")
+    g_ids, g_d2 = gpu_search(gi, Qd, w.k, 1, delta_d=dd, stats=stats, **sched)
+    compare(o_ids, logs, g_ids, g_d2, X, Q, w.k)
+    st = to_np(stats)
+    np.testing.assert_array_equal(st[:, 0], logs["dcos"].astype(np.int64))
+    rel = np.abs(st[:, 1] - logs["dims"]) / logs["dims"]
+    assert np.median(rel) == 0.0 and rel.max() < 0.02
+    gi.close()
