@@ -640,6 +640,21 @@ __device__ inline void keep_below(unsigned long long* c, int n, unsigned long lo
   __syncthreads();
 }
 
+// An upper bound on the K-th smallest of c(0..n): the K-th smallest of its first 64 entries
+// (wave 0 ranks them by shuffles), or ~0 when that cannot help (n <= 96, K > 64).  Keys are
+// unique.  To *t; ends with a barrier.
+template <typename GetFn>
+__device__ inline void sample_bound(GetFn c, int n, int K, unsigned long long* t, int tid) {
+  if (tid == 0) *t = ~0ull;
+  if (n > 96 && K <= 64 && tid < 64) {
+    const unsigned long long key = c(tid);
+    int rank = 0;
+    for (int j = 0; j < 64; ++j) rank += int(__shfl(key, j) < key);
+    if (rank == K - 1) *t = key;
+  }
+  __syncthreads();
+}
+
 // heap[0..heap_n) (ascending keys) <- the K smallest of heap and cand[0..n); keys are unique,
 // so each key's rank is the count of smaller keys.  cand must have room for pad8(n + K)
 // entries.  Ends with a barrier.
@@ -908,8 +923,8 @@ __global__ __launch_bounds__(kThreads) void merge_round_kernel(RoundArgs a, int 
   __shared__ __align__(16) unsigned long long fk[RERANK ? kMaxK : 8];
   __shared__ __align__(16) unsigned long long cand[kMergeChunk + kMaxK];
   __shared__ __align__(16) unsigned long long qk[kMergeChunk];   // the queued keys, when they fit
-  __shared__ int s_nc;
-  __shared__ unsigned long long s_b;
+  __shared__ int s_nc, s_below;
+  __shared__ unsigned long long s_b, s_t;
 
   const int q = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63;
@@ -957,16 +972,25 @@ __global__ __launch_bounds__(kThreads) void merge_round_kernel(RoundArgs a, int 
   if (!RERANK) {
     for (int base = 0; base < m; base += kMergeChunk) {
       const int cnt = m - base < kMergeChunk ? m - base : kMergeChunk;
+      // only keys below the heap's K-th, and (a bound from a sample) among the chunk's K smallest
+      sample_bound([&](int i) { return queued(base + i); }, cnt, K, &s_t, tid);
       const unsigned long long kth = topk_n == K ? topk[K - 1] : ~0ull;
-      if (tid == 0) s_nc = 0;
+      const unsigned long long lim = s_t < kth ? s_t : kth;
+      if (tid == 0) {
+        s_nc = 0;
+        s_below = 0;
+      }
       __syncthreads();
       for (int i0 = 0; i0 < cnt; i0 += kThreads) {
         const int i = i0 + tid;
         const unsigned long long key = i < cnt ? queued(base + i) : ~0ull;
-        append_lds(cand, &s_nc, i < cnt && key < kth, key, lane);
+        const bool below = i < cnt && key < kth;   // kept: below the heap's K-th
+        const unsigned long long mb = __ballot(below);
+        if (lane == 0 && mb) atomicAdd(&s_below, __popcll(mb));
+        append_lds(cand, &s_nc, below && key <= lim, key, lane);
       }
       __syncthreads();
-      if (tid == 0) st_kept += unsigned(s_nc);
+      if (tid == 0) st_kept += unsigned(s_below);
       merge_into(topk, topk_n, newk, cand, s_nc, K, tid);
     }
   } else if (m > 0) {
@@ -980,13 +1004,15 @@ __global__ __launch_bounds__(kThreads) void merge_round_kernel(RoundArgs a, int 
     } else {
       for (int base = 0; base < m; base += kMergeChunk) {
         const int cnt = m - base < kMergeChunk ? m - base : kMergeChunk;
+        sample_bound([&](int i) { return queued(base + i); }, cnt, K, &s_t, tid);
         const unsigned long long kth = fn == K ? fk[K - 1] : ~0ull;
+        const unsigned long long lim = s_t < kth ? s_t : kth;
         if (tid == 0) s_nc = 0;
         __syncthreads();
         for (int i0 = 0; i0 < cnt; i0 += kThreads) {
           const int i = i0 + tid;
           const unsigned long long key = i < cnt ? queued(base + i) : ~0ull;
-          append_lds(cand, &s_nc, i < cnt && key < kth, key, lane);
+          append_lds(cand, &s_nc, i < cnt && key < kth && key <= lim, key, lane);
         }
         __syncthreads();
         merge_into(fk, fn, newk, cand, s_nc, K, tid);
