@@ -35,11 +35,12 @@ def oracle_from_library(gi, X, store):
                      Y_exact=Ye, delta=art["delta"], T=T)
 
 
-def run_workload(name, p_s, nprobe, n_sample, k_per_query=None, nprobe_per_query=None, k=None):
+def run_workload(name, p_s, nprobe, n_sample, k_per_query=None, nprobe_per_query=None, k=None, keep=False,
+                 n_queries=None):
     import torch
     _need_gpu()
     w = workloads.WORKLOADS[name]
-    X, Q = workloads.make(w)
+    X, Q = workloads.make(w, n_queries=n_queries)
     dev = torch.device("cuda:0")
     Xd, Qd = torch.from_numpy(X).to(dev), torch.from_numpy(Q).to(dev)
     gi = dade.dade_build_index(Xd, w.nlist, store=w.store, init_rows=workloads.kmeans_init_rows(w.n, w.nlist, w.seed))
@@ -87,6 +88,8 @@ def run_workload(name, p_s, nprobe, n_sample, k_per_query=None, nprobe_per_query
     # dimensions read agree in aggregate (single decisions may differ at near ties)
     dims_g, dims_o = st[sample, 1][same_probes].sum(), logs["dims"][same_probes].sum()
     assert abs(dims_g - dims_o) <= 0.01 * dims_o, (dims_g, dims_o)
+    if keep:
+        return ids, d2, gi, Qd, kw
     gi.close()
     return ids, d2
 
@@ -108,3 +111,30 @@ def test_fullsize_uneven_batch():
     w = workloads.WORKLOADS["uneven-2m-d256"]
     K, npb = workloads.uneven_batch(w.n_queries, 8, 128, (1, 10, 50, 100), seed=w.seed)
     run_workload("uneven-2m-d256", p_s=0.1, nprobe=128, n_sample=6, k_per_query=K, nprobe_per_query=npb, k=100)
+
+
+def test_fullsize_serving_mix():
+    """5M x 768, BF16, nlist 8192 (the serving workload's index): a batch assembled from seeded
+    requests (each 1..256 queries sharing K in {10, 100} and nprobe in {32, 96}) searched in one
+    launch.  Every distance against FP64 and sampled queries against the oracle; then a few
+    requests searched on their own give exactly their rows of the mixed batch."""
+    import torch
+    w = workloads.WORKLOADS["serve-5m-d768"]
+    _, sizes, ks, nps = workloads.requests(64, 1000.0, seed=w.seed)
+    starts = np.concatenate([[0], np.cumsum(sizes)])
+    n_req = int(np.searchsorted(starts, w.n_queries, side="right")) - 1   # whole requests within the batch
+    nq = int(starts[n_req])
+    K = np.repeat(ks[:n_req], sizes[:n_req]).astype(np.int32)
+    npb = np.repeat(nps[:n_req], sizes[:n_req]).astype(np.int32)
+    assert nq == len(K) and nq > 100
+    ids, d2, gi, Qd, kw = run_workload("serve-5m-d768", p_s=0.1, nprobe=96, n_sample=3, k_per_query=K,
+                                       nprobe_per_query=npb, k=100, keep=True, n_queries=nq)
+    for r in sorted({0, n_req // 2, n_req - 1}):
+        a, b = int(starts[r]), int(starts[r + 1])
+        kp = torch.from_numpy(K[a:b]).to(Qd.device)
+        npp = torch.from_numpy(npb[a:b]).to(Qd.device)
+        i1, d1 = dade.dade_search(gi, Qd[a:b].contiguous(), 100, 96, k_per_query=kp, nprobe_per_query=npp, **kw)
+        torch.cuda.synchronize()
+        assert np.array_equal(to_np(i1), ids[a:b]), r
+        assert np.array_equal(to_np(d1).view(np.uint32), d2[a:b].view(np.uint32)), r
+    gi.close()
