@@ -148,11 +148,68 @@ def cpu_baseline(w, X, Q, nprobe, p_s, seconds=20.0):
             ivf.search(oi, Q[done:done + 1], w.k, nprobe, w.delta_d, **SCHEDULE)
             done += 1
         el = time.perf_counter() - t0
-    return {"value": done / el, "unit": "queries/s", "cores": 1, "kind": "oracle",
-            "sample": f"{done} queries, DADE {SCHEDULE['schedule']} schedule, P_s {p_s}, nprobe {nprobe}, "
-                      f"K {w.k}, over an oracle-built index of a {n_s}-row subsample with nlist {nl_s} "
-                      f"(same list size and D as the workload); one thread; index build {build_s:.1f} s "
-                      f"not timed"}
+    out = {"value": done / el, "unit": "queries/s", "cores": 1, "kind": "oracle",
+           "sample": f"{done} queries, DADE {SCHEDULE['schedule']} schedule, P_s {p_s}, nprobe {nprobe}, "
+                     f"K {w.k}, over an oracle-built index of a {n_s}-row subsample with nlist {nl_s} "
+                     f"(same list size and D as the workload); one thread; index build {build_s:.1f} s "
+                     f"not timed"}
+    # the same search on every host core this job may use: a child process (this one holds the
+    # GPU) builds the same index and forks one single-threaded worker per core over query shards
+    import subprocess
+    import tempfile
+    with tempfile.TemporaryDirectory() as tmp:
+        path = os.path.join(tmp, "sample.npz")
+        np.savez(path, X=Xs, Q=Q)
+        r = subprocess.run([sys.executable, os.path.abspath(__file__), "--oracle-pool", path, "--workload", w.name,
+                            "--nprobe", str(nprobe), "--p-s", str(p_s), "--cpu-seconds", str(seconds)],
+                           capture_output=True, text=True, timeout=600)
+    if r.returncode == 0 and r.stdout.strip():
+        out["all_cores"] = json.loads(r.stdout.strip().splitlines()[-1])
+    else:
+        out["all_cores"] = {"error": (r.stderr or "")[-300:]}
+    return out
+
+
+def oracle_pool(path, w, nprobe, p_s, seconds):
+    """Child of cpu_baseline (no GPU here): the oracle index over the given subsample, then one
+    single-threaded worker per usable core (at most 16) searching every P-th query for ~`seconds`."""
+    import multiprocessing as mp
+
+    from threadpoolctl import threadpool_limits
+
+    from oracle import ivf
+    from paper_2411_17229_amd import workloads
+    d = np.load(path)
+    Xs, Q = d["X"], d["Q"]
+    n_s, nl_s = len(Xs), max(1, w.nlist // 20)
+    global _POOL_INDEX
+    _POOL_INDEX = (ivf.build(Xs, nl_s, workloads.kmeans_init_rows(n_s, nl_s, 0),
+                             workloads.calibration_pairs(n_s, 100_000, 0), p_s=p_s, iters=10), Q, w, nprobe, seconds)
+    cores = min(16, len(os.sched_getaffinity(0)))
+    ctx = mp.get_context("fork")
+    t0 = time.perf_counter()
+    with ctx.Pool(cores) as pool:
+        counts = pool.map(_pool_worker, [(i, cores) for i in range(cores)])
+    el = time.perf_counter() - t0
+    return {"value": sum(counts) / el, "unit": "queries/s", "cores": cores, "kind": "oracle",
+            "sample": f"{sum(counts)} queries over {cores} single-threaded worker processes, same index and "
+                      f"settings as the one-thread run; wall time includes the pool's start"}
+
+
+def _pool_worker(arg):
+    from threadpoolctl import threadpool_limits
+
+    from oracle import ivf
+    i, cores = arg
+    oi, Q, w, nprobe, seconds = _POOL_INDEX
+    done, t0 = 0, time.perf_counter()
+    with threadpool_limits(limits=1):
+        for qi in range(i, len(Q), cores):
+            if time.perf_counter() - t0 >= seconds:
+                break
+            ivf.search(oi, Q[qi:qi + 1], w.k, nprobe, w.delta_d, **SCHEDULE)
+            done += 1
+    return done
 
 
 ABL_PS = (0.3, 0.2, 0.1, 0.05, 0.02, 0.01, 0.005)   # P_s of the data-oblivious comparison
@@ -256,7 +313,13 @@ def main():
                          "does not see kernels replayed from a graph)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy 5 times (HBM counter calibration)")
+    ap.add_argument("--oracle-pool", default=None, help=argparse.SUPPRESS)   # child of the CPU baseline
     args = ap.parse_args()
+    if args.oracle_pool:
+        from paper_2411_17229_amd import workloads
+        print(json.dumps(oracle_pool(args.oracle_pool, workloads.WORKLOADS[args.workload], args.nprobe, args.p_s,
+                                     args.cpu_seconds)), flush=True)
+        return
     if args.copy_probe:
         import torch
         src = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
