@@ -289,6 +289,62 @@ def linear_scan(dade, torch, w, store, p_s, steps, n=100_000, nq=200):
     return out
 
 
+SERVE_RATES = (0.25, 0.5, 0.75, 0.9, 1.0, 1.1)
+
+
+def serving_sweep(dade, ix, Q, gt, k, ks, nprobes, n_req=2000, budget=512 << 20, max_batch=2048, seed=0, **kw):
+    """The serving loop (dade_serve): its saturated throughput (every request arriving at once),
+    then Poisson arrivals at fractions of it: per offered rate, achieved QPS, p50/p99 request latency (arrival to results on
+    the host) and recall@k of the served rows.  Requests hold 1..256 queries (log-uniform) with
+    K and nprobe drawn from `ks` x `nprobes`; their queries cycle through Q and are handed over in
+    pinned host memory (a serving front end's receive buffers), which the loop copies from."""
+    import torch
+
+    from paper_2411_17229_amd import workloads
+    _, sizes, rk, rn = workloads.requests(n_req, 1.0, ks=ks, nprobes=nprobes, seed=seed)
+    sizes = sizes.astype(np.int32)
+    total = int(sizes.sum())
+    rows = np.arange(total) % len(Q)
+    Qs = torch.from_numpy(Q[rows]).pin_memory()
+    k_max, np_max = int(max(ks)), int(max(nprobes))
+    # warm-up (allocations, code objects); then the saturated throughput: every request arrives
+    # at once; then one run per offered rate (sizes, K and nprobe do not depend on the rate: the
+    # gaps are drawn first and scaled by it)
+    dade.dade_serve(ix, np.zeros(8), sizes[:8], rk[:8], rn[:8], Q[rows[: int(sizes[:8].sum())]], k_max, np_max,
+                    budget_bytes=budget, max_batch=max_batch, **kw)
+    bursts = [dade.dade_serve(ix, np.zeros(n_req), sizes, rk, rn, Qs, k_max, np_max, budget_bytes=budget,
+                              max_batch=max_batch, **kw)[3] for _ in range(2)]   # the first pays one-time costs
+    st = min(bursts, key=lambda b: b["wall_s"])
+    sat_qps = st["served_queries"] / st["wall_s"]
+    burst = {"qps": round(sat_qps, 1), "wall_ms": round(st["wall_s"] * 1e3, 3), "launches": st["launches"],
+             "mean_queries_per_launch": round(st["served_queries"] / max(1, st["launches"]), 1)}
+    log(f"[bench] serving burst: {sat_qps:.0f} QPS over {st['launches']} launches")
+    out = []
+    for f in SERVE_RATES:
+        rate_rps = f * sat_qps / sizes.mean()
+        arr = workloads.requests(n_req, rate_rps, ks=ks, nprobes=nprobes, seed=seed)[0]
+        ids, _, lat, st = dade.dade_serve(ix, arr, sizes, rk, rn, Qs, k_max, np_max, budget_bytes=budget,
+                                          max_batch=max_batch, **kw)
+        served = lat >= 0
+        rec = recall_at(ids[:, :k], gt[rows], k)
+        out.append({"offered_fraction": f, "offered_qps": round(f * sat_qps, 1),
+                    "achieved_qps": round(st["served_queries"] / st["wall_s"], 1),
+                    "p50_ms": round(float(np.percentile(lat[served], 50)) * 1e3, 4),
+                    "p99_ms": round(float(np.percentile(lat[served], 99)) * 1e3, 4),
+                    "mean_queries_per_launch": round(st["served_queries"] / max(1, st["launches"]), 1),
+                    "waited_requests": st["waited_requests"], "rejected_requests": st["rejected_requests"],
+                    "host_ms": {"stage": round(st["stage_s"] * 1e3, 3), "launch": round(st["launch_s"] * 1e3, 3),
+                                "retire": round(st["retire_s"] * 1e3, 3)},
+                    "recall@%d" % k: round(rec, 4)})
+        log(f"[bench] serving at {f:.2f} x {sat_qps:.0f} QPS: {out[-1]['achieved_qps']:.0f} QPS, "
+            f"p50 {out[-1]['p50_ms']:.3f} ms, p99 {out[-1]['p99_ms']:.3f} ms, "
+            f"{out[-1]['mean_queries_per_launch']} queries/launch, recall {rec:.4f}")
+    return {"requests_per_rate": n_req, "queries_per_rate": total, "mean_request_queries": round(float(sizes.mean()), 2),
+            "k": list(map(int, ks)), "nprobe": list(map(int, nprobes)), "ring_slots": st["ring_slots"],
+            "workspace_bytes": st["workspace_bytes"], "budget_bytes": budget, "max_batch": max_batch,
+            "pinned_queries": True, "saturated": burst, "rates": out}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -303,6 +359,12 @@ def main():
     ap.add_argument("--no-ablation", action="store_true",
                     help="skip the data-aware vs data-oblivious transform comparison")
     ap.add_argument("--no-linear", action="store_true", help="skip the linear-scan (one list) study")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving-loop sweep")
+    ap.add_argument("--serving-only", action="store_true",
+                    help="build, then only run the serving-loop sweep with the workload's request mix "
+                         "(K in {10, 100}, nprobe in {32, 96}) at --p-s")
+    ap.add_argument("--serve-budget-mib", type=int, default=None,
+                    help="device budget of the serving loop (default 512 MiB; 1 GiB with --serving-only)")
     ap.add_argument("--profile-only", action="store_true",
                     help="build, then only run timed DADE steps at --nprobe / --p-s (for profilers)")
     ap.add_argument("--nprobe", type=int, default=None)
@@ -364,6 +426,15 @@ def main():
     t0 = time.perf_counter()
     gt = ground_truth(torch, Xd, Qd, w.k)
     log(f"[bench] FP64 ground truth in {time.perf_counter() - t0:.1f}s")
+
+    if args.serving_only:
+        mib = args.serve_budget_mib or 1024
+        sv = serving_sweep(dade, ix, Q, gt, w.k, (10, 100), (32, 96), budget=mib << 20, seed=w.seed,
+                           delta_d=w.delta_d, **SCHEDULE)
+        print(json.dumps({"workload": w.name, "n": w.n, "dim": w.dim, "nlist": w.nlist, "store": store,
+                          "p_s": args.p_s or w.alpha, "delta_d": w.delta_d, "schedule": SCHEDULE, "serving": sv}),
+              flush=True)
+        return
 
     pairs = workloads.calibration_pairs(w.n, 100_000, w.seed)
 
@@ -470,6 +541,10 @@ def main():
                      "alg_bytes_per_launch": round(d["alg_round"] / launches), "launches_per_step": launches,
                      "avg_launch_ms": round(avg_ms, 5)},
     }
+    if not args.no_serving:
+        mib = args.serve_budget_mib or 512
+        out["serving"] = serving_sweep(dade, ix, Q, gt, w.k, (w.k,), (d["nprobe"],), budget=mib << 20, seed=w.seed,
+                                       delta_d=w.delta_d, **SCHEDULE)
     if not args.no_variants and store != "f32":
         # the same lists and transform with the other 16-bit store and with FP32 (recall vs FP32)
         art = dade.dade_export(ix)

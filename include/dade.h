@@ -208,6 +208,74 @@ typedef struct {
 /* dade_stage_times -- wait for the last timed dade_search and report its times. */
 int dade_stage_times(dade_index* ix, dade_times* out);
 
+/*
+ * Serving loop (continuous batching over an open arrival process).  Every query is the IVF
+ * search that dade_search runs (end of the Methodology section); the loop around it -- admission,
+ * batching, copies -- is an engineering layer the paper does not describe.
+ *
+ * dade_serve runs a stream of requests against one index and returns when every request has
+ * completed.  Request i arrives arrival_s[i] seconds after the call starts (a non-decreasing
+ * schedule, e.g. Poisson arrivals drawn by the caller) and holds req_queries[i] >= 1 queries that
+ * share K = req_k[i] and nprobe = req_nprobe[i].  The loop, on the calling thread:
+ *   - admits arrived requests in arrival order while the device budget has room: an admitted
+ *     request takes one slot per query in a device ring (query row, K, nprobe, k_max results);
+ *     its rows are copied to the device from Q itself when Q is pinned host memory
+ *     (hipHostMalloc, torch pin_memory), else staged first in a pinned mirror of the ring (a host
+ *     copy that costs host bandwidth); a request that
+ *     does not fit waits (and those behind it); one larger than the whole ring is rejected.
+ *     Admission pauses while the admitted queries not yet launched already fill max_inflight
+ *     launches of max_batch;
+ *   - whenever fewer than max_inflight searches are on the device, launches the admitted queries
+ *     not yet launched (up to max_batch, whole or part requests, contiguous ring slots): their
+ *     slots are copied to the device on a copy stream (overlapping the launches before), and one
+ *     dade_search with per-query K and nprobe runs on `stream` after the copy; requests that
+ *     arrive meanwhile are admitted while it runs and go into the next launch;
+ *   - copies each launch's results back on a second copy stream; a request completes when its
+ *     last query's results are on the host, and its slots are freed.
+ * Each query's result is that of dade_search on the query alone with the same K, nprobe and
+ * options (results do not depend on the batch).
+ * Q: host [sum(req_queries) x dim] FP32 (pinned or pageable), the requests' queries one after
+ * another in request order.  out_ids (host int64) and out_dist2 (host FP32) are [sum(req_queries) x k_max] in the
+ * same order, padded as dade_search's; a rejected request's rows are all (-1, +inf).
+ * out_latency_s (host, nullable): per request, the time from its arrival to its completion in
+ * seconds, -1 for a rejected request.  stats (host, nullable) is filled on success.
+ * Device memory: the search workspace for max_batch queries plus the ring, both within
+ * opts->budget_bytes and within the index's own HBM budget; the ring is freed on return.
+ * Requires the index state search requires; arrival_s non-decreasing and >= 0; 1 <= req_k[i] <=
+ * k_max <= 128; 1 <= req_nprobe[i] <= nprobe_max.  Synchronises `stream` before returning.
+ */
+typedef struct {
+  int64_t budget_bytes;     /* device bytes for the search workspace and the request ring;
+                               0 means 512 MiB */
+  int32_t max_batch;        /* most queries in one launch; 0 means 1024 */
+  int32_t max_inflight;     /* most launches on the device at once; 0 means 2 */
+  int32_t k_max;            /* result row length (the largest K a request may ask for) */
+  int32_t nprobe_max;       /* the largest nprobe a request may ask for */
+  dade_search_opts search;  /* as for dade_search; stats, record_times and use_graph are
+                               ignored (launches are not captured) */
+} dade_serve_opts;
+
+typedef struct {
+  double wall_s;             /* from the call's start (arrival time 0) to the last completion */
+  int64_t served_requests;
+  int64_t rejected_requests;
+  int64_t served_queries;
+  int64_t launches;          /* dade_search launches */
+  int64_t ring_slots;        /* query slots of the ring (what the budget left after the
+                                workspace) */
+  int64_t peak_slots;        /* most ring slots held at once */
+  int64_t waited_requests;   /* requests that found the ring full on arrival and waited */
+  int64_t workspace_bytes;   /* device bytes of the search workspace */
+  double stage_s;            /* host seconds spent staging admitted queries in pinned memory */
+  double launch_s;           /* host seconds spent enqueueing copies and searches */
+  double retire_s;           /* host seconds spent handing results out */
+} dade_serve_stats;
+
+int dade_serve(dade_index* ix, int64_t n_req, const double* arrival_s, const int32_t* req_queries,
+               const int32_t* req_k, const int32_t* req_nprobe, const float* Q,
+               const dade_serve_opts* opts, int64_t* out_ids, float* out_dist2,
+               double* out_latency_s, dade_serve_stats* stats, void* stream);
+
 /* dade_destroy -- free the index and all its device memory (NULL is a no-op). */
 void dade_destroy(dade_index* ix);
 

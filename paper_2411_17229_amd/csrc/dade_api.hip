@@ -73,6 +73,7 @@ struct dade_index {
   std::vector<double> W, mu, lam, T, cent_h;
   double delta = 0.0;
   std::vector<int64_t> off_h, ids_h;
+  std::vector<int64_t> sizes_desc;   // list sizes, largest first (round capacities)
   // search workspace (grown on demand, each with its element count)
   float* w_qpad = nullptr; float* w_qrot = nullptr; float* w_pd = nullptr;
   int32_t* w_probes = nullptr;
@@ -199,6 +200,9 @@ int set_lists(dade_index* ix, const std::vector<int32_t>& lab, hipStream_t s) {
   ix->off_h.assign(ix->nlist + 1, 0);
   for (int64_t i = 0; i < n; ++i) ix->off_h[lab[i] + 1]++;
   for (int l = 0; l < ix->nlist; ++l) ix->off_h[l + 1] += ix->off_h[l];
+  ix->sizes_desc.resize(ix->nlist);
+  for (int l = 0; l < ix->nlist; ++l) ix->sizes_desc[l] = ix->off_h[l + 1] - ix->off_h[l];
+  std::sort(ix->sizes_desc.begin(), ix->sizes_desc.end(), std::greater<int64_t>());
   ix->ids_h.assign(n, 0);
   std::vector<int64_t> fill(ix->off_h.begin(), ix->off_h.end() - 1);
   for (int64_t i = 0; i < n; ++i) ix->ids_h[fill[lab[i]]++] = i;
@@ -266,7 +270,99 @@ int upload_T(dade_index* ix, hipStream_t s) {
   return DADE_OK;
 }
 
+// Sizes of one search's round workspace, from the list sizes, K, nprobe and the schedule.
+struct SearchPlan {
+  int npm = 0, widest = 1, rounds = 0;
+  int64_t kb_cap = 0, first = 0, items_pq = 0, chunk = 0;
+};
+
+// The plan of a search of nq queries (k, nprobe: the largest per-query values) and its workspace,
+// grown on demand (growing synchronises `s`; a workspace already large enough is reused as is).
+int plan_search(dade_index* ix, int64_t nq, int32_t k, int32_t nprobe, const dade_search_opts& o,
+                hipStream_t s, SearchPlan& pl) {
+  int rc;
+  const int dp = ix->dp, nl = ix->nlist;
+  const int npm = std::min<int>(nprobe, nl);
+  // the most candidates one round can hold (per-rank: one list; doubling: its widest round)
+  const std::vector<int64_t>& sizes = ix->sizes_desc;
+  int widest = 1, rounds = npm + 1;
+  if (o.schedule == DADE_SCHED_DOUBLING) {
+    int b = 1, nb = 0;
+    while (b < npm) { widest = std::max(widest, std::min(2 * b, npm) - b); b *= 2; ++nb; }
+    rounds = nb + 2;
+  }
+  int64_t kb_cap = 0, most = 0;   // most: the largest candidate count a query can have
+  for (int i = 0; i < widest && i < nl; ++i) kb_cap += sizes[i];
+  for (int i = 0; i < npm; ++i) most += sizes[i];
+  const int64_t first = std::max<int64_t>(k, o.fill_min);
+  kb_cap = std::max<int64_t>(kb_cap, std::min(first, most));
+  // Rounds cut short by the growth cap: such a round at position p takes growth x p candidates,
+  // so it needs more than (1 + growth) p of them and leaves the position at (1 + growth) p.
+  // Every query's first round ends at p0 >= min(fill_min, most) or later, so its c-th capped
+  // round needs p0 (1 + growth)^c < most.
+  if (o.growth > 0)
+    for (int64_t p = std::max<int64_t>(1, std::min<int64_t>(o.fill_min, most)) * (1 + o.growth); p < most;
+         p *= 1 + o.growth)
+      ++rounds;
+  // work items of one query in one round: its segments cut at 16 candidates (whole-row rounds;
+  // other rounds use 64)
+  const int64_t items_pq = std::max<int64_t>((kb_cap + 15) / 16 + widest + 1, (first + 15) / 16 + npm);
+  // queries per pass: the round workspace stays under 1 GiB
+  const int64_t per_q = kb_cap * 8 + rounds * (items_pq * 16 + 4) + int64_t(k) * 8 + 48;
+  const int64_t chunk =
+      std::max<int64_t>(1, std::min<int64_t>({nq, (int64_t(1) << 30) / per_q, int64_t(kMaxPassQueries)}));
+  // workspace
+  if (nq > ix->w_nq || npm > ix->w_np) {
+    const int64_t new_nq = std::max(nq, ix->w_nq), new_np = std::max<int64_t>(npm, ix->w_np);
+    HIPC(hipStreamSynchronize(s));
+    dev_free(ix, ix->w_qpad, sizeof(float) * ix->w_nq * dp);
+    dev_free(ix, ix->w_qrot, sizeof(float) * ix->w_nq * dp);
+    dev_free(ix, ix->w_pd, sizeof(float) * ix->w_nq * nl);
+    dev_free(ix, ix->w_probes, sizeof(int32_t) * ix->w_nq * ix->w_np);
+    ix->w_qpad = ix->w_qrot = ix->w_pd = nullptr;
+    ix->w_probes = nullptr;
+    ix->w_nq = ix->w_np = 0;
+    if ((rc = alloc_t(ix, &ix->w_qpad, size_t(new_nq) * dp)) || (rc = alloc_t(ix, &ix->w_qrot, size_t(new_nq) * dp)) ||
+        (rc = alloc_t(ix, &ix->w_pd, size_t(new_nq) * nl)) || (rc = alloc_t(ix, &ix->w_probes, size_t(new_nq) * new_np)))
+      return rc;
+    ix->w_nq = new_nq; ix->w_np = new_np;
+  }
+  if ((rc = grow(ix, &ix->w_topk, ix->w_topk_n, chunk * k, s)) || (rc = grow(ix, &ix->w_keyr, ix->w_keyr_n, chunk, s)) ||
+      (rc = grow(ix, &ix->w_r2, ix->w_r2_n, chunk, s)) || (rc = grow(ix, &ix->w_qint, ix->w_qint_n, chunk * 3, s)) ||
+      (rc = grow(ix, &ix->w_kb, ix->w_kb_n, chunk * kb_cap, s)) ||
+      (rc = grow(ix, &ix->w_items, ix->w_items_n, int64_t(rounds) * chunk * items_pq, s)) ||
+      (rc = grow(ix, &ix->w_counter, ix->w_counter_n, rounds, s)) ||
+      (rc = grow(ix, &ix->w_counts, ix->w_counts_n, int64_t(rounds) * chunk, s)))
+    return rc;
+  if (!ix->w_flags) {
+    if ((rc = alloc_t(ix, &ix->w_flags, 1))) return rc;
+    HIPC(launch_fill_i32(ix->w_flags, 1, 0, s));
+  }
+  pl.npm = npm; pl.widest = widest; pl.rounds = rounds;
+  pl.kb_cap = kb_cap; pl.first = first; pl.items_pq = items_pq; pl.chunk = chunk;
+  return DADE_OK;
+}
+
 }  // namespace
+
+// Hooks for the serving loop (serve.hip): device memory counted against the index's HBM budget,
+// and the search workspace sized ahead of time for the largest batch.
+namespace dade {
+int index_alloc(dade_index* ix, void** p, size_t bytes) { return dev_alloc(ix, p, bytes); }
+void index_free(dade_index* ix, void* p, size_t bytes) { dev_free(ix, p, bytes); }
+int index_prepare_search(dade_index* ix, int64_t nq, int32_t k, int32_t nprobe, const dade_search_opts& o,
+                         hipStream_t s, int64_t* workspace_bytes) {
+  SearchPlan pl;
+  const int rc = plan_search(ix, nq, k, nprobe, o, s, pl);
+  if (rc) return rc;
+  const int64_t dp = ix->dp, nl = ix->nlist;
+  *workspace_bytes = ix->w_nq * (2 * dp * 4 + nl * 4 + ix->w_np * 4) + ix->w_topk_n * 8 + ix->w_keyr_n * 8 +
+                     ix->w_r2_n * 4 + ix->w_qint_n * 4 + ix->w_kb_n * 8 + ix->w_items_n * 16 + ix->w_counter_n * 4 +
+                     ix->w_counts_n * 4;
+  return DADE_OK;
+}
+int index_dim(const dade_index* ix) { return ix->dim; }
+}  // namespace dade
 
 extern "C" {
 
@@ -680,64 +776,10 @@ int dade_search(dade_index* ix, const float* Q, int64_t nq, int32_t k, int32_t n
   if (o.stats && (rc = check_device_pointer(o.stats, "stats"))) return rc;
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int dp = ix->dp, nl = ix->nlist;
-  const int npm = std::min<int>(nprobe, nl);
-  // the most candidates one round can hold (per-rank: one list; doubling: its widest round)
-  std::vector<int64_t> sizes(nl);
-  for (int l = 0; l < nl; ++l) sizes[l] = ix->off_h[l + 1] - ix->off_h[l];
-  std::sort(sizes.begin(), sizes.end(), std::greater<int64_t>());
-  int widest = 1, rounds = npm + 1;
-  if (o.schedule == DADE_SCHED_DOUBLING) {
-    int b = 1, nb = 0;
-    while (b < npm) { widest = std::max(widest, std::min(2 * b, npm) - b); b *= 2; ++nb; }
-    rounds = nb + 2;
-  }
-  int64_t kb_cap = 0, most = 0;   // most: the largest candidate count a query can have
-  for (int i = 0; i < widest && i < nl; ++i) kb_cap += sizes[i];
-  for (int i = 0; i < npm; ++i) most += sizes[i];
-  const int64_t first = std::max<int64_t>(k, o.fill_min);
-  kb_cap = std::max<int64_t>(kb_cap, std::min(first, most));
-  // Rounds cut short by the growth cap: such a round at position p takes growth x p candidates,
-  // so it needs more than (1 + growth) p of them and leaves the position at (1 + growth) p.
-  // Every query's first round ends at p0 >= min(fill_min, most) or later, so its c-th capped
-  // round needs p0 (1 + growth)^c < most.
-  if (o.growth > 0)
-    for (int64_t p = std::max<int64_t>(1, std::min<int64_t>(o.fill_min, most)) * (1 + o.growth); p < most;
-         p *= 1 + o.growth)
-      ++rounds;
-  // work items of one query in one round: its segments cut at 16 candidates (whole-row rounds;
-  // other rounds use 64)
-  const int64_t items_pq = std::max<int64_t>((kb_cap + 15) / 16 + widest + 1, (first + 15) / 16 + npm);
-  // queries per pass: the round workspace stays under 1 GiB
-  const int64_t per_q = kb_cap * 8 + rounds * (items_pq * 16 + 4) + int64_t(k) * 8 + 48;
-  const int64_t chunk =
-      std::max<int64_t>(1, std::min<int64_t>({nq, (int64_t(1) << 30) / per_q, int64_t(kMaxPassQueries)}));
-  // workspace
-  if (nq > ix->w_nq || npm > ix->w_np) {
-    const int64_t new_nq = std::max(nq, ix->w_nq), new_np = std::max<int64_t>(npm, ix->w_np);
-    HIPC(hipStreamSynchronize(s));
-    dev_free(ix, ix->w_qpad, sizeof(float) * ix->w_nq * dp);
-    dev_free(ix, ix->w_qrot, sizeof(float) * ix->w_nq * dp);
-    dev_free(ix, ix->w_pd, sizeof(float) * ix->w_nq * nl);
-    dev_free(ix, ix->w_probes, sizeof(int32_t) * ix->w_nq * ix->w_np);
-    ix->w_qpad = ix->w_qrot = ix->w_pd = nullptr;
-    ix->w_probes = nullptr;
-    ix->w_nq = ix->w_np = 0;
-    if ((rc = alloc_t(ix, &ix->w_qpad, size_t(new_nq) * dp)) || (rc = alloc_t(ix, &ix->w_qrot, size_t(new_nq) * dp)) ||
-        (rc = alloc_t(ix, &ix->w_pd, size_t(new_nq) * nl)) || (rc = alloc_t(ix, &ix->w_probes, size_t(new_nq) * new_np)))
-      return rc;
-    ix->w_nq = new_nq; ix->w_np = new_np;
-  }
-  if ((rc = grow(ix, &ix->w_topk, ix->w_topk_n, chunk * k, s)) || (rc = grow(ix, &ix->w_keyr, ix->w_keyr_n, chunk, s)) ||
-      (rc = grow(ix, &ix->w_r2, ix->w_r2_n, chunk, s)) || (rc = grow(ix, &ix->w_qint, ix->w_qint_n, chunk * 3, s)) ||
-      (rc = grow(ix, &ix->w_kb, ix->w_kb_n, chunk * kb_cap, s)) ||
-      (rc = grow(ix, &ix->w_items, ix->w_items_n, int64_t(rounds) * chunk * items_pq, s)) ||
-      (rc = grow(ix, &ix->w_counter, ix->w_counter_n, rounds, s)) ||
-      (rc = grow(ix, &ix->w_counts, ix->w_counts_n, int64_t(rounds) * chunk, s)))
-    return rc;
-  if (!ix->w_flags) {
-    if ((rc = alloc_t(ix, &ix->w_flags, 1))) return rc;
-    HIPC(launch_fill_i32(ix->w_flags, 1, 0, s));
-  }
+  SearchPlan pl;
+  if ((rc = plan_search(ix, nq, k, nprobe, o, s, pl))) return rc;
+  const int npm = pl.npm, rounds = pl.rounds;
+  const int64_t kb_cap = pl.kb_cap, items_pq = pl.items_pq, chunk = pl.chunk;
   if (!ix->cap) HIPC(hipStreamCreateWithFlags(&ix->cap, hipStreamNonBlocking));
   int& occ = ix->scan_occ[ix->store][o.mode][dd % 8 != 0];
   if (occ == 0) occ = round_blocks_per_cu(ix->store, o.mode, dd);

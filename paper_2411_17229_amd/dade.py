@@ -22,7 +22,7 @@ MODES = {"dade": 0, "full_d": 1}
 SCHEDULES = {"per_rank": 0, "doubling": 1}
 STATE_BUILT, STATE_ROTATED, STATE_CALIBRATED = 1, 2, 3
 EXPORTED = ("dade_build_index", "dade_rotate", "dade_calibrate", "dade_search", "dade_check", "dade_index_info",
-            "dade_export", "dade_import", "dade_stage_times", "dade_destroy", "dade_last_error")
+            "dade_export", "dade_import", "dade_stage_times", "dade_serve", "dade_destroy", "dade_last_error")
 
 
 class DadeError(RuntimeError):
@@ -42,6 +42,19 @@ class SearchOpts(ctypes.Structure):
                 ("rerank_delta", ctypes.c_float), ("stats", ctypes.c_void_p),
                 ("record_times", ctypes.c_int32), ("fill_min", ctypes.c_int32), ("growth", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32)]
+
+
+class ServeOpts(ctypes.Structure):
+    _fields_ = [("budget_bytes", ctypes.c_int64), ("max_batch", ctypes.c_int32), ("max_inflight", ctypes.c_int32),
+                ("k_max", ctypes.c_int32), ("nprobe_max", ctypes.c_int32), ("search", SearchOpts)]
+
+
+class ServeStats(ctypes.Structure):
+    _fields_ = [("wall_s", ctypes.c_double), ("served_requests", ctypes.c_int64),
+                ("rejected_requests", ctypes.c_int64), ("served_queries", ctypes.c_int64),
+                ("launches", ctypes.c_int64), ("ring_slots", ctypes.c_int64), ("peak_slots", ctypes.c_int64),
+                ("waited_requests", ctypes.c_int64), ("workspace_bytes", ctypes.c_int64),
+                ("stage_s", ctypes.c_double), ("launch_s", ctypes.c_double), ("retire_s", ctypes.c_double)]
 
 
 class Times(ctypes.Structure):
@@ -79,6 +92,8 @@ def lib():
         L.dade_export.argtypes = [vp, ctypes.POINTER(Artifacts)]
         L.dade_import.argtypes = [ctypes.POINTER(Artifacts), vp, ctypes.POINTER(BuildOpts), vp, pp]
         L.dade_stage_times.argtypes = [vp, ctypes.POINTER(Times)]
+        L.dade_serve.argtypes = [vp, i64, vp, vp, vp, vp, vp, ctypes.POINTER(ServeOpts), vp, vp, vp,
+                                 ctypes.POINTER(ServeStats), vp]
         L.dade_destroy.argtypes = [vp]
         L.dade_destroy.restype = None
         L.dade_last_error.restype = ctypes.c_char_p
@@ -189,6 +204,46 @@ def dade_search(ix: Index, Q, k, nprobe, k_per_query=None, nprobe_per_query=None
                              _dev(out_ids, torch.int64, "out_ids"),
                              _dev(out_dist2, torch.float32, "out_dist2"), _stream(stream)))
     return out_ids, out_dist2
+
+
+def _search_opts(delta_d=0, mode="dade", schedule="per_rank", rerank_delta=-1.0, fill_min=32, growth=16):
+    o = SearchOpts()
+    o.delta_d, o.mode, o.schedule = delta_d, MODES[mode], SCHEDULES[schedule]
+    o.rerank_delta = rerank_delta
+    o.fill_min, o.growth = fill_min, growth
+    return o
+
+
+def dade_serve(ix: Index, arrival_s, req_queries, req_k, req_nprobe, Q, k_max, nprobe_max, budget_bytes=0,
+               max_batch=0, max_inflight=0, stream=None, **search_kw):
+    """Runs the serving loop over host request arrays and queries Q [sum(req_queries), dim] float32
+    (a numpy array or a CPU torch tensor; pinned memory, e.g. ``torch.Tensor.pin_memory()``, is
+    copied from directly); returns (ids [nq, k_max] int64, dist2 [nq, k_max] float32,
+    latency_s [n_req], stats)."""
+    if hasattr(Q, "is_pinned"):   # a CPU torch tensor: its memory as is
+        if Q.is_cuda:
+            raise TypeError("Q must be host memory")
+        Q = Q.contiguous().numpy()
+    arr = np.ascontiguousarray(arrival_s, dtype=np.float64)
+    nq = np.ascontiguousarray(req_queries, dtype=np.int32)
+    ks = np.ascontiguousarray(req_k, dtype=np.int32)
+    nps = np.ascontiguousarray(req_nprobe, dtype=np.int32)
+    Qh = np.ascontiguousarray(Q, dtype=np.float32)
+    n_req, total = len(arr), int(nq.sum()) if len(nq) else 0
+    if not (len(nq) == len(ks) == len(nps) == n_req) or Qh.ndim != 2 or Qh.shape[0] != total:
+        raise ValueError("request arrays must have one entry per request and Q one row per query")
+    ids = np.empty((total, k_max), np.int64)
+    d2 = np.empty((total, k_max), np.float32)
+    lat = np.empty(n_req, np.float64)
+    o = ServeOpts()
+    o.budget_bytes, o.max_batch, o.max_inflight = budget_bytes, max_batch, max_inflight
+    o.k_max, o.nprobe_max = k_max, nprobe_max
+    o.search = _search_opts(**search_kw)
+    st = ServeStats()
+    ptr = lambda a: ctypes.c_void_p(a.ctypes.data)  # noqa: E731
+    _check(lib().dade_serve(ix.handle, n_req, ptr(arr), ptr(nq), ptr(ks), ptr(nps), ptr(Qh), ctypes.byref(o),
+                            ptr(ids), ptr(d2), ptr(lat), ctypes.byref(st), _stream(stream)))
+    return ids, d2, lat, {name: getattr(st, name) for name, _ in ServeStats._fields_}
 
 
 def dade_check(ix: Index, stream=None):

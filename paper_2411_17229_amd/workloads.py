@@ -139,10 +139,11 @@ def uneven_batch(n_queries: int, nprobe_lo=8, nprobe_hi=128, ks=(1, 10, 50, 100)
     return k, nprobe
 
 
-def requests(n_requests: int, rate_qps: float, ks=(10, 100), nprobes=(32, 96), seed: int = 0):
-    """Poisson arrivals; each request holds floor(exp(U[0, ln 257))) clipped to [1, 256] queries."""
+def requests(n_requests: int, rate_rps: float, ks=(10, 100), nprobes=(32, 96), seed: int = 0):
+    """Poisson arrivals at `rate_rps` requests per second (arrival times in seconds); each request
+    holds floor(exp(U[0, ln 257))) clipped to [1, 256] queries and draws its K and nprobe."""
     rng = _streams(seed)["arrivals"]
-    gaps = rng.exponential(1.0 / rate_qps, n_requests)
+    gaps = rng.exponential(1.0 / rate_rps, n_requests)
     sizes = np.clip(np.floor(np.exp(rng.uniform(0.0, math.log(257.0), n_requests))), 1, 256).astype(np.int64)
     k = np.asarray(ks)[rng.integers(0, len(ks), n_requests)]
     nprobe = np.asarray(nprobes)[rng.integers(0, len(nprobes), n_requests)]

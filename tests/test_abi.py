@@ -46,3 +46,15 @@ def test_product_code_never_touches_the_oracle():
                 assert not re.search(r"^\s*(from|import)\s+oracle\b", src, re.M), f
                 assert "oracle" not in src.lower() or f.endswith(".py") and "oracle" not in \
                     re.sub(r'""".*?"""|#.*', "", src, flags=re.S).lower(), f
+
+
+def test_serve_rejects_missing_arguments_before_touching_a_device():
+    """dade_serve validates its handle and options before any HIP call (safe without a GPU)."""
+    from paper_2411_17229_amd import dade
+    if not os.path.exists(dade.LIB_PATH):
+        pytest.skip("libdade.so not built")
+    L = dade.lib()
+    args = [None] * 13
+    args[1] = 0
+    assert L.dade_serve(*args) == dade.DADE_EINVAL
+    assert "index is NULL" in dade.dade_last_error()
