@@ -364,7 +364,7 @@ def main():
                     help="build, then only run the serving-loop sweep with the workload's request mix "
                          "(K in {10, 100}, nprobe in {32, 96}) at --p-s")
     ap.add_argument("--serve-budget-mib", type=int, default=None,
-                    help="device budget of the serving loop (default 512 MiB; 1 GiB with --serving-only)")
+                    help="device budget of the serving loop (default 512 MiB; 4 GiB with --serving-only)")
     ap.add_argument("--profile-only", action="store_true",
                     help="build, then only run timed DADE steps at --nprobe / --p-s (for profilers)")
     ap.add_argument("--nprobe", type=int, default=None)
@@ -428,12 +428,24 @@ def main():
     log(f"[bench] FP64 ground truth in {time.perf_counter() - t0:.1f}s")
 
     if args.serving_only:
-        mib = args.serve_budget_mib or 1024
+        # P_s: the largest of the sweep whose recall@10 at the mix's smaller nprobe reaches the target
+        # (unless --p-s fixes it)
+        pairs = workloads.calibration_pairs(w.n, 100_000, w.seed)
+        chosen_ps, rec_by_ps = args.p_s, {}
+        for ps in ([args.p_s] if args.p_s else PS_SWEEP):
+            dade.dade_calibrate(ix, ps, pairs=pairs)
+            ids, _ = dade.dade_search(ix, Qd, w.k, 32, delta_d=w.delta_d, **SCHEDULE)
+            rec_by_ps[str(ps)] = round(recall_at(ids.cpu().numpy(), gt, w.k), 4)
+            log(f"[bench] serving workload: P_s {ps} recall@10 at nprobe 32: {rec_by_ps[str(ps)]}")
+            chosen_ps = ps
+            if rec_by_ps[str(ps)] >= args.target:
+                break
+        mib = args.serve_budget_mib or 4096
         sv = serving_sweep(dade, ix, Q, gt, w.k, (10, 100), (32, 96), budget=mib << 20, seed=w.seed,
                            delta_d=w.delta_d, **SCHEDULE)
         print(json.dumps({"workload": w.name, "n": w.n, "dim": w.dim, "nlist": w.nlist, "store": store,
-                          "p_s": args.p_s or w.alpha, "delta_d": w.delta_d, "schedule": SCHEDULE, "serving": sv}),
-              flush=True)
+                          "p_s": chosen_ps, "recall@10_nprobe32_by_p_s": rec_by_ps, "delta_d": w.delta_d,
+                          "schedule": SCHEDULE, "serving": sv}), flush=True)
         return
 
     pairs = workloads.calibration_pairs(w.n, 100_000, w.seed)
