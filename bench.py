@@ -360,6 +360,7 @@ def main():
                     help="skip the data-aware vs data-oblivious transform comparison")
     ap.add_argument("--no-linear", action="store_true", help="skip the linear-scan (one list) study")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving-loop sweep")
+    ap.add_argument("--no-tune", action="store_true", help="skip the autotuner run")
     ap.add_argument("--serving-only", action="store_true",
                     help="build, then only run the serving-loop sweep with the workload's request mix "
                          "(K in {10, 100}, nprobe in {32, 96}) at --p-s")
@@ -557,6 +558,20 @@ def main():
         mib = args.serve_budget_mib or 512
         out["serving"] = serving_sweep(dade, ix, Q, gt, w.k, (w.k,), (d["nprobe"],), budget=mib << 20, seed=w.seed,
                                        delta_d=w.delta_d, **SCHEDULE)
+    if not args.no_tune:
+        # the autotuner at the operating point: agreement with FULL_D at this nprobe (whose recall is
+        # 1.0 here) bounded by the recall target
+        chosen, table = dade.dade_autotune(ix, Qd, w.k, d["nprobe"], min_agreement=args.target, reps=5)
+        ms = throughput(dade, torch, ix, Qd, w.k, d["nprobe"], max(3, args.steps // 4), 1, **chosen)
+        ids_t, _ = dade.dade_search(ix, Qd, w.k, d["nprobe"], **chosen)
+        torch.cuda.synchronize()
+        out["autotune"] = {"min_agreement_with_full_d": args.target, "chosen": chosen,
+                           "qps": round(nq / (ms / 1e3), 1), "recall@10": round(recall_at(ids_t.cpu().numpy(), gt,
+                                                                                          w.k), 4),
+                           "table": [{k_: (round(v, 4) if isinstance(v, float) else v) for k_, v in t.items()}
+                                     for t in table]}
+        log(f"[bench] autotune: {chosen} -> {out['autotune']['qps']:.0f} QPS, recall "
+            f"{out['autotune']['recall@10']:.4f}")
     if not args.no_variants and store != "f32":
         # the same lists and transform with the other 16-bit store and with FP32 (recall vs FP32)
         art = dade.dade_export(ix)

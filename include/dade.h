@@ -94,6 +94,9 @@ typedef struct {
   int32_t use_graph;          /* nonzero: the list scan's kernel sequence is captured once into
                                  a HIP graph and replayed while the arguments (pointers, sizes,
                                  options) stay the same; results are identical either way */
+  int32_t scan_blocks_per_cu; /* launch shape of the DCO kernel: workgroups per compute unit of
+                                 its persistent grid; 0 (or more than fit) means as many as are
+                                 resident at once; results are identical for every value */
 } dade_search_opts;
 
 /* Host copies of an index's artifacts (for checkpoints and for parity checks).  All arrays
@@ -161,7 +164,8 @@ int dade_calibrate(dade_index* ix, double alpha, const int64_t* pairs, int64_t n
  * ascending by (squared distance, id), padded with (-1, +inf) after the query's K results.
  * Requires state CALIBRATED for DADE mode and >= ROTATED for FULL_D; 1 <= k <= 128;
  * nprobe >= 1; nq >= 0 (nq == 0 is a no-op).  opts may be NULL: delta_d 32, DADE mode,
- * PER_RANK, the calibrated rerank_delta, no stats or timing, fill_min 32, growth 16, graph.
+ * PER_RANK, the calibrated rerank_delta, no stats or timing, fill_min 32, growth 16, graph, a
+ * full grid.
  * Asynchronous on `stream`.
  */
 int dade_search(dade_index* ix, const float* Q, int64_t nq, int32_t k, int32_t nprobe,
@@ -275,6 +279,45 @@ int dade_serve(dade_index* ix, int64_t n_req, const double* arrival_s, const int
                const int32_t* req_k, const int32_t* req_nprobe, const float* Q,
                const dade_serve_opts* opts, int64_t* out_ids, float* out_dist2,
                double* out_latency_s, dade_serve_stats* stats, void* stream);
+
+/*
+ * Autotuner.  The hypothesis tests run at multiples of Delta_d (Algorithm 1); the paper leaves
+ * Delta_d as a parameter and reports that its best value depends on the workload (Experiments:
+ * the Delta_d study).  dade_autotune picks Delta_d, the round shape and the DCO kernel's launch
+ * shape for a given index and query sample by measurement:
+ *   1. a FULL_D search of the sample with the same K / nprobe is the reference (its top-K is the
+ *      exact top-K of the probed candidates, whatever the round shape);
+ *   2. every candidate (Delta_d in {8, 16, 32, 64, 128} within [1, dim], times the round shapes
+ *      {doubling, fill_min 32, growth 0}, {doubling, 32, 16}, {per-rank, 32, 16}) is searched
+ *      once, its agreement measured (mean over queries of |top-K ids in the reference| / the
+ *      reference's valid ids), then timed over `reps` searches with HIP events on `stream`;
+ *   3. the fastest candidate with agreement >= min_agreement wins (none: the most agreeing);
+ *   4. the winner is timed at scan_blocks_per_cu 1, 2 and 0 (full) and the fastest kept (the
+ *      launch shape does not change results).
+ * Delta_d and the round shape change which candidates are rejected, so they are part of the
+ * result's definition: record them with the results (the oracle takes the same values).
+ * Q, k_per_query, nprobe_per_query: as dade_search (device).  opts: in, the base options (mode
+ * must be DADE; rerank_delta and use_graph are kept); out, the chosen options.  results (host,
+ * nullable): one entry per configuration tried, at most DADE_TUNE_MAX; *n_results (nullable) their
+ * count.  Requires a CALIBRATED index, nq >= 1, reps >= 1 (0 means 5), 0 <= min_agreement <= 1.
+ * Temporary device buffers (two [nq x k] result sets) count against the index's HBM budget.
+ * Synchronises `stream`.
+ */
+#define DADE_TUNE_MAX 24
+typedef struct {
+  int32_t delta_d;
+  int32_t schedule;
+  int32_t fill_min;
+  int32_t growth;
+  int32_t scan_blocks_per_cu;
+  float ms;                 /* mean duration of one search of the sample */
+  float agreement;          /* with the FULL_D reference, in [0, 1] */
+} dade_tune_result;
+
+int dade_autotune(dade_index* ix, const float* Q, int64_t nq, int32_t k, int32_t nprobe,
+                  const int32_t* k_per_query, const int32_t* nprobe_per_query, float min_agreement,
+                  int32_t reps, dade_search_opts* opts, dade_tune_result* results, int32_t* n_results,
+                  void* stream);
 
 /* dade_destroy -- free the index and all its device memory (NULL is a no-op). */
 void dade_destroy(dade_index* ix);

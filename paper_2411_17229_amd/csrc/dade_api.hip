@@ -781,8 +781,10 @@ int dade_search(dade_index* ix, const float* Q, int64_t nq, int32_t k, int32_t n
   const int npm = pl.npm, rounds = pl.rounds;
   const int64_t kb_cap = pl.kb_cap, items_pq = pl.items_pq, chunk = pl.chunk;
   if (!ix->cap) HIPC(hipStreamCreateWithFlags(&ix->cap, hipStreamNonBlocking));
+  if (o.scan_blocks_per_cu < 0) FAIL(DADE_EINVAL, "scan_blocks_per_cu must be >= 0");
   int& occ = ix->scan_occ[ix->store][o.mode][dd % 8 != 0];
   if (occ == 0) occ = round_blocks_per_cu(ix->store, o.mode, dd);
+  const int blocks_per_cu = o.scan_blocks_per_cu > 0 ? std::min(o.scan_blocks_per_cu, occ) : occ;
   if (o.record_times && !ix->ev_made) {
     for (auto& e : ix->ev) HIPC(hipEventCreate(&e));
     ix->ev_made = true;
@@ -822,7 +824,7 @@ int dade_search(dade_index* ix, const float* Q, int64_t nq, int32_t k, int32_t n
   ra.rerank_delta = o.rerank_delta >= 0.f ? o.rerank_delta : float(ix->delta);
   ra.kb_cap = kb_cap;
   ra.rounds = rounds;
-  ra.grid = ix->cus * occ;
+  ra.grid = ix->cus * blocks_per_cu;
   for (int64_t c0 = 0; c0 < nq; c0 += chunk) {
     const int64_t cn = std::min(chunk, nq - c0);
     RoundArgs a;

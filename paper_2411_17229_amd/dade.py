@@ -22,7 +22,9 @@ MODES = {"dade": 0, "full_d": 1}
 SCHEDULES = {"per_rank": 0, "doubling": 1}
 STATE_BUILT, STATE_ROTATED, STATE_CALIBRATED = 1, 2, 3
 EXPORTED = ("dade_build_index", "dade_rotate", "dade_calibrate", "dade_search", "dade_check", "dade_index_info",
-            "dade_export", "dade_import", "dade_stage_times", "dade_serve", "dade_destroy", "dade_last_error")
+            "dade_export", "dade_import", "dade_stage_times", "dade_serve", "dade_autotune", "dade_destroy",
+            "dade_last_error")
+TUNE_MAX = 24
 
 
 class DadeError(RuntimeError):
@@ -41,7 +43,7 @@ class SearchOpts(ctypes.Structure):
     _fields_ = [("delta_d", ctypes.c_int32), ("mode", ctypes.c_int32), ("schedule", ctypes.c_int32),
                 ("rerank_delta", ctypes.c_float), ("stats", ctypes.c_void_p),
                 ("record_times", ctypes.c_int32), ("fill_min", ctypes.c_int32), ("growth", ctypes.c_int32),
-                ("use_graph", ctypes.c_int32)]
+                ("use_graph", ctypes.c_int32), ("scan_blocks_per_cu", ctypes.c_int32)]
 
 
 class ServeOpts(ctypes.Structure):
@@ -55,6 +57,12 @@ class ServeStats(ctypes.Structure):
                 ("launches", ctypes.c_int64), ("ring_slots", ctypes.c_int64), ("peak_slots", ctypes.c_int64),
                 ("waited_requests", ctypes.c_int64), ("workspace_bytes", ctypes.c_int64),
                 ("stage_s", ctypes.c_double), ("launch_s", ctypes.c_double), ("retire_s", ctypes.c_double)]
+
+
+class TuneResult(ctypes.Structure):
+    _fields_ = [("delta_d", ctypes.c_int32), ("schedule", ctypes.c_int32), ("fill_min", ctypes.c_int32),
+                ("growth", ctypes.c_int32), ("scan_blocks_per_cu", ctypes.c_int32), ("ms", ctypes.c_float),
+                ("agreement", ctypes.c_float)]
 
 
 class Times(ctypes.Structure):
@@ -94,6 +102,8 @@ def lib():
         L.dade_stage_times.argtypes = [vp, ctypes.POINTER(Times)]
         L.dade_serve.argtypes = [vp, i64, vp, vp, vp, vp, vp, ctypes.POINTER(ServeOpts), vp, vp, vp,
                                  ctypes.POINTER(ServeStats), vp]
+        L.dade_autotune.argtypes = [vp, vp, i64, i32, i32, vp, vp, ctypes.c_float, i32, ctypes.POINTER(SearchOpts),
+                                    ctypes.POINTER(TuneResult), ctypes.POINTER(i32), vp]
         L.dade_destroy.argtypes = [vp]
         L.dade_destroy.restype = None
         L.dade_last_error.restype = ctypes.c_char_p
@@ -183,7 +193,8 @@ def dade_calibrate(ix: Index, alpha=0.1, pairs=None, n_pairs=100_000, seed=0, st
 
 def dade_search(ix: Index, Q, k, nprobe, k_per_query=None, nprobe_per_query=None, delta_d=0,
                 mode="dade", schedule="per_rank", rerank_delta=-1.0, stats=None, record_times=False,
-                out_ids=None, out_dist2=None, stream=None, fill_min=32, growth=16, use_graph=True):
+                out_ids=None, out_dist2=None, stream=None, fill_min=32, growth=16, use_graph=True,
+                scan_blocks_per_cu=0):
     """Returns (ids [nq, k] int64, dist2 [nq, k] float32) device tensors (asynchronous)."""
     import torch
     qp = _dev(Q, torch.float32, "Q")
@@ -198,6 +209,7 @@ def dade_search(ix: Index, Q, k, nprobe, k_per_query=None, nprobe_per_query=None
     o.stats = None if stats is None else _dev(stats, torch.int64, "stats").value
     o.record_times = int(bool(record_times))
     o.fill_min, o.growth, o.use_graph = fill_min, growth, int(bool(use_graph))
+    o.scan_blocks_per_cu = scan_blocks_per_cu
     kp = None if k_per_query is None else _dev(k_per_query, torch.int32, "k_per_query")
     npp = None if nprobe_per_query is None else _dev(nprobe_per_query, torch.int32, "nprobe_per_query")
     _check(lib().dade_search(ix.handle, qp, nq, k, nprobe, kp, npp, ctypes.byref(o),
@@ -206,11 +218,13 @@ def dade_search(ix: Index, Q, k, nprobe, k_per_query=None, nprobe_per_query=None
     return out_ids, out_dist2
 
 
-def _search_opts(delta_d=0, mode="dade", schedule="per_rank", rerank_delta=-1.0, fill_min=32, growth=16):
+def _search_opts(delta_d=0, mode="dade", schedule="per_rank", rerank_delta=-1.0, fill_min=32, growth=16,
+                 use_graph=True, scan_blocks_per_cu=0):
     o = SearchOpts()
     o.delta_d, o.mode, o.schedule = delta_d, MODES[mode], SCHEDULES[schedule]
     o.rerank_delta = rerank_delta
     o.fill_min, o.growth = fill_min, growth
+    o.use_graph, o.scan_blocks_per_cu = int(bool(use_graph)), scan_blocks_per_cu
     return o
 
 
@@ -244,6 +258,27 @@ def dade_serve(ix: Index, arrival_s, req_queries, req_k, req_nprobe, Q, k_max, n
     _check(lib().dade_serve(ix.handle, n_req, ptr(arr), ptr(nq), ptr(ks), ptr(nps), ptr(Qh), ctypes.byref(o),
                             ptr(ids), ptr(d2), ptr(lat), ctypes.byref(st), _stream(stream)))
     return ids, d2, lat, {name: getattr(st, name) for name, _ in ServeStats._fields_}
+
+
+def dade_autotune(ix: Index, Q, k, nprobe, k_per_query=None, nprobe_per_query=None, min_agreement=0.0, reps=5,
+                  stream=None, **search_kw):
+    """Returns (chosen, table): `chosen` holds dade_search keyword arguments (delta_d, schedule,
+    fill_min, growth, scan_blocks_per_cu) of the configuration picked; `table` one dict per
+    configuration timed (its options, ms per search of Q and agreement with FULL_D)."""
+    import torch
+    o = _search_opts(**search_kw)
+    kp = None if k_per_query is None else _dev(k_per_query, torch.int32, "k_per_query")
+    npp = None if nprobe_per_query is None else _dev(nprobe_per_query, torch.int32, "nprobe_per_query")
+    res = (TuneResult * TUNE_MAX)()
+    n = ctypes.c_int32()
+    _check(lib().dade_autotune(ix.handle, _dev(Q, torch.float32, "Q"), Q.shape[0], k, nprobe, kp, npp,
+                               float(min_agreement), reps, ctypes.byref(o), res, ctypes.byref(n), _stream(stream)))
+    names = {v: k_ for k_, v in SCHEDULES.items()}
+    chosen = dict(delta_d=o.delta_d, schedule=names[o.schedule], fill_min=o.fill_min, growth=o.growth,
+                  scan_blocks_per_cu=o.scan_blocks_per_cu)
+    table = [dict(delta_d=r.delta_d, schedule=names[r.schedule], fill_min=r.fill_min, growth=r.growth,
+                  scan_blocks_per_cu=r.scan_blocks_per_cu, ms=r.ms, agreement=r.agreement) for r in res[: n.value]]
+    return chosen, table
 
 
 def dade_check(ix: Index, stream=None):

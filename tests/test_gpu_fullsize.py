@@ -36,7 +36,7 @@ def oracle_from_library(gi, X, store):
 
 
 def run_workload(name, p_s, nprobe, n_sample, k_per_query=None, nprobe_per_query=None, k=None, keep=False,
-                 n_queries=None):
+                 n_queries=None, tune=None):
     import torch
     _need_gpu()
     w = workloads.WORKLOADS[name]
@@ -50,6 +50,12 @@ def run_workload(name, p_s, nprobe, n_sample, k_per_query=None, nprobe_per_query
     kw = dict(delta_d=w.delta_d, **SCHEDULE)
     kp = None if k_per_query is None else torch.from_numpy(k_per_query).to(dev)
     npp = None if nprobe_per_query is None else torch.from_numpy(nprobe_per_query).to(dev)
+    if tune is not None:   # Delta_d, round and launch shape from the autotuner on the first `tune` queries
+        kw, table = dade.dade_autotune(gi, Qd[:tune].contiguous(), K, nprobe,
+                                       k_per_query=None if kp is None else kp[:tune].contiguous(),
+                                       nprobe_per_query=None if npp is None else npp[:tune].contiguous(),
+                                       min_agreement=0.95, reps=2)
+        assert len(table) >= 15 and any(t["agreement"] >= 0.95 for t in table), table
     stats = torch.zeros((len(Q), 4), dtype=torch.int64, device=dev)
     ids, d2 = dade.dade_search(gi, Qd, K, nprobe, k_per_query=kp, nprobe_per_query=npp, stats=stats, **kw)
     # the graph-replayed launch (as timed) gives the same rows
@@ -72,7 +78,8 @@ def run_workload(name, p_s, nprobe, n_sample, k_per_query=None, nprobe_per_query
     sample = np.sort(np.random.default_rng(7).choice(len(Q), n_sample, replace=False))
     Ko = Ks[sample]
     npo = nprobe if nprobe_per_query is None else nprobe_per_query[sample]
-    o_ids, _, logs = ivf.search(oi, Q[sample], Ko, npo, w.delta_d, log=True, **SCHEDULE)
+    o_ids, _, logs = ivf.search(oi, Q[sample], Ko, npo, kw["delta_d"], log=True, schedule=kw["schedule"],
+                                fill_min=kw["fill_min"], growth=kw["growth"])
     excused = 0
     same_probes = logs["probe_gap"] > MARGIN_TOL   # no near tie in the probe order
     for j, qi in enumerate(sample):
@@ -107,10 +114,12 @@ def test_fullsize_scale_f32():
 
 def test_fullsize_uneven_batch():
     """2M x 256, BF16 store, 4096 queries with per-query K in {1, 10, 50, 100} and nprobe in
-    8..128 (seeded), nlist 4096."""
+    8..128 (seeded), nlist 4096; Delta_d, the round shape and the launch shape from the
+    autotuner (on the first 512 queries), the oracle run with the chosen values."""
     w = workloads.WORKLOADS["uneven-2m-d256"]
     K, npb = workloads.uneven_batch(w.n_queries, 8, 128, (1, 10, 50, 100), seed=w.seed)
-    run_workload("uneven-2m-d256", p_s=0.1, nprobe=128, n_sample=6, k_per_query=K, nprobe_per_query=npb, k=100)
+    run_workload("uneven-2m-d256", p_s=0.1, nprobe=128, n_sample=6, k_per_query=K, nprobe_per_query=npb, k=100,
+                 tune=512)
 
 
 def test_fullsize_serving_mix():
