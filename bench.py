@@ -153,6 +153,15 @@ def cpu_baseline(w, X, Q, nprobe, p_s, seconds=20.0):
                      f"K {w.k}, over an oracle-built index of a {n_s}-row subsample with nlist {nl_s} "
                      f"(same list size and D as the workload); one thread; index build {build_s:.1f} s "
                      f"not timed"}
+    # the oracle's exact mode (FDScanning) on the same index, one thread, half the time
+    with threadpool_limits(limits=1):
+        done_f, t0 = 0, time.perf_counter()
+        while done_f < len(Q) and time.perf_counter() - t0 < seconds / 2:
+            ivf.search(oi, Q[done_f:done_f + 1], w.k, nprobe, w.delta_d, mode="full_d", **SCHEDULE)
+            done_f += 1
+        el_f = time.perf_counter() - t0
+    out["full_d"] = {"value": done_f / el_f, "unit": "queries/s", "cores": 1, "kind": "oracle",
+                     "sample": f"{done_f} queries, FULL_D mode, same index, nprobe and K; one thread"}
     # the same search on every host core this job may use: a child process (this one holds the
     # GPU) builds the same index and forks one single-threaded worker per core over query shards
     import subprocess
