@@ -1,0 +1,117 @@
+"""Graph search with DADE distance comparisons, in float64 (test infrastructure only).
+
+The paper's graph setting (HNSW** in the Experiments section) scans the neighbours of visited
+objects, giving each one DCO against the maximum distance of the result set (size ef), and
+discards a neighbour whose DCO answers no.  This oracle follows that search on a flat graph:
+
+* Graph (reading; the paper uses HNSW's hierarchy, this build uses one layer): every object's
+  out-neighbours are its ``degree`` nearest other objects by the index's exact IVF search
+  (FDScanning with K = degree + 1 over ``nprobe`` lists), ordered by (dist^2, id), the object
+  itself removed, -1 padded.
+* Entry points (reading): each IVF list's medoid, the member nearest its centroid (ties to the
+  lower id); a query starts from the medoids of its ``n_entry`` nearest lists (probe order).
+* Beam: a pool of at most ``ef`` (dist^2, id) entries, each marked expanded or not.  Seeds enter
+  with their full-D distance.  Each step expands the first unexpanded entry of the pool in
+  (dist^2, id) order: its unvisited neighbours are marked visited and each gets one DCO (Algorithm
+  1 at the given Delta_d, or FDScanning) against the pool's snapshot at the step's start
+  (r^2 = the ef-th distance, +inf while the pool holds fewer than ef), with the keep rule of the
+  IVF oracle; the kept ones are merged in (the ef smallest stay).  The search stops when every
+  pool entry is expanded or after ``max_iters`` expansions.
+* Low-precision stores: DCOs and the pool use the stored coordinates; at the end every pool
+  entry is reranked with the exact coordinates and the K smallest by (exact dist^2, id) are
+  returned.  With an FP32 store the final distances are the stored ones recomputed exactly.
+"""
+from __future__ import annotations
+
+import dataclasses
+
+import numpy as np
+
+from . import ivf, pca
+
+
+def build_knn_graph(index: ivf.Index, X, degree: int, nprobe: int, delta_d: int = 32):
+    """[n x degree] int64 out-neighbours (row ids, -1 padded) from the index's FDScanning search."""
+    X = np.asarray(X)
+    ids = ivf.search(index, X, degree + 1, nprobe, delta_d, mode="full_d", schedule="doubling")[0]
+    out = np.full((len(X), degree), -1, dtype=np.int64)
+    for i in range(len(X)):
+        row = [int(v) for v in ids[i] if v >= 0 and v != i][:degree]
+        out[i, :len(row)] = row
+    return out
+
+
+def list_medoids(index: ivf.Index, X) -> np.ndarray:
+    """[nlist] row id of each list's member nearest its centroid (ties: lower id), -1 if empty."""
+    X = np.asarray(X, dtype=np.float64)
+    out = np.full(index.nlist, -1, dtype=np.int64)
+    for l in range(index.nlist):
+        members = index.ids[index.offsets[l]:index.offsets[l + 1]]
+        if len(members) == 0:
+            continue
+        d2 = np.sum((X[members] - index.centroids[l]) ** 2, axis=1)
+        out[l] = members[np.lexsort((members, d2))[0]]
+    return out
+
+
+def search(index: ivf.Index, neighbors, entries, Q, K: int, ef: int, n_entry: int, delta_d: int,
+           mode: str = "dade", max_iters: int = 0, log: bool = False):
+    """Beam search per query.  Returns (ids [nq, K] int64 -1 padded, dist2 [nq, K] +inf padded,
+    logs) with logs per query: dcos, dims (sum of exit d), expansions, visited (count and, in
+    visited_ids, the ids), min_margin (the smallest relative margin of any test, keep compare or
+    merge boundary)."""
+    Q = np.asarray(Q)
+    nq = len(Q)
+    max_iters = max_iters or 2 * ef
+    beam = dataclasses.replace(index, Y_exact=None)   # DCOs and the pool on the stored coordinates
+    exact_rows = index.Y_exact if index.Y_exact is not None else index.Y
+    Qr = pca.rotate(Q, index.mu, index.W)
+    cent = index.cent_rot()
+    D = index.dim
+    tests = ivf.tested_dims(D, delta_d)
+    out_i = np.full((nq, K), -1, dtype=np.int64)
+    out_d = np.full((nq, K), np.inf)
+    logs = {k: np.zeros(nq) for k in ("dcos", "dims", "expansions", "visited")}
+    logs["min_margin"] = np.full(nq, np.inf)
+    logs["visited_ids"] = []
+    for qi in range(nq):
+        q = Qr[qi]
+        lists, _ = ivf.probe_order(q, cent, min(n_entry, index.nlist))
+        seeds = np.array([entries[l] for l in lists if entries[l] >= 0], dtype=np.int64)
+        visited = set(seeds.tolist())
+        diff = index.Y[seeds] - q
+        sd = np.sum(diff * diff, axis=1)
+        hd, hi, gap = ivf._merge(np.zeros(0), np.zeros(0, dtype=np.int64), sd, seeds, ef)
+        margin = gap
+        expanded = set()
+        it = 0
+        while it < max_iters:
+            todo = [j for j in range(len(hi)) if int(hi[j]) not in expanded]
+            if not todo:
+                break
+            c = int(hi[todo[0]])
+            expanded.add(c)
+            it += 1
+            cand = np.array([u for u in neighbors[c] if u >= 0 and int(u) not in visited], dtype=np.int64)
+            if len(cand) == 0:
+                continue
+            visited.update(cand.tolist())
+            d2, ids, exit_d, m, _ = ivf._scan_round(beam, q, cand, hd, hi, ef, delta_d, mode, tests)
+            logs["dcos"][qi] += len(cand)
+            logs["dims"][qi] += exit_d.sum()
+            hd, hi, gap = ivf._merge(hd, hi, d2, ids, ef)
+            margin = min(margin, m, gap)
+        logs["expansions"][qi] = it
+        logs["visited"][qi] = len(visited)
+        logs["visited_ids"].append(np.array(sorted(visited), dtype=np.int64))
+        # final pool: exact distances, the K smallest by (dist^2, id)
+        de = exact_rows[hi] - q
+        ex = np.sum(de * de, axis=1)
+        o = np.lexsort((hi, ex))
+        if len(o) > K and ex[o[K - 1]] > 0:
+            margin = min(margin, abs(ex[o[K]] - ex[o[K - 1]]) / ex[o[K - 1]])
+        o = o[:K]
+        out_i[qi, :len(o)] = hi[o]
+        out_d[qi, :len(o)] = ex[o]
+        logs["min_margin"][qi] = margin
+    return out_i, out_d, (logs if log else None)

@@ -1,0 +1,113 @@
+"""Pins of the graph-search oracle (oracle/graph.py) against what the definitions fix: the kNN
+graph against brute force (oracle/knn.py, a separate implementation), the medoid's minimality,
+a beam that sees every object returning the exact KNN, the FDScanning beam returning the exact
+top-K of what it visited, and DADE with tests that never reject reducing to FDScanning."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+from oracle import graph, ivf, knn, lowp
+
+pytestmark = pytest.mark.filterwarnings("ignore::RuntimeWarning")
+
+
+def gaussian(n, d, seed, centres=4):
+    rng = np.random.default_rng(seed)
+    C = rng.normal(0, 3, (centres, d))
+    return (C[rng.integers(0, centres, n)] + rng.normal(0, 1, (n, d)) * np.linspace(2, 0.2, d)).astype(np.float32)
+
+
+def small_index(n=400, d=16, nlist=6, seed=0, store=None):
+    X = gaussian(n, d, seed)
+    rng = np.random.default_rng(seed + 1)
+    init = rng.choice(n, nlist, replace=False)
+    pairs = np.stack([rng.integers(0, n, 4000), rng.integers(0, n, 4000)], 1)
+    pairs = pairs[pairs[:, 0] != pairs[:, 1]]
+    st = None if store is None else (lambda y: lowp.store(y, store))
+    return X, ivf.build(X, nlist, init, pairs, p_s=0.1, iters=5, store=st)
+
+
+def test_knn_graph_over_all_lists_is_brute_force():
+    X, oi = small_index()
+    G = graph.build_knn_graph(oi, X, degree=8, nprobe=oi.nlist)
+    bf, _ = knn.brute_force(X, X, 9)
+    for i in range(len(X)):
+        assert G[i].tolist() == [v for v in bf[i].tolist() if v != i][:8], i
+
+
+def test_medoids_are_members_nearest_their_centroid():
+    X, oi = small_index()
+    med = graph.list_medoids(oi, X)
+    for l in range(oi.nlist):
+        members = oi.ids[oi.offsets[l]:oi.offsets[l + 1]]
+        assert med[l] in members
+        dm = np.sum((X[med[l]].astype(np.float64) - oi.centroids[l]) ** 2)
+        for m in members:
+            assert np.sum((X[m].astype(np.float64) - oi.centroids[l]) ** 2) >= dm
+
+
+@pytest.mark.parametrize("mode", ["full_d", "dade"])
+def test_beam_over_a_complete_graph_is_exact_knn(mode):
+    """Every object is a neighbour of every seed and ef >= n: the pool ends holding every object
+    that was not rejected; in FDScanning mode that is all of them, so the result is the KNN."""
+    X, oi = small_index(n=60, nlist=3)
+    n = len(X)
+    G = np.array([[j for j in range(n) if j != i] for i in range(n)])
+    med = graph.list_medoids(oi, X)
+    Q = gaussian(12, X.shape[1], 9)
+    ids, d2, logs = graph.search(oi, G, med, Q, 10, ef=n, n_entry=oi.nlist, delta_d=4, mode=mode, log=True)
+    bf_i, bf_d = knn.brute_force(X, Q, 10)
+    if mode == "full_d":
+        np.testing.assert_array_equal(ids, bf_i)
+        np.testing.assert_allclose(d2, bf_d, rtol=1e-12)
+    assert np.all(logs["visited"] == n)
+    # returned distances are exact whatever the mode
+    for q in range(len(Q)):
+        ex = np.sum((X[ids[q]].astype(np.float64) - Q[q].astype(np.float64)) ** 2, axis=1)
+        np.testing.assert_allclose(d2[q], ex, rtol=1e-12)
+
+
+@pytest.mark.parametrize("ef", [4, 10, 24])
+def test_full_d_beam_returns_the_top_k_of_what_it_visited(ef):
+    """An object dropped at any step was farther than that step's r, which only shrinks, so the
+    FDScanning pool ends as the ef nearest of the visited set and the result as its K nearest."""
+    X, oi = small_index(seed=3)
+    G = graph.build_knn_graph(oi, X, degree=6, nprobe=2)
+    med = graph.list_medoids(oi, X)
+    Q = gaussian(20, X.shape[1], 11)
+    K = min(4, ef)
+    ids, d2, logs = graph.search(oi, G, med, Q, K, ef=ef, n_entry=2, delta_d=4, mode="full_d", log=True)
+    for q in range(len(Q)):
+        vis = logs["visited_ids"][q]
+        bi, bd = knn.brute_force(X[vis], Q[q:q + 1], K)
+        assert ids[q].tolist() == vis[bi[0]].tolist(), q
+        np.testing.assert_allclose(d2[q], bd[0], rtol=1e-12)
+
+
+def test_dade_without_rejections_is_full_d():
+    X, oi = small_index(seed=5)
+    G = graph.build_knn_graph(oi, X, degree=6, nprobe=2)
+    med = graph.list_medoids(oi, X)
+    Q = gaussian(15, X.shape[1], 13)
+    never = dataclasses.replace(oi, eps=np.full_like(oi.eps, np.inf))
+    a = graph.search(never, G, med, Q, 5, ef=12, n_entry=2, delta_d=4, mode="dade", log=True)
+    b = graph.search(oi, G, med, Q, 5, ef=12, n_entry=2, delta_d=4, mode="full_d", log=True)
+    np.testing.assert_array_equal(a[0], b[0])
+    np.testing.assert_array_equal(a[1], b[1])
+    # the calibrated tests do reject and read fewer dimensions
+    c = graph.search(oi, G, med, Q, 5, ef=12, n_entry=2, delta_d=4, mode="dade", log=True)
+    assert c[2]["dims"].sum() < b[2]["dims"].sum()
+
+
+def test_low_precision_beam_returns_exact_distances():
+    X, oi = small_index(seed=7, store="bf16")
+    G = graph.build_knn_graph(oi, X, degree=6, nprobe=2)
+    med = graph.list_medoids(oi, X)
+    Q = gaussian(10, X.shape[1], 17)
+    ids, d2, _ = graph.search(oi, G, med, Q, 5, ef=12, n_entry=2, delta_d=4, log=True)
+    for q in range(len(Q)):
+        v = ids[q] >= 0
+        ex = np.sum((X[ids[q][v]].astype(np.float64) - Q[q].astype(np.float64)) ** 2, axis=1)
+        np.testing.assert_allclose(d2[q][v], ex, rtol=1e-10)
+        assert list(d2[q][v]) == sorted(d2[q][v])
