@@ -30,13 +30,15 @@ import numpy as np
 from . import ivf, pca
 
 
-def build_knn_graph(index: ivf.Index, X, degree: int, nprobe: int, delta_d: int = 32):
-    """[n x degree] int64 out-neighbours (row ids, -1 padded) from the index's FDScanning search."""
+def build_knn_graph(index: ivf.Index, X, degree: int, nprobe: int, delta_d: int = 32, rows=None):
+    """[len(rows) x degree] int64 out-neighbours (row ids, -1 padded) of the given rows (all rows
+    by default) from the index's FDScanning search."""
     X = np.asarray(X)
-    ids = ivf.search(index, X, degree + 1, nprobe, delta_d, mode="full_d", schedule="doubling")[0]
-    out = np.full((len(X), degree), -1, dtype=np.int64)
-    for i in range(len(X)):
-        row = [int(v) for v in ids[i] if v >= 0 and v != i][:degree]
+    rows = np.arange(len(X)) if rows is None else np.asarray(rows)
+    ids = ivf.search(index, X[rows], degree + 1, nprobe, delta_d, mode="full_d", schedule="doubling")[0]
+    out = np.full((len(rows), degree), -1, dtype=np.int64)
+    for i, r in enumerate(rows):
+        row = [int(v) for v in ids[i] if v >= 0 and v != r][:degree]
         out[i, :len(row)] = row
     return out
 
@@ -59,7 +61,8 @@ def search(index: ivf.Index, neighbors, entries, Q, K: int, ef: int, n_entry: in
     """Beam search per query.  Returns (ids [nq, K] int64 -1 padded, dist2 [nq, K] +inf padded,
     logs) with logs per query: dcos, dims (sum of exit d), expansions, visited (count and, in
     visited_ids, the ids), min_margin (the smallest relative margin of any test, keep compare or
-    merge boundary)."""
+    merge boundary) and probe_gap (the smallest relative gap between consecutive centroid
+    distances up to the first list past the entry lists)."""
     Q = np.asarray(Q)
     nq = len(Q)
     max_iters = max_iters or 2 * ef
@@ -73,10 +76,17 @@ def search(index: ivf.Index, neighbors, entries, Q, K: int, ef: int, n_entry: in
     out_d = np.full((nq, K), np.inf)
     logs = {k: np.zeros(nq) for k in ("dcos", "dims", "expansions", "visited")}
     logs["min_margin"] = np.full(nq, np.inf)
+    logs["probe_gap"] = np.full(nq, np.inf)
     logs["visited_ids"] = []
     for qi in range(nq):
         q = Qr[qi]
-        lists, _ = ivf.probe_order(q, cent, min(n_entry, index.nlist))
+        ne = min(n_entry, index.nlist)
+        lists, cd = ivf.probe_order(q, cent, ne)
+        head = cd[:ne + 1]   # the entry lists and the next one: a near tie can swap an entry list
+        if len(head) > 1:
+            with np.errstate(divide="ignore", invalid="ignore"):
+                g = np.abs(np.diff(head)) / np.maximum(head[:-1], 1e-300)
+            logs["probe_gap"][qi] = float(g.min())
         seeds = np.array([entries[l] for l in lists if entries[l] >= 0], dtype=np.int64)
         visited = set(seeds.tolist())
         diff = index.Y[seeds] - q

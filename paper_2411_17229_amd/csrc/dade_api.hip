@@ -100,6 +100,10 @@ struct dade_index {
   hipGraphExec_t graph_exec = nullptr;
   const float* last_q = nullptr;   // the query buffer of the last search
   std::vector<unsigned char> graph_key;
+  // kNN graph (dade_graph_build)
+  int32_t* d_nbr = nullptr;    // [n x graph_degree] out-neighbour positions, by position
+  int32_t* d_entry = nullptr;  // [nlist] medoid position per list
+  int graph_degree = 0;
 
   std::vector<void*> owned;
 };
@@ -270,6 +274,29 @@ int upload_T(dade_index* ix, hipStream_t s) {
   return DADE_OK;
 }
 
+// Query-side workspace: padded and rotated queries, centroid distances and probe lists of nq
+// queries with npm probes (grown on demand; growing synchronises `s`).
+int grow_query_workspace(dade_index* ix, int64_t nq, int64_t npm, hipStream_t s) {
+  int rc;
+  const int dp = ix->dp, nl = ix->nlist;
+  if (nq > ix->w_nq || npm > ix->w_np) {
+    const int64_t new_nq = std::max(nq, ix->w_nq), new_np = std::max<int64_t>(npm, ix->w_np);
+    HIPC(hipStreamSynchronize(s));
+    dev_free(ix, ix->w_qpad, sizeof(float) * ix->w_nq * dp);
+    dev_free(ix, ix->w_qrot, sizeof(float) * ix->w_nq * dp);
+    dev_free(ix, ix->w_pd, sizeof(float) * ix->w_nq * nl);
+    dev_free(ix, ix->w_probes, sizeof(int32_t) * ix->w_nq * ix->w_np);
+    ix->w_qpad = ix->w_qrot = ix->w_pd = nullptr;
+    ix->w_probes = nullptr;
+    ix->w_nq = ix->w_np = 0;
+    if ((rc = alloc_t(ix, &ix->w_qpad, size_t(new_nq) * dp)) || (rc = alloc_t(ix, &ix->w_qrot, size_t(new_nq) * dp)) ||
+        (rc = alloc_t(ix, &ix->w_pd, size_t(new_nq) * nl)) || (rc = alloc_t(ix, &ix->w_probes, size_t(new_nq) * new_np)))
+      return rc;
+    ix->w_nq = new_nq; ix->w_np = new_np;
+  }
+  return DADE_OK;
+}
+
 // Sizes of one search's round workspace, from the list sizes, K, nprobe and the schedule.
 struct SearchPlan {
   int npm = 0, widest = 1, rounds = 0;
@@ -311,22 +338,7 @@ int plan_search(dade_index* ix, int64_t nq, int32_t k, int32_t nprobe, const dad
   const int64_t per_q = kb_cap * 8 + rounds * (items_pq * 16 + 4) + int64_t(k) * 8 + 48;
   const int64_t chunk =
       std::max<int64_t>(1, std::min<int64_t>({nq, (int64_t(1) << 30) / per_q, int64_t(kMaxPassQueries)}));
-  // workspace
-  if (nq > ix->w_nq || npm > ix->w_np) {
-    const int64_t new_nq = std::max(nq, ix->w_nq), new_np = std::max<int64_t>(npm, ix->w_np);
-    HIPC(hipStreamSynchronize(s));
-    dev_free(ix, ix->w_qpad, sizeof(float) * ix->w_nq * dp);
-    dev_free(ix, ix->w_qrot, sizeof(float) * ix->w_nq * dp);
-    dev_free(ix, ix->w_pd, sizeof(float) * ix->w_nq * nl);
-    dev_free(ix, ix->w_probes, sizeof(int32_t) * ix->w_nq * ix->w_np);
-    ix->w_qpad = ix->w_qrot = ix->w_pd = nullptr;
-    ix->w_probes = nullptr;
-    ix->w_nq = ix->w_np = 0;
-    if ((rc = alloc_t(ix, &ix->w_qpad, size_t(new_nq) * dp)) || (rc = alloc_t(ix, &ix->w_qrot, size_t(new_nq) * dp)) ||
-        (rc = alloc_t(ix, &ix->w_pd, size_t(new_nq) * nl)) || (rc = alloc_t(ix, &ix->w_probes, size_t(new_nq) * new_np)))
-      return rc;
-    ix->w_nq = new_nq; ix->w_np = new_np;
-  }
+  if ((rc = grow_query_workspace(ix, nq, npm, s))) return rc;
   if ((rc = grow(ix, &ix->w_topk, ix->w_topk_n, chunk * k, s)) || (rc = grow(ix, &ix->w_keyr, ix->w_keyr_n, chunk, s)) ||
       (rc = grow(ix, &ix->w_r2, ix->w_r2_n, chunk, s)) || (rc = grow(ix, &ix->w_qint, ix->w_qint_n, chunk * 3, s)) ||
       (rc = grow(ix, &ix->w_kb, ix->w_kb_n, chunk * kb_cap, s)) ||
@@ -922,6 +934,148 @@ int dade_stage_times(dade_index* ix, dade_times* out) {
     out->merge_kernel_ms += t2;
     ++out->round_launches;
   }
+  return DADE_OK;
+}
+
+int dade_graph_build(dade_index* ix, const float* X, int32_t degree, int32_t nprobe, void* stream) {
+  if (!ix) FAIL(DADE_EINVAL, "index is NULL");
+  if (degree < 1 || degree > kGraphMax) FAIL(DADE_EINVAL, "degree must be in [1, 64]");
+  if (nprobe < 1) FAIL(DADE_EINVAL, "nprobe must be >= 1");
+  if (ix->state < DADE_STATE_ROTATED) FAIL(DADE_ESTATE, "the graph needs a rotated index");
+  int rc = check_device_pointer(X, "X");
+  if (rc) return rc;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int64_t n = ix->n;
+  if (ix->d_nbr && ix->graph_degree != degree) {
+    HIPC(hipStreamSynchronize(s));
+    dev_free(ix, ix->d_nbr, sizeof(int32_t) * size_t(n) * ix->graph_degree);
+    ix->d_nbr = nullptr;
+    ix->graph_degree = 0;
+  }
+  if (!ix->d_nbr && (rc = alloc_t(ix, &ix->d_nbr, size_t(n) * degree))) return rc;
+  if (!ix->d_entry && (rc = alloc_t(ix, &ix->d_entry, size_t(ix->nlist)))) return rc;
+  ix->graph_degree = 0;   // not usable until complete
+  const int64_t chunk = std::min<int64_t>(n, 65536);
+  int64_t* res = nullptr;
+  float* rd = nullptr;
+  if ((rc = alloc_t(ix, &res, size_t(chunk) * (degree + 1)))) return rc;
+  if ((rc = alloc_t(ix, &rd, size_t(chunk) * (degree + 1)))) {
+    dev_free(ix, res, sizeof(int64_t) * size_t(chunk) * (degree + 1));
+    return rc;
+  }
+  dade_search_opts o{};
+  o.mode = DADE_MODE_FULL_D;
+  o.schedule = DADE_SCHED_DOUBLING;
+  o.rerank_delta = -1.f;
+  o.fill_min = 32;
+  o.growth = 0;
+  // every row's degree + 1 nearest by FDScanning over nprobe lists, then itself dropped
+  for (int64_t c0 = 0; c0 < n && rc == DADE_OK; c0 += chunk) {
+    const int64_t cn = std::min(chunk, n - c0);
+    rc = dade_search(ix, X + c0 * ix->dim, cn, degree + 1, nprobe, nullptr, nullptr, &o, res, rd, stream);
+    if (rc == DADE_OK) {
+      const hipError_t e = launch_graph_collect(res, int(cn), c0, degree, ix->d_pos, ix->d_nbr, s);
+      if (e != hipSuccess) { dade::set_error(hip_msg(e, "graph collect")); rc = DADE_EDEVICE; }
+    }
+  }
+  if (rc == DADE_OK) {
+    const hipError_t e = launch_graph_entry(ix->X, ix->cent, ix->d_off, ix->d_ids, ix->d_pos, ix->dp, ix->nlist,
+                                            ix->d_entry, s);
+    if (e != hipSuccess) { dade::set_error(hip_msg(e, "graph entry points")); rc = DADE_EDEVICE; }
+  }
+  const hipError_t e = hipStreamSynchronize(s);
+  dev_free(ix, res, sizeof(int64_t) * size_t(chunk) * (degree + 1));
+  dev_free(ix, rd, sizeof(float) * size_t(chunk) * (degree + 1));
+  if (rc) return rc;
+  if (e != hipSuccess) FAIL(DADE_EDEVICE, hip_msg(e, "graph build"));
+  ix->graph_degree = degree;
+  return DADE_OK;
+}
+
+int dade_graph_export(const dade_index* ix, int32_t* degree, int64_t* neighbors, int64_t* entries) {
+  if (!ix) FAIL(DADE_EINVAL, "index is NULL");
+  if (ix->graph_degree == 0) FAIL(DADE_ESTATE, "no graph has been built");
+  if (degree) *degree = ix->graph_degree;
+  const int64_t n = ix->n;
+  const int deg = ix->graph_degree;
+  if (neighbors) {
+    std::vector<int32_t> nb(size_t(n) * deg);
+    HIPC(hipMemcpy(nb.data(), ix->d_nbr, sizeof(int32_t) * nb.size(), hipMemcpyDeviceToHost));
+    for (int64_t p = 0; p < n; ++p) {
+      const int64_t row = ix->ids_h[size_t(p)];
+      for (int j = 0; j < deg; ++j) {
+        const int32_t u = nb[size_t(p) * deg + j];
+        neighbors[row * deg + j] = u < 0 ? -1 : ix->ids_h[size_t(u)];
+      }
+    }
+  }
+  if (entries) {
+    std::vector<int32_t> en(size_t(ix->nlist));
+    HIPC(hipMemcpy(en.data(), ix->d_entry, sizeof(int32_t) * en.size(), hipMemcpyDeviceToHost));
+    for (int l = 0; l < ix->nlist; ++l) entries[l] = en[size_t(l)] < 0 ? -1 : ix->ids_h[size_t(en[size_t(l)])];
+  }
+  return DADE_OK;
+}
+
+int dade_graph_search(dade_index* ix, const float* Q, int64_t nq, int32_t k, int32_t ef, int32_t n_entry,
+                      int32_t max_iters, const dade_search_opts* opts, int64_t* out_ids, float* out_dist2,
+                      void* stream) {
+  if (!ix) FAIL(DADE_EINVAL, "index is NULL");
+  if (ix->graph_degree == 0) FAIL(DADE_ESTATE, "no graph has been built");
+  if (nq < 0 || nq >= (int64_t(1) << 31)) FAIL(DADE_EINVAL, "nq must be in [0, 2^31)");
+  if (ef < 1 || ef > kGraphMax) FAIL(DADE_EINVAL, "ef must be in [1, 64]");
+  if (k < 1 || k > ef) FAIL(DADE_EINVAL, "k must be in [1, ef]");
+  if (n_entry < 1 || n_entry > kGraphMax) FAIL(DADE_EINVAL, "n_entry must be in [1, 64]");
+  if (max_iters < 0) FAIL(DADE_EINVAL, "max_iters must be >= 0");
+  dade_search_opts o{};
+  o.mode = DADE_MODE_DADE;
+  if (opts) o = *opts;
+  const int dd = o.delta_d > 0 ? o.delta_d : std::min(32, ix->dim);
+  if (o.mode != DADE_MODE_DADE && o.mode != DADE_MODE_FULL_D) FAIL(DADE_EINVAL, "bad mode");
+  if (o.mode == DADE_MODE_DADE && (dd % 8 != 0 || dd > ix->dim))
+    FAIL(DADE_EINVAL, "graph search: delta_d must be a multiple of 8 in [8, dim]");
+  if (ix->state < DADE_STATE_ROTATED) FAIL(DADE_ESTATE, "search needs a rotated index");
+  if (o.mode == DADE_MODE_DADE && ix->state < DADE_STATE_CALIBRATED) FAIL(DADE_ESTATE, "DADE mode needs a calibrated index");
+  const int deg = ix->graph_degree;
+  const int npm = std::min<int>(n_entry, ix->nlist);
+  const int iters = max_iters > 0 ? max_iters : 2 * ef;
+  // the visited table: at least twice the most insertions (seeds + iters x degree), <= 8192 slots
+  const int64_t most = int64_t(npm) + int64_t(iters) * deg;
+  int slots_log2 = 6;
+  while ((int64_t(1) << slots_log2) < 2 * most) ++slots_log2;
+  if (slots_log2 > 13)
+    FAIL(DADE_EINVAL, "graph search: n_entry + max_iters x degree must be <= 4096 (visited table of 8192 slots)");
+  if (nq == 0) return DADE_OK;
+  int rc;
+  if ((rc = check_device_pointer(Q, "Q")) || (rc = check_device_pointer(out_ids, "out_ids")) ||
+      (rc = check_device_pointer(out_dist2, "out_dist2")))
+    return rc;
+  if (o.stats && (rc = check_device_pointer(o.stats, "stats"))) return rc;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int dp = ix->dp, nl = ix->nlist;
+  if ((rc = grow_query_workspace(ix, nq, npm, s))) return rc;
+  // rotation and entry lists: the same GEMM and selection as dade_search
+  const bool q_in_place = ix->dim == dp && reinterpret_cast<uintptr_t>(Q) % 16 == 0;
+  const float* qpad = q_in_place ? Q : ix->w_qpad;
+  if (!q_in_place) HIPC(launch_pad_rows(Q, nq, ix->dim, ix->w_qpad, dp, s));
+  GemmArgs g;
+  g.M = int(nq); g.N = dp + nl; g.K = dp;
+  g.A = qpad; g.lda = dp; g.a_shift = ix->d_mu;
+  g.B = ix->d_B; g.ldb = ix->ldB; g.C = ix->w_qrot; g.ldc = dp;
+  g.split_col = dp; g.C2 = ix->w_pd; g.ldc2 = nl; g.col_norm = ix->d_cent_norm;
+  HIPC(launch_gemm(g, kEpiRotateProbe, s));
+  HIPC(launch_select_probes(ix->w_pd, nl, int(nq), nl, npm, ix->w_probes, s));
+  GraphArgs a;
+  a.nq = int(nq); a.dim = ix->dim; a.dp = dp; a.delta_d = dd;
+  a.mode = o.mode == DADE_MODE_DADE ? 0 : 1; a.dtype = ix->store;
+  a.K = k; a.ef = ef; a.n_entry = npm; a.npm = npm;
+  a.degree = deg; a.max_iters = iters; a.slots_log2 = slots_log2;
+  a.head = ix->d_store;
+  a.tail = static_cast<const char*>(ix->d_store) + size_t(ix->n) * kHead * dtype_size(ix->store);
+  a.qrot = ix->w_qrot; a.qorig = qpad; a.probes = ix->w_probes;
+  a.entry = ix->d_entry; a.nbr = ix->d_nbr; a.ids = ix->d_ids; a.X = ix->X; a.T = ix->d_T;
+  a.out_ids = out_ids; a.out_d2 = out_dist2; a.stats = o.stats;
+  HIPC(launch_graph_search(a, s));
   return DADE_OK;
 }
 

@@ -145,4 +145,33 @@ hipError_t launch_merge(const RoundArgs& a, int r, hipStream_t s);
 // Resident scan_round workgroups per CU for a store type / mode / Delta_d.
 int round_blocks_per_cu(int dtype, int mode, int delta_d);
 
+// ---------------------------------------------------------------- graph search (graph.hip)
+constexpr int kGraphMax = 64;   // largest degree, ef and n_entry (one wave holds a query's pool)
+struct GraphArgs {
+  int nq = 0, dim = 0, dp = 0, delta_d = 0;   // delta_d % 8 == 0 in DADE mode
+  int mode = 0, dtype = 0;                    // mode 0: DADE, 1: FDScanning
+  int K = 0, ef = 0, n_entry = 0, npm = 0;    // K <= ef <= 64, n_entry <= npm <= 64
+  int degree = 0, max_iters = 0, slots_log2 = 0;
+  const void* head = nullptr;       // packed store, as RoundArgs
+  const void* tail = nullptr;
+  const float* qrot = nullptr;      // [nq x dp]
+  const float* qorig = nullptr;     // [nq x dp] original queries (final rerank)
+  const int32_t* probes = nullptr;  // [nq x npm] list ids in probe order
+  const int32_t* entry = nullptr;   // [nlist] medoid position per list, -1 if empty
+  const int32_t* nbr = nullptr;     // [n x degree] out-neighbour positions, -1 padded
+  const int32_t* ids = nullptr;     // packed position -> row id
+  const float* X = nullptr;         // [n x dp] original vectors by row id
+  const float* T = nullptr;         // [dim]
+  int64_t* out_ids = nullptr;       // [nq x K]
+  float* out_d2 = nullptr;
+  int64_t* stats = nullptr;         // [nq x 4]: DCOs, dimensions read, expansions, visited
+};
+// LDS bytes of one query's workgroup: the visited table (2^slots_log2 ints) and the merge area.
+size_t graph_lds_bytes(int slots_log2);
+hipError_t launch_graph_search(const GraphArgs& a, hipStream_t s);
+hipError_t launch_graph_collect(const int64_t* res, int cn, int64_t c0, int degree, const int64_t* pos,
+                                int32_t* nbr, hipStream_t s);
+hipError_t launch_graph_entry(const float* X, const float* cent, const int64_t* off, const int32_t* ids,
+                              const int64_t* pos, int dp, int nlist, int32_t* entry, hipStream_t s);
+
 }  // namespace dade

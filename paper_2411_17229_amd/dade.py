@@ -22,8 +22,8 @@ MODES = {"dade": 0, "full_d": 1}
 SCHEDULES = {"per_rank": 0, "doubling": 1}
 STATE_BUILT, STATE_ROTATED, STATE_CALIBRATED = 1, 2, 3
 EXPORTED = ("dade_build_index", "dade_rotate", "dade_calibrate", "dade_search", "dade_check", "dade_index_info",
-            "dade_export", "dade_import", "dade_stage_times", "dade_serve", "dade_autotune", "dade_destroy",
-            "dade_last_error")
+            "dade_export", "dade_import", "dade_stage_times", "dade_serve", "dade_autotune", "dade_graph_build",
+            "dade_graph_search", "dade_graph_export", "dade_destroy", "dade_last_error")
 TUNE_MAX = 24
 
 
@@ -102,6 +102,9 @@ def lib():
         L.dade_stage_times.argtypes = [vp, ctypes.POINTER(Times)]
         L.dade_serve.argtypes = [vp, i64, vp, vp, vp, vp, vp, ctypes.POINTER(ServeOpts), vp, vp, vp,
                                  ctypes.POINTER(ServeStats), vp]
+        L.dade_graph_build.argtypes = [vp, vp, i32, i32, vp]
+        L.dade_graph_search.argtypes = [vp, vp, i64, i32, i32, i32, i32, ctypes.POINTER(SearchOpts), vp, vp, vp]
+        L.dade_graph_export.argtypes = [vp, ctypes.POINTER(i32), vp, vp]
         L.dade_autotune.argtypes = [vp, vp, i64, i32, i32, vp, vp, ctypes.c_float, i32, ctypes.POINTER(SearchOpts),
                                     ctypes.POINTER(TuneResult), ctypes.POINTER(i32), vp]
         L.dade_destroy.argtypes = [vp]
@@ -279,6 +282,40 @@ def dade_autotune(ix: Index, Q, k, nprobe, k_per_query=None, nprobe_per_query=No
     table = [dict(delta_d=r.delta_d, schedule=names[r.schedule], fill_min=r.fill_min, growth=r.growth,
                   scan_blocks_per_cu=r.scan_blocks_per_cu, ms=r.ms, agreement=r.agreement) for r in res[: n.value]]
     return chosen, table
+
+
+def dade_graph_build(ix: Index, X, degree=32, nprobe=16, stream=None):
+    import torch
+    _check(lib().dade_graph_build(ix.handle, _dev(X, torch.float32, "X"), degree, nprobe, _stream(stream)))
+
+
+def dade_graph_search(ix: Index, Q, k, ef, n_entry=4, max_iters=0, delta_d=32, mode="dade", stats=None,
+                      out_ids=None, out_dist2=None, stream=None):
+    """Returns (ids [nq, k] int64, dist2 [nq, k] float32) device tensors (asynchronous)."""
+    import torch
+    nq = Q.shape[0]
+    if out_ids is None:
+        out_ids = torch.empty((nq, k), dtype=torch.int64, device=Q.device)
+    if out_dist2 is None:
+        out_dist2 = torch.empty((nq, k), dtype=torch.float32, device=Q.device)
+    o = _search_opts(delta_d=delta_d, mode=mode)
+    o.stats = None if stats is None else _dev(stats, torch.int64, "stats").value
+    _check(lib().dade_graph_search(ix.handle, _dev(Q, torch.float32, "Q"), nq, k, ef, n_entry, max_iters,
+                                   ctypes.byref(o), _dev(out_ids, torch.int64, "out_ids"),
+                                   _dev(out_dist2, torch.float32, "out_dist2"), _stream(stream)))
+    return out_ids, out_dist2
+
+
+def dade_graph_export(ix: Index):
+    """(neighbors [n, degree] int64 row ids, entries [nlist] int64 row ids) on the host."""
+    inf = dade_index_info(ix)
+    deg = ctypes.c_int32()
+    _check(lib().dade_graph_export(ix.handle, ctypes.byref(deg), None, None))
+    nb = np.empty((inf["n"], deg.value), np.int64)
+    en = np.empty(inf["nlist"], np.int64)
+    _check(lib().dade_graph_export(ix.handle, ctypes.byref(deg), ctypes.c_void_p(nb.ctypes.data),
+                                   ctypes.c_void_p(en.ctypes.data)))
+    return nb, en
 
 
 def dade_check(ix: Index, stream=None):

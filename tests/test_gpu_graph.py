@@ -1,0 +1,126 @@
+"""Graph search on the GPU (dade_graph_build / dade_graph_search) against the oracle
+(oracle/graph.py): the kNN graph and the entry points the library builds, then beam searches in
+DADE and FDScanning modes, FP32 and BF16 stores, run by the oracle on the library's own graph
+(exported as row ids) and compared element by element, near ties excused by their logged margins."""
+import numpy as np
+import pytest
+
+from oracle import graph, ivf
+from paper_2411_17229_amd import dade, workloads
+from gpu_helpers import MARGIN_TOL, artifacts, compare, oracle_index, to_np
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+DEG, NPROBE_BUILD = 16, 4
+
+
+def _setup(store):
+    w = workloads.WORKLOADS["small-20k-d128"]
+    X, Q = workloads.make(w, n_queries=200)
+    oi, _, _ = oracle_index(X, w.nlist, w.seed, alpha=w.alpha, store=store)
+    Xd = torch.from_numpy(X).cuda()
+    gi = dade.dade_import(artifacts(oi), Xd, store=store or "f32")
+    dade.dade_graph_build(gi, Xd, degree=DEG, nprobe=NPROBE_BUILD)
+    nb, en = dade.dade_graph_export(gi)
+    return dict(w=w, X=X, Q=Q, Qd=torch.from_numpy(Q).cuda(), oi=oi, gi=gi, nb=nb, en=en)
+
+
+@pytest.fixture(scope="module")
+def f32():
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    return _setup(None)
+
+
+@pytest.fixture(scope="module")
+def bf16():
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    return _setup("bf16")
+
+
+def test_graph_build_matches_oracle(f32):
+    """Sampled rows: the same neighbour distances as the oracle's FDScanning kNN (ids may swap only
+    between equal distances)."""
+    X, oi, nb = f32["X"], f32["oi"], f32["nb"]
+    rows = np.sort(np.random.default_rng(0).choice(len(X), 300, replace=False))
+    o_nb = graph.build_knn_graph(oi, X, DEG, NPROBE_BUILD, rows=rows)
+    Xd = X.astype(np.float64)
+    for i, r in enumerate(rows):
+        assert np.all(nb[r] >= 0) and r not in nb[r]
+        dg = np.sum((Xd[nb[r]] - Xd[r]) ** 2, axis=1)
+        do = np.sum((Xd[o_nb[i]] - Xd[r]) ** 2, axis=1)
+        np.testing.assert_allclose(dg, do, rtol=1e-5, err_msg=f"row {r}")
+        assert np.all(np.diff(dg) >= -1e-5 * dg[1:]), r
+
+
+def test_entry_points_are_list_medoids(f32):
+    X, oi, en = f32["X"], f32["oi"], f32["en"]
+    med = graph.list_medoids(oi, X)
+    Xd = X.astype(np.float64)
+    for l in range(oi.nlist):
+        members = oi.ids[oi.offsets[l]:oi.offsets[l + 1]]
+        assert en[l] in members
+        d_g = np.sum((Xd[en[l]] - oi.centroids[l]) ** 2)
+        d_o = np.sum((Xd[med[l]] - oi.centroids[l]) ** 2)
+        assert abs(d_g - d_o) <= 1e-5 * d_o, l
+
+
+def run_parity(env, mode, K=10, ef=48, n_entry=4, max_iters=0, dd=32):
+    nq = len(env["Q"])
+    stats = torch.zeros((nq, 4), dtype=torch.int64, device="cuda")
+    ids, d2 = dade.dade_graph_search(env["gi"], env["Qd"], K, ef, n_entry=n_entry, max_iters=max_iters,
+                                     delta_d=dd, mode=mode, stats=stats)
+    torch.cuda.synchronize()
+    ids, d2, st = to_np(ids), to_np(d2), to_np(stats)
+    o_ids, _, logs = graph.search(env["oi"], env["nb"], env["en"], env["Q"], K, ef, n_entry, dd, mode=mode,
+                                  max_iters=max_iters, log=True)
+    compare(o_ids, logs, ids, d2, env["X"], env["Q"], K, max_excused=0.05)
+    # queries without a near tie follow the same trajectory: the same DCOs, steps and visits
+    same = (logs["min_margin"] > MARGIN_TOL) & (logs["probe_gap"] > MARGIN_TOL)
+    assert same.mean() > 0.5
+    np.testing.assert_array_equal(st[same, 0], logs["dcos"][same])
+    np.testing.assert_array_equal(st[same, 1], logs["dims"][same])
+    np.testing.assert_array_equal(st[same, 2], logs["expansions"][same])
+    np.testing.assert_array_equal(st[same, 3], logs["visited"][same])
+    return st, logs
+
+
+@pytest.mark.parametrize("mode", ["dade", "full_d"])
+def test_graph_search_matches_oracle_f32(f32, mode):
+    st, _ = run_parity(f32, mode)
+    if mode == "dade":   # some tests exit early (a graph's candidates are near ones, so fewer than in IVF)
+        assert st[:, 1].sum() < st[:, 0].sum() * f32["w"].dim
+
+
+@pytest.mark.parametrize("ef,n_entry,max_iters,dd", [(10, 1, 0, 8), (64, 8, 40, 16), (32, 2, 0, 64)])
+def test_graph_search_parameters(f32, ef, n_entry, max_iters, dd):
+    run_parity(f32, "dade", K=min(10, ef), ef=ef, n_entry=n_entry, max_iters=max_iters, dd=dd)
+
+
+def test_graph_search_matches_oracle_bf16(bf16):
+    run_parity(bf16, "dade")
+
+
+def test_graph_search_batch_invariance(f32):
+    ids_b, d2_b = dade.dade_graph_search(f32["gi"], f32["Qd"], 10, 48, n_entry=4)
+    ids_b, d2_b = to_np(ids_b), to_np(d2_b)
+    for qi in (0, 77, 199):
+        i1, d1 = dade.dade_graph_search(f32["gi"], f32["Qd"][qi:qi + 1].contiguous(), 10, 48, n_entry=4)
+        assert np.array_equal(to_np(i1)[0], ids_b[qi]) and np.array_equal(to_np(d1)[0].view(np.uint32),
+                                                                         d2_b[qi].view(np.uint32))
+
+
+def test_graph_argument_errors(f32):
+    gi, Qd = f32["gi"], f32["Qd"]
+    for kw in (dict(k=10, ef=65), dict(k=20, ef=10), dict(k=10, ef=32, delta_d=12), dict(k=10, ef=32, n_entry=0),
+               dict(k=10, ef=64, max_iters=300)):
+        k, ef = kw.pop("k"), kw.pop("ef")
+        with pytest.raises(dade.DadeError):
+            dade.dade_graph_search(gi, Qd, k, ef, **kw)
+    other = dade.dade_import(artifacts(f32["oi"]), torch.from_numpy(f32["X"]).cuda())
+    with pytest.raises(dade.DadeError):   # no graph yet
+        dade.dade_graph_search(other, Qd, 10, 32)
+    other.close()
