@@ -354,6 +354,70 @@ def serving_sweep(dade, ix, Q, gt, k, ks, nprobes, n_req=2000, budget=512 << 20,
             "pinned_queries": True, "saturated": burst, "rates": out}
 
 
+GRAPH_EF = (16, 32, 64)
+GRAPH_ENTRY = (4, 16, 64)
+
+
+def graph_study(dade, torch, target, steps, degree=16, reverse=8, nprobe_build=4):
+    """The graph setting (one-layer kNN graph, DADE DCOs in a beam search) on the 20k x 128
+    workload (graph builds are limited to 20,000 rows): build time, then per ef the recall@k, QPS
+    and dimensions read of DADE (P_s of the workload) and FDScanning; the headline pair is each
+    mode's fastest (entry lists, ef) reaching `target`."""
+    from paper_2411_17229_amd import workloads
+    w = workloads.WORKLOADS["small-20k-d128"]
+    X, Q = workloads.make(w, n_queries=1000)
+    Xd, Qd = torch.from_numpy(X).cuda(), torch.from_numpy(Q).cuda()
+    store = w.store
+    ix = dade.dade_build_index(Xd, w.nlist, store=store, init_rows=workloads.kmeans_init_rows(w.n, w.nlist, w.seed))
+    dade.dade_rotate(ix)
+    dade.dade_calibrate(ix, w.alpha, pairs=workloads.calibration_pairs(w.n, 100_000, w.seed))
+    gt = ground_truth(torch, Xd, Qd, w.k)
+    t0 = time.perf_counter()
+    dade.dade_graph_build(ix, Xd, degree=degree, reverse=reverse, nprobe=nprobe_build)
+    build_s = time.perf_counter() - t0
+    nq = Qd.shape[0]
+    s_bytes = 2 if store in ("bf16", "f16") else 4
+    out = {"workload": w.name, "n": w.n, "dim": w.dim, "queries": len(Q), "p_s": w.alpha, "store": store,
+           "degree": degree, "reverse": reverse, "nprobe_build": nprobe_build, "build_s": round(build_s, 2),
+           "sweep": {}}
+    log(f"[bench] graph: degree {degree} + {reverse} back links built in {build_s:.1f}s")
+    for mode in ("dade", "full_d"):
+        rows = {}
+        for n_entry, ef in [(e, f) for e in GRAPH_ENTRY for f in GRAPH_EF]:
+            kw = dict(n_entry=n_entry, delta_d=w.delta_d, mode=mode)
+            stats = torch.zeros((nq, 4), dtype=torch.int64, device=Qd.device)
+            ids, _ = dade.dade_graph_search(ix, Qd, w.k, ef, stats=stats, **kw)
+            torch.cuda.synchronize()
+            st = stats.cpu().numpy().sum(0)
+            rec = recall_at(ids.cpu().numpy(), gt, w.k)
+            for _ in range(2):
+                dade.dade_graph_search(ix, Qd, w.k, ef, **kw)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            e0.record()
+            for _ in range(steps):
+                dade.dade_graph_search(ix, Qd, w.k, ef, **kw)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3 / steps
+            rows[(n_entry, ef)] = {"recall@10": round(rec, 4), "qps": round(nq / (ms / 1e3), 1), "ms_per_step": round(ms, 4),
+                        "event_ms": round(e0.elapsed_time(e1) / steps, 4),
+                        "dcos_per_query": round(float(st[0]) / nq, 1), "dims_frac": round(float(st[1]) / max(1, st[0] * w.dim), 4),
+                        "steps_per_query": round(float(st[2]) / nq, 1),
+                        "alg_GBps": round(s_bytes * float(st[1]) / (ms * 1e-3) / 1e9, 1)}
+            r_ = rows[(n_entry, ef)]
+            log(f"[bench] graph {mode} entry {n_entry} ef {ef}: recall {rec:.4f} {r_['qps']:.0f} QPS "
+                f"dims {r_['dims_frac']:.4f} dcos/q {r_['dcos_per_query']}")
+        out["sweep"][mode] = {f"entry{k_[0]}_ef{k_[1]}": v for k_, v in rows.items()}
+        ok = [c for c in rows if rows[c]["recall@10"] >= target]
+        pick = max(ok, key=lambda c: rows[c]["qps"]) if ok else max(rows, key=lambda c: rows[c]["recall@10"])
+        out[mode] = dict(n_entry=pick[0], ef=pick[1], **rows[pick])
+    out["speedup_vs_full_d"] = round(out["dade"]["qps"] / out["full_d"]["qps"], 3)
+    ix.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -370,6 +434,7 @@ def main():
     ap.add_argument("--no-linear", action="store_true", help="skip the linear-scan (one list) study")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving-loop sweep")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner run")
+    ap.add_argument("--no-graph-study", action="store_true", help="skip the graph-search study")
     ap.add_argument("--serving-only", action="store_true",
                     help="build, then only run the serving-loop sweep with the workload's request mix "
                          "(K in {10, 100}, nprobe in {32, 96}) at --p-s")
@@ -581,6 +646,8 @@ def main():
                                      for t in table]}
         log(f"[bench] autotune: {chosen} -> {out['autotune']['qps']:.0f} QPS, recall "
             f"{out['autotune']['recall@10']:.4f}")
+    if not args.no_graph_study:
+        out["graph"] = graph_study(dade, torch, args.target, max(3, args.steps // 4))
     if not args.no_variants and store != "f32":
         # the same lists and transform with the other 16-bit store and with FP32 (recall vs FP32)
         art = dade.dade_export(ix)

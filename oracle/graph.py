@@ -7,7 +7,7 @@ discards a neighbour whose DCO answers no.  This oracle follows that search on a
 * Graph (reading; the paper uses HNSW's hierarchy, this build uses one layer): every object's
   out-neighbours are its ``degree`` nearest other objects by the index's exact IVF search
   (FDScanning with K = degree + 1 over ``nprobe`` lists), ordered by (dist^2, id), the object
-  itself removed, -1 padded.
+  itself removed, -1 padded; then up to ``reverse`` back links (``add_reverse_edges``).
 * Entry points (reading): each IVF list's medoid, the member nearest its centroid (ties to the
   lower id); a query starts from the medoids of its ``n_entry`` nearest lists (probe order).
 * Beam: a pool of at most ``ef`` (dist^2, id) entries, each marked expanded or not.  Seeds enter
@@ -40,6 +40,32 @@ def build_knn_graph(index: ivf.Index, X, degree: int, nprobe: int, delta_d: int 
     for i, r in enumerate(rows):
         row = [int(v) for v in ids[i] if v >= 0 and v != r][:degree]
         out[i, :len(row)] = row
+    return out
+
+
+def add_reverse_edges(neighbors, X, reverse: int) -> np.ndarray:
+    """Rows of degree + reverse: each row's out-neighbours, then up to `reverse` of the rows that
+    list it as an out-neighbour and it does not list already, nearest first by (dist^2, id);
+    -1 padded (reading: one-layer graphs are made navigable by linking back, as HNSW's
+    bidirectional links do)."""
+    neighbors = np.asarray(neighbors)
+    n, deg = neighbors.shape
+    X = np.asarray(X, dtype=np.float64)
+    incoming = [[] for _ in range(n)]
+    for u in range(n):
+        for v in neighbors[u]:
+            if v >= 0:
+                incoming[int(v)].append(u)
+    out = np.full((n, deg + reverse), -1, dtype=np.int64)
+    for v in range(n):
+        fwd = [int(u) for u in neighbors[v] if u >= 0]
+        out[v, :len(fwd)] = fwd
+        cand = np.array(sorted(set(incoming[v]) - set(fwd)), dtype=np.int64)
+        if reverse == 0 or len(cand) == 0:
+            continue
+        d2 = np.sum((X[cand] - X[v]) ** 2, axis=1)
+        chosen = cand[np.lexsort((cand, d2))[:reverse]]
+        out[v, len(fwd):len(fwd) + len(chosen)] = chosen
     return out
 
 

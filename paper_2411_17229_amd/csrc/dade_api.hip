@@ -103,7 +103,10 @@ struct dade_index {
   // kNN graph (dade_graph_build)
   int32_t* d_nbr = nullptr;    // [n x graph_degree] out-neighbour positions, by position
   int32_t* d_entry = nullptr;  // [nlist] medoid position per list
-  int graph_degree = 0;
+  int graph_degree = 0;         // row width of a usable graph (0: none)
+  int graph_width = 0;          // row width of d_nbr's allocation
+  std::vector<int64_t> pos_h;   // row id -> packed position (host)
+  int64_t d_pos_h(int64_t row) const { return pos_h[size_t(row)]; }
 
   std::vector<void*> owned;
 };
@@ -213,6 +216,7 @@ int set_lists(dade_index* ix, const std::vector<int32_t>& lab, hipStream_t s) {
   std::vector<int32_t> ids32(n);
   std::vector<int64_t> pos(n);
   for (int64_t p = 0; p < n; ++p) { ids32[p] = int32_t(ix->ids_h[p]); pos[ix->ids_h[p]] = p; }
+  ix->pos_h = pos;
   int rc;
   if (!ix->d_off && (rc = alloc_t(ix, &ix->d_off, ix->nlist + 1))) return rc;
   if (!ix->d_ids && (rc = alloc_t(ix, &ix->d_ids, n))) return rc;
@@ -937,24 +941,32 @@ int dade_stage_times(dade_index* ix, dade_times* out) {
   return DADE_OK;
 }
 
-int dade_graph_build(dade_index* ix, const float* X, int32_t degree, int32_t nprobe, void* stream) {
+int dade_graph_build(dade_index* ix, const float* X, int32_t degree, int32_t reverse, int32_t nprobe,
+                     void* stream) {
   if (!ix) FAIL(DADE_EINVAL, "index is NULL");
-  if (degree < 1 || degree > kGraphMax) FAIL(DADE_EINVAL, "degree must be in [1, 64]");
+  if (degree < 1 || reverse < 0 || degree + reverse > kGraphMax)
+    FAIL(DADE_EINVAL, "degree >= 1, reverse >= 0 and degree + reverse <= 64 are required");
   if (nprobe < 1) FAIL(DADE_EINVAL, "nprobe must be >= 1");
   if (ix->state < DADE_STATE_ROTATED) FAIL(DADE_ESTATE, "the graph needs a rotated index");
+  if (ix->n > kGraphBuildMaxRows)
+    FAIL(DADE_EINVAL, "graph build: indexes of more than " + std::to_string(kGraphBuildMaxRows) +
+                          " rows are not supported (a build of 1M x 960 rows faulted the GPU; its cause is open)");
   int rc = check_device_pointer(X, "X");
   if (rc) return rc;
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int64_t n = ix->n;
-  if (ix->d_nbr && ix->graph_degree != degree) {
+  const int width = degree + reverse;
+  if (ix->d_nbr && ix->graph_width != width) {
     HIPC(hipStreamSynchronize(s));
-    dev_free(ix, ix->d_nbr, sizeof(int32_t) * size_t(n) * ix->graph_degree);
+    dev_free(ix, ix->d_nbr, sizeof(int32_t) * size_t(n) * ix->graph_width);
     ix->d_nbr = nullptr;
-    ix->graph_degree = 0;
+    ix->graph_width = 0;
   }
-  if (!ix->d_nbr && (rc = alloc_t(ix, &ix->d_nbr, size_t(n) * degree))) return rc;
+  if (!ix->d_nbr && (rc = alloc_t(ix, &ix->d_nbr, size_t(n) * width))) return rc;
+  ix->graph_width = width;
   if (!ix->d_entry && (rc = alloc_t(ix, &ix->d_entry, size_t(ix->nlist)))) return rc;
   ix->graph_degree = 0;   // not usable until complete
+  // forward lists first, at stride `width`, then the back links merged in on the host
   const int64_t chunk = std::min<int64_t>(n, 65536);
   int64_t* res = nullptr;
   float* rd = nullptr;
@@ -974,7 +986,7 @@ int dade_graph_build(dade_index* ix, const float* X, int32_t degree, int32_t npr
     const int64_t cn = std::min(chunk, n - c0);
     rc = dade_search(ix, X + c0 * ix->dim, cn, degree + 1, nprobe, nullptr, nullptr, &o, res, rd, stream);
     if (rc == DADE_OK) {
-      const hipError_t e = launch_graph_collect(res, int(cn), c0, degree, ix->d_pos, ix->d_nbr, s);
+      const hipError_t e = launch_graph_collect(res, int(cn), c0, degree, width, ix->d_pos, ix->d_nbr, s);
       if (e != hipSuccess) { dade::set_error(hip_msg(e, "graph collect")); rc = DADE_EDEVICE; }
     }
   }
@@ -988,7 +1000,45 @@ int dade_graph_build(dade_index* ix, const float* X, int32_t degree, int32_t npr
   dev_free(ix, rd, sizeof(float) * size_t(chunk) * (degree + 1));
   if (rc) return rc;
   if (e != hipSuccess) FAIL(DADE_EDEVICE, hip_msg(e, "graph build"));
-  ix->graph_degree = degree;
+  if (reverse > 0) {
+    // back links: for each row, the rows listing it that it does not list, nearest first by
+    // (squared distance in FP64 over the FP32 vectors, row id), at most `reverse` of them
+    const int dp = ix->dp;
+    std::vector<int32_t> nb(size_t(n) * width);
+    std::vector<float> xh(size_t(n) * dp);
+    HIPC(hipMemcpy(nb.data(), ix->d_nbr, sizeof(int32_t) * nb.size(), hipMemcpyDeviceToHost));
+    HIPC(hipMemcpy(xh.data(), ix->X, sizeof(float) * xh.size(), hipMemcpyDeviceToHost));
+    std::vector<std::vector<int32_t>> incoming(static_cast<size_t>(n));
+    for (int64_t p = 0; p < n; ++p)
+      for (int j = 0; j < degree; ++j) {
+        const int32_t u = nb[size_t(p) * width + j];
+        if (u >= 0) incoming[size_t(u)].push_back(int32_t(p));
+      }
+    std::vector<std::pair<double, int64_t>> cand;   // (distance, row id)
+    for (int64_t v = 0; v < n; ++v) {
+      int32_t* row = nb.data() + size_t(v) * width;
+      const int64_t rv = ix->ids_h[size_t(v)];
+      cand.clear();
+      for (int32_t u : incoming[size_t(v)]) {
+        if (std::find(row, row + degree, u) != row + degree) continue;
+        const int64_t ru = ix->ids_h[size_t(u)];
+        double d2 = 0.0;
+        for (int c = 0; c < ix->dim; ++c) {
+          const double t = double(xh[size_t(ru) * dp + c]) - double(xh[size_t(rv) * dp + c]);
+          d2 += t * t;
+        }
+        cand.emplace_back(d2, ru);
+      }
+      std::sort(cand.begin(), cand.end());
+      cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
+      int w = 0;
+      while (w < degree && row[w] >= 0) ++w;
+      for (size_t i = 0; i < cand.size() && i < size_t(reverse); ++i) row[w++] = int32_t(ix->d_pos_h(cand[i].second));
+      for (; w < width; ++w) row[w] = -1;
+    }
+    HIPC(hipMemcpy(ix->d_nbr, nb.data(), sizeof(int32_t) * nb.size(), hipMemcpyHostToDevice));
+  }
+  ix->graph_degree = width;
   return DADE_OK;
 }
 

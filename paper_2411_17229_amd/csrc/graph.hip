@@ -228,13 +228,14 @@ __global__ __launch_bounds__(64) void graph_search_kernel(GraphArgs a) {
 }
 
 // Out-neighbours of query rows [c0, c0 + cn) from their FDScanning results (K = degree + 1):
-// the row itself dropped, positions written at the row's own position, -1 padded.
-__global__ void graph_collect_kernel(const int64_t* res, int cn, int64_t c0, int degree, const int64_t* pos,
-                                     int32_t* nbr) {
+// the row itself dropped, positions written at the row's own position (rows of `width`),
+// -1 padded up to degree.
+__global__ void graph_collect_kernel(const int64_t* res, int cn, int64_t c0, int degree, int width,
+                                     const int64_t* pos, int32_t* nbr) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= cn) return;
   const int64_t i = c0 + t;
-  int32_t* out = nbr + pos[i] * degree;
+  int32_t* out = nbr + pos[i] * width;
   int w = 0;
   for (int j = 0; j <= degree; ++j) {
     const int64_t id = res[int64_t(t) * (degree + 1) + j];
@@ -299,10 +300,11 @@ hipError_t launch_graph_search(const GraphArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_graph_collect(const int64_t* res, int cn, int64_t c0, int degree, const int64_t* pos,
+hipError_t launch_graph_collect(const int64_t* res, int cn, int64_t c0, int degree, int width, const int64_t* pos,
                                 int32_t* nbr, hipStream_t s) {
   if (cn == 0) return hipSuccess;
-  hipLaunchKernelGGL(graph_collect_kernel, dim3((cn + 255) / 256), dim3(256), 0, s, res, cn, c0, degree, pos, nbr);
+  hipLaunchKernelGGL(graph_collect_kernel, dim3((cn + 255) / 256), dim3(256), 0, s, res, cn, c0, degree, width,
+                     pos, nbr);
   return hipGetLastError();
 }
 

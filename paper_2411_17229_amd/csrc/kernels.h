@@ -147,6 +147,7 @@ int round_blocks_per_cu(int dtype, int mode, int delta_d);
 
 // ---------------------------------------------------------------- graph search (graph.hip)
 constexpr int kGraphMax = 64;   // largest degree, ef and n_entry (one wave holds a query's pool)
+constexpr int64_t kGraphBuildMaxRows = 20000;   // largest index dade_graph_build accepts
 struct GraphArgs {
   int nq = 0, dim = 0, dp = 0, delta_d = 0;   // delta_d % 8 == 0 in DADE mode
   int mode = 0, dtype = 0;                    // mode 0: DADE, 1: FDScanning
@@ -169,7 +170,7 @@ struct GraphArgs {
 // LDS bytes of one query's workgroup: the visited table (2^slots_log2 ints) and the merge area.
 size_t graph_lds_bytes(int slots_log2);
 hipError_t launch_graph_search(const GraphArgs& a, hipStream_t s);
-hipError_t launch_graph_collect(const int64_t* res, int cn, int64_t c0, int degree, const int64_t* pos,
+hipError_t launch_graph_collect(const int64_t* res, int cn, int64_t c0, int degree, int width, const int64_t* pos,
                                 int32_t* nbr, hipStream_t s);
 hipError_t launch_graph_entry(const float* X, const float* cent, const int64_t* off, const int32_t* ids,
                               const int64_t* pos, int dp, int nlist, int32_t* entry, hipStream_t s);

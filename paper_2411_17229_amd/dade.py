@@ -102,7 +102,7 @@ def lib():
         L.dade_stage_times.argtypes = [vp, ctypes.POINTER(Times)]
         L.dade_serve.argtypes = [vp, i64, vp, vp, vp, vp, vp, ctypes.POINTER(ServeOpts), vp, vp, vp,
                                  ctypes.POINTER(ServeStats), vp]
-        L.dade_graph_build.argtypes = [vp, vp, i32, i32, vp]
+        L.dade_graph_build.argtypes = [vp, vp, i32, i32, i32, vp]
         L.dade_graph_search.argtypes = [vp, vp, i64, i32, i32, i32, i32, ctypes.POINTER(SearchOpts), vp, vp, vp]
         L.dade_graph_export.argtypes = [vp, ctypes.POINTER(i32), vp, vp]
         L.dade_autotune.argtypes = [vp, vp, i64, i32, i32, vp, vp, ctypes.c_float, i32, ctypes.POINTER(SearchOpts),
@@ -284,9 +284,10 @@ def dade_autotune(ix: Index, Q, k, nprobe, k_per_query=None, nprobe_per_query=No
     return chosen, table
 
 
-def dade_graph_build(ix: Index, X, degree=32, nprobe=16, stream=None):
+def dade_graph_build(ix: Index, X, degree=16, reverse=8, nprobe=4, stream=None):
     import torch
-    _check(lib().dade_graph_build(ix.handle, _dev(X, torch.float32, "X"), degree, nprobe, _stream(stream)))
+    _check(lib().dade_graph_build(ix.handle, _dev(X, torch.float32, "X"), degree, reverse, nprobe,
+                                  _stream(stream)))
 
 
 def dade_graph_search(ix: Index, Q, k, ef, n_entry=4, max_iters=0, delta_d=32, mode="dade", stats=None,

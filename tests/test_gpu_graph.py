@@ -13,7 +13,7 @@ pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
 
-DEG, NPROBE_BUILD = 16, 4
+DEG, REV, NPROBE_BUILD = 16, 8, 4
 
 
 def _setup(store):
@@ -22,7 +22,7 @@ def _setup(store):
     oi, _, _ = oracle_index(X, w.nlist, w.seed, alpha=w.alpha, store=store)
     Xd = torch.from_numpy(X).cuda()
     gi = dade.dade_import(artifacts(oi), Xd, store=store or "f32")
-    dade.dade_graph_build(gi, Xd, degree=DEG, nprobe=NPROBE_BUILD)
+    dade.dade_graph_build(gi, Xd, degree=DEG, reverse=REV, nprobe=NPROBE_BUILD)
     nb, en = dade.dade_graph_export(gi)
     return dict(w=w, X=X, Q=Q, Qd=torch.from_numpy(Q).cuda(), oi=oi, gi=gi, nb=nb, en=en)
 
@@ -48,12 +48,23 @@ def test_graph_build_matches_oracle(f32):
     rows = np.sort(np.random.default_rng(0).choice(len(X), 300, replace=False))
     o_nb = graph.build_knn_graph(oi, X, DEG, NPROBE_BUILD, rows=rows)
     Xd = X.astype(np.float64)
+    assert nb.shape == (len(X), DEG + REV)
     for i, r in enumerate(rows):
-        assert np.all(nb[r] >= 0) and r not in nb[r]
-        dg = np.sum((Xd[nb[r]] - Xd[r]) ** 2, axis=1)
+        fwd = nb[r, :DEG]
+        assert np.all(fwd >= 0) and r not in nb[r]
+        dg = np.sum((Xd[fwd] - Xd[r]) ** 2, axis=1)
         do = np.sum((Xd[o_nb[i]] - Xd[r]) ** 2, axis=1)
         np.testing.assert_allclose(dg, do, rtol=1e-5, err_msg=f"row {r}")
         assert np.all(np.diff(dg) >= -1e-5 * dg[1:]), r
+    # back links: the oracle's rule applied to the library's forward lists
+    H = graph.add_reverse_edges(nb[:, :DEG], X, REV)
+    for r in rows:
+        got = [u for u in nb[r, DEG:] if u >= 0]
+        want = [u for u in H[r, DEG:] if u >= 0]
+        assert len(got) == len(want), r
+        dg = np.sum((Xd[got] - Xd[r]) ** 2, axis=1)
+        dw = np.sum((Xd[want] - Xd[r]) ** 2, axis=1)
+        np.testing.assert_allclose(dg, dw, rtol=1e-12, err_msg=f"row {r}")
 
 
 def test_entry_points_are_list_medoids(f32):
@@ -124,3 +135,17 @@ def test_graph_argument_errors(f32):
     with pytest.raises(dade.DadeError):   # no graph yet
         dade.dade_graph_search(other, Qd, 10, 32)
     other.close()
+
+
+def test_graph_build_rejects_indexes_above_its_limit():
+    """Builds above 20,000 rows are refused before any device work (the check is on the host)."""
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    w = workloads.WORKLOADS["small-20k-d128"]
+    X = np.concatenate([workloads.make(w)[0], workloads.make(w)[0][:10]])
+    Xd = torch.from_numpy(X).cuda()
+    gi = dade.dade_build_index(Xd, 16, kmeans_iters=1)
+    dade.dade_rotate(gi)
+    with pytest.raises(dade.DadeError, match="not supported"):
+        dade.dade_graph_build(gi, Xd, degree=8, reverse=0, nprobe=2)
+    gi.close()

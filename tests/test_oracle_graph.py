@@ -111,3 +111,24 @@ def test_low_precision_beam_returns_exact_distances():
         ex = np.sum((X[ids[q][v]].astype(np.float64) - Q[q].astype(np.float64)) ** 2, axis=1)
         np.testing.assert_allclose(d2[q][v], ex, rtol=1e-10)
         assert list(d2[q][v]) == sorted(d2[q][v])
+
+
+def test_reverse_edges_link_back_nearest_first():
+    """Every listed back link is a row that points here; each row keeps its forward list first;
+    the back links are the nearest such rows (brute force over all in-links); no duplicates."""
+    X, oi = small_index(seed=11)
+    G = graph.build_knn_graph(oi, X, degree=4, nprobe=2)
+    H = graph.add_reverse_edges(G, X, reverse=3)
+    assert H.shape == (len(X), 7)
+    Xd = X.astype(np.float64)
+    for v in range(len(X)):
+        row = [int(u) for u in H[v] if u >= 0]
+        assert len(row) == len(set(row)) and v not in row
+        assert row[:4] == [int(u) for u in G[v] if u >= 0]
+        back = row[4:]
+        pointing = [u for u in range(len(X)) if v in G[u] and u not in G[v]]
+        assert set(back) <= set(pointing)
+        want = sorted(pointing, key=lambda u: (np.sum((Xd[u] - Xd[v]) ** 2), u))[:3]
+        assert back == want, v
+    # every row that has an in-link can now be reached back from it
+    assert sum((H >= 0).sum(1)) > sum((G >= 0).sum(1))
