@@ -418,6 +418,52 @@ def graph_study(dade, torch, target, steps, degree=16, reverse=8, nprobe_build=4
     return out
 
 
+def uneven_study(dade, torch, ix, Xd, Qd, w, store, target, steps, warmup):
+    """One launch of the uneven batch (per-query K and nprobe drawn as the workload states): P_s is
+    the largest of the sweep whose mean recall@K reaches `target`; Delta_d and the round and launch
+    shapes come from the autotuner (first 512 queries, agreement bound `target`); then DADE and
+    FDScanning are timed on the whole batch, with recall@K per K."""
+    from paper_2411_17229_amd import workloads
+    nq = Qd.shape[0]
+    K, npb = workloads.uneven_batch(nq, 8, 128, (1, 10, 50, 100), seed=w.seed)
+    kp, npp = torch.from_numpy(K).to(Qd.device), torch.from_numpy(npb).to(Qd.device)
+    kmax, npmax = int(K.max()), int(npb.max())
+    gt = ground_truth(torch, Xd, Qd, kmax)
+    pairs = workloads.calibration_pairs(w.n, 100_000, w.seed)
+
+    def recall(ids):
+        r = np.array([len(set(ids[i, :K[i]].tolist()) & set(gt[i, :K[i]].tolist())) / K[i] for i in range(nq)])
+        return float(r.mean()), {str(k_): round(float(r[K == k_].mean()), 4) for k_ in sorted(set(K.tolist()))}
+
+    base = dict(delta_d=w.delta_d, **SCHEDULE)
+    by_ps = {}
+    chosen_ps = PS_SWEEP[-1]
+    for ps in PS_SWEEP:
+        dade.dade_calibrate(ix, ps, pairs=pairs)
+        ids, _ = dade.dade_search(ix, Qd, kmax, npmax, k_per_query=kp, nprobe_per_query=npp, **base)
+        by_ps[str(ps)] = round(recall(ids.cpu().numpy())[0], 4)
+        log(f"[bench] uneven: P_s {ps} recall {by_ps[str(ps)]}")
+        if by_ps[str(ps)] >= target:
+            chosen_ps = ps
+            break
+    dade.dade_calibrate(ix, chosen_ps, pairs=pairs)
+    tuned, table = dade.dade_autotune(ix, Qd[:512].contiguous(), kmax, npmax, k_per_query=kp[:512].contiguous(),
+                                      nprobe_per_query=npp[:512].contiguous(), min_agreement=target, reps=3)
+    log(f"[bench] uneven: autotuned {tuned}")
+    out = {"workload": w.name, "n": w.n, "dim": w.dim, "nlist": w.nlist, "store": store, "queries": nq,
+           "k_mix": {str(k_): int((K == k_).sum()) for k_ in sorted(set(K.tolist()))},
+           "nprobe_mean": round(float(npb.mean()), 1), "p_s": chosen_ps, "recall_by_p_s": by_ps, "autotuned": tuned}
+    for mode, kw in (("dade", dict(tuned)), ("full_d", dict(base, mode="full_d"))):
+        ms = throughput(dade, torch, ix, Qd, kmax, npmax, steps, warmup, k_per_query=kp, nprobe_per_query=npp, **kw)
+        ids, _ = dade.dade_search(ix, Qd, kmax, npmax, k_per_query=kp, nprobe_per_query=npp, **kw)
+        rec, per_k = recall(ids.cpu().numpy())
+        out[mode] = {"qps": round(nq / (ms / 1e3), 1), "ms_per_step": round(ms, 4), "recall": round(rec, 4),
+                     "recall_by_k": per_k}
+        log(f"[bench] uneven {mode}: {out[mode]['qps']:.0f} QPS ({ms:.3f} ms per batch), recall {rec:.4f} {per_k}")
+    out["speedup_vs_full_d"] = round(out["dade"]["qps"] / out["full_d"]["qps"], 3)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -435,6 +481,9 @@ def main():
     ap.add_argument("--no-serving", action="store_true", help="skip the serving-loop sweep")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner run")
     ap.add_argument("--no-graph-study", action="store_true", help="skip the graph-search study")
+    ap.add_argument("--uneven-only", action="store_true",
+                    help="build, then only measure the workload's uneven batch (per-query K in {1, 10, 50, 100}, "
+                         "nprobe in 8..128): DADE with autotuned options against FDScanning")
     ap.add_argument("--serving-only", action="store_true",
                     help="build, then only run the serving-loop sweep with the workload's request mix "
                          "(K in {10, 100}, nprobe in {32, 96}) at --p-s")
@@ -501,6 +550,11 @@ def main():
     t0 = time.perf_counter()
     gt = ground_truth(torch, Xd, Qd, w.k)
     log(f"[bench] FP64 ground truth in {time.perf_counter() - t0:.1f}s")
+
+    if args.uneven_only:
+        print(json.dumps(uneven_study(dade, torch, ix, Xd, Qd, w, store, args.target, args.steps, args.warmup)),
+              flush=True)
+        return
 
     if args.serving_only:
         # P_s: the largest of the sweep whose recall@10 at the mix's smaller nprobe reaches the target
