@@ -312,7 +312,7 @@ struct SearchPlan {
 int plan_search(dade_index* ix, int64_t nq, int32_t k, int32_t nprobe, const dade_search_opts& o,
                 hipStream_t s, SearchPlan& pl) {
   int rc;
-  const int dp = ix->dp, nl = ix->nlist;
+  const int nl = ix->nlist;
   const int npm = std::min<int>(nprobe, nl);
   // the most candidates one round can hold (per-rank: one list; doubling: its widest round)
   const std::vector<int64_t>& sizes = ix->sizes_desc;
