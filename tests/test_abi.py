@@ -58,3 +58,17 @@ def test_serve_rejects_missing_arguments_before_touching_a_device():
     args[1] = 0
     assert L.dade_serve(*args) == dade.DADE_EINVAL
     assert "index is NULL" in dade.dade_last_error()
+
+
+def test_new_entry_points_reject_null_handles_before_touching_a_device():
+    """dade_autotune, dade_graph_build, dade_graph_search and dade_graph_export validate their
+    handle before any HIP call (safe without a GPU)."""
+    from paper_2411_17229_amd import dade
+    if not os.path.exists(dade.LIB_PATH):
+        pytest.skip("libdade.so not built")
+    L = dade.lib()
+    assert L.dade_autotune(None, None, 1, 10, 8, None, None, 0.5, 1, None, None, None, None) == dade.DADE_EINVAL
+    assert L.dade_graph_build(None, None, 16, 8, 4, None) == dade.DADE_EINVAL
+    assert L.dade_graph_search(None, None, 1, 10, 32, 4, 0, None, None, None, None) == dade.DADE_EINVAL
+    assert L.dade_graph_export(None, None, None, None) == dade.DADE_EINVAL
+    assert "NULL" in dade.dade_last_error()
