@@ -6,6 +6,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <cstdlib>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -115,9 +117,30 @@ namespace {
 
 size_t dtype_size(int dt) { return dt == DADE_F32 ? 4 : 2; }
 
+// Failure injection for tests of error paths: with DADE_FAIL_ALLOC_AFTER=N in the environment,
+// every device allocation after the first N made since the variable took its current value fails
+// with DADE_ENOMEM before hipMalloc is called.
+bool refuse_allocation() {
+  static std::mutex mu;
+  static std::string last;
+  static long count = 0;
+  const char* env = std::getenv("DADE_FAIL_ALLOC_AFTER");
+  std::lock_guard<std::mutex> lock(mu);
+  if (!env) {
+    last.clear();
+    return false;
+  }
+  if (last != env) {
+    last = env;
+    count = 0;
+  }
+  return count++ >= std::atol(env);
+}
+
 int dev_alloc(dade_index* ix, void** p, size_t bytes) {
   *p = nullptr;
   if (bytes == 0) bytes = 16;
+  if (refuse_allocation()) FAIL(DADE_ENOMEM, "allocation refused (DADE_FAIL_ALLOC_AFTER)");
   if (ix->budget > 0 && ix->held + int64_t(bytes) > ix->budget)
     FAIL(DADE_ENOMEM, "HBM budget exceeded: need " + std::to_string(ix->held + bytes) + " bytes, budget " +
                           std::to_string(ix->budget));
@@ -294,8 +317,16 @@ int grow_query_workspace(dade_index* ix, int64_t nq, int64_t npm, hipStream_t s)
     ix->w_probes = nullptr;
     ix->w_nq = ix->w_np = 0;
     if ((rc = alloc_t(ix, &ix->w_qpad, size_t(new_nq) * dp)) || (rc = alloc_t(ix, &ix->w_qrot, size_t(new_nq) * dp)) ||
-        (rc = alloc_t(ix, &ix->w_pd, size_t(new_nq) * nl)) || (rc = alloc_t(ix, &ix->w_probes, size_t(new_nq) * new_np)))
+        (rc = alloc_t(ix, &ix->w_pd, size_t(new_nq) * nl)) || (rc = alloc_t(ix, &ix->w_probes, size_t(new_nq) * new_np))) {
+      // leave no part of the workspace behind (the next search grows it again)
+      dev_free(ix, ix->w_qpad, sizeof(float) * new_nq * dp);
+      dev_free(ix, ix->w_qrot, sizeof(float) * new_nq * dp);
+      dev_free(ix, ix->w_pd, sizeof(float) * new_nq * nl);
+      dev_free(ix, ix->w_probes, sizeof(int32_t) * new_nq * new_np);
+      ix->w_qpad = ix->w_qrot = ix->w_pd = nullptr;
+      ix->w_probes = nullptr;
       return rc;
+    }
     ix->w_nq = new_nq; ix->w_np = new_np;
   }
   return DADE_OK;
@@ -956,6 +987,7 @@ int dade_graph_build(dade_index* ix, const float* X, int32_t degree, int32_t rev
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int64_t n = ix->n;
   const int width = degree + reverse;
+  ix->graph_degree = 0;   // not usable until complete
   if (ix->d_nbr && ix->graph_width != width) {
     HIPC(hipStreamSynchronize(s));
     dev_free(ix, ix->d_nbr, sizeof(int32_t) * size_t(n) * ix->graph_width);
@@ -965,7 +997,6 @@ int dade_graph_build(dade_index* ix, const float* X, int32_t degree, int32_t rev
   if (!ix->d_nbr && (rc = alloc_t(ix, &ix->d_nbr, size_t(n) * width))) return rc;
   ix->graph_width = width;
   if (!ix->d_entry && (rc = alloc_t(ix, &ix->d_entry, size_t(ix->nlist)))) return rc;
-  ix->graph_degree = 0;   // not usable until complete
   // forward lists first, at stride `width`, then the back links merged in on the host
   const int64_t chunk = std::min<int64_t>(n, 65536);
   int64_t* res = nullptr;
