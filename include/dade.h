@@ -203,10 +203,11 @@ typedef struct {
   float query_gemm_ms;      /* one GEMM: rotated queries and query-centroid distances */
   float select_ms;          /* probe selection */
   float scan_ms;            /* the whole list scan: planning, rounds and merges */
-  float round_kernel_ms;    /* sum over rounds of the DCO kernel's duration */
-  float merge_kernel_ms;    /* sum over rounds of the merge kernel's duration */
-  float plan_ms;            /* work-item planning */
-  int32_t round_launches;   /* DCO kernel launches summed in round_kernel_ms */
+  float round_kernel_ms;    /* sum over rounds (and passes) of the DCO kernel's duration */
+  float merge_kernel_ms;    /* sum over rounds (and passes) of the merge kernel's duration */
+  float plan_ms;            /* work-item planning (all passes) */
+  int32_t round_launches;   /* DCO kernel launches summed in round_kernel_ms; a search whose
+                               workspace cannot hold every query at once runs in passes */
 } dade_times;
 
 /* dade_stage_times -- wait for the last timed dade_search and report its times. */

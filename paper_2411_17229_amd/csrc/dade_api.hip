@@ -92,10 +92,10 @@ struct dade_index {
   int scan_occ[3][2][2] = {};                        // resident scan workgroups per CU
   hipEvent_t ev[4] = {};
   bool ev_made = false, ev_used = false;
-  // per-kernel events of a timed search: plan (before, after), then per round (before the DCO
+  // per-kernel events of a timed search, one set per pass: plan (before, after), then per round (before the DCO
   // kernel, between it and the merge, after the merge)
   std::vector<hipEvent_t> kev;
-  int kev_rounds = 0;
+  int kev_rounds = 0, kev_passes = 0;
   int cus = 256;
   hipStream_t cap = nullptr;   // origin stream of graph captures (the caller's may be the null stream)
   // the last captured round-launch sequence and the argument bytes it was captured with
@@ -775,11 +775,11 @@ int dade_import(const dade_artifacts* a, const float* X, const dade_build_opts* 
 }
 
 // The launches of one pass of the list scan: planning, then each round's DCO and merge kernels.
-static hipError_t enqueue_rounds(dade_index* ix, const RoundArgs& a, int rounds, bool timed, hipStream_t s) {
+// kev (nullable): this pass's events (layout: see dade_index::kev).
+static hipError_t enqueue_rounds(dade_index* ix, const RoundArgs& a, int rounds, hipEvent_t* kev, hipStream_t s) {
   hipError_t e;
 #define ENQ(x) \
   if ((e = (x)) != hipSuccess) return e
-  hipEvent_t* kev = timed ? ix->kev.data() : nullptr;   // layout: see dade_index::kev
   if (kev) ENQ(hipEventRecord(kev[0], s));
   ENQ(launch_plan(a, ix->w_counts, s));
   if (kev) ENQ(hipEventRecord(kev[1], s));
@@ -890,13 +890,17 @@ int dade_search(dade_index* ix, const float* Q, int64_t nq, int32_t k, int32_t n
     a.items = ix->w_items;
     a.n_items = ix->w_counter; a.overflow = ix->w_flags;
     a.item_off = ix->w_counts;
-    if (o.record_times) {   // events for this pass (the last pass's times are reported)
-      while (ix->kev.size() < size_t(2 + 3 * rounds)) {
+    hipEvent_t* kev = nullptr;
+    if (o.record_times) {   // one set of events per pass; the reported times sum every pass
+      const int64_t n_pass = (nq + chunk - 1) / chunk;
+      while (ix->kev.size() < size_t(n_pass * (2 + 3 * rounds))) {
         hipEvent_t e;
         HIPC(hipEventCreate(&e));
         ix->kev.push_back(e);
       }
       ix->kev_rounds = rounds;
+      ix->kev_passes = int(n_pass);
+      kev = ix->kev.data() + size_t(c0 / chunk) * (2 + 3 * rounds);
     }
     // the launch sequence of this pass; replayed from a captured graph when it is the same as
     // the last captured one (a whole batch in one pass).  Captures start on an internal stream
@@ -914,7 +918,7 @@ int dade_search(dade_index* ix, const float* Q, int64_t nq, int32_t k, int32_t n
       }
       HIPC(hipStreamBeginCapture(ix->cap, hipStreamCaptureModeRelaxed));
     }
-    hipError_t e = enqueue_rounds(ix, a, rounds, o.record_times != 0, graph ? ix->cap : s);
+    hipError_t e = enqueue_rounds(ix, a, rounds, kev, graph ? ix->cap : s);
     if (graph) {
       hipGraph_t g = nullptr;
       const hipError_t e2 = hipStreamEndCapture(ix->cap, &g);
@@ -959,15 +963,20 @@ int dade_stage_times(dade_index* ix, dade_times* out) {
   out->query_gemm_ms = ms[0];
   out->select_ms = ms[1];
   out->scan_ms = ms[2];
-  HIPC(hipEventElapsedTime(&out->plan_ms, ix->kev[0], ix->kev[1]));
-  for (int r = 0; r < ix->kev_rounds; ++r) {
-    const hipEvent_t* e = ix->kev.data() + 2 + 3 * r;
-    float t1, t2;
-    HIPC(hipEventElapsedTime(&t1, e[0], e[1]));
-    HIPC(hipEventElapsedTime(&t2, e[1], e[2]));
-    out->round_kernel_ms += t1;
-    out->merge_kernel_ms += t2;
-    ++out->round_launches;
+  for (int p = 0; p < ix->kev_passes; ++p) {
+    const hipEvent_t* k = ix->kev.data() + size_t(p) * (2 + 3 * ix->kev_rounds);
+    float tp;
+    HIPC(hipEventElapsedTime(&tp, k[0], k[1]));
+    out->plan_ms += tp;
+    for (int r = 0; r < ix->kev_rounds; ++r) {
+      const hipEvent_t* e = k + 2 + 3 * r;
+      float t1, t2;
+      HIPC(hipEventElapsedTime(&t1, e[0], e[1]));
+      HIPC(hipEventElapsedTime(&t2, e[1], e[2]));
+      out->round_kernel_ms += t1;
+      out->merge_kernel_ms += t2;
+      ++out->round_launches;
+    }
   }
   return DADE_OK;
 }

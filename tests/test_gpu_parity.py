@@ -296,3 +296,18 @@ def test_linear_scan_one_list(dd):
     rel = np.abs(st[:, 1] - logs["dims"]) / logs["dims"]
     assert np.median(rel) == 0.0 and rel.max() < 0.02
     gi.close()
+
+
+def test_stage_times_of_a_timed_search(small):
+    """A timed search (kernels launched one by one, events around each) gives the same rows as
+    the untimed one; its report counts every round's DCO kernel and the kernels fit in the stage."""
+    w = small["w"]
+    kw = dict(delta_d=w.delta_d, schedule="doubling", fill_min=32, growth=0)
+    ids0, d0 = gpu_search(small["gi"], small["Qd"], w.k, w.nprobe, **kw)
+    ids1, d1 = gpu_search(small["gi"], small["Qd"], w.k, w.nprobe, record_times=True, **kw)
+    assert np.array_equal(ids0, ids1) and np.array_equal(d0.view(np.uint32), d1.view(np.uint32))
+    t = dade.dade_stage_times(small["gi"])
+    rounds = 2 + int(np.ceil(np.log2(w.nprobe)))   # the first round, then ranks 1, 2, 4, ... nprobe
+    assert t["round_launches"] == rounds
+    assert t["round_kernel_ms"] > 0 and t["merge_kernel_ms"] > 0 and t["plan_ms"] > 0
+    assert t["round_kernel_ms"] + t["merge_kernel_ms"] + t["plan_ms"] <= t["scan_ms"] * 1.01
