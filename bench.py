@@ -18,6 +18,7 @@ Prints one JSON line.
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import hashlib
 import json
 import os
@@ -472,6 +473,7 @@ def main():
     ap.add_argument("--workload", default="highd-1m-d960")
     ap.add_argument("--store", default=None)
     ap.add_argument("--target", type=float, default=0.95)
+    ap.add_argument("--k", type=int, default=None, help="K of every query (default: the workload's)")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
@@ -524,6 +526,8 @@ def main():
 
     from paper_2411_17229_amd import dade, workloads
     w = workloads.WORKLOADS[args.workload]
+    if args.k:
+        w = dataclasses.replace(w, k=args.k)
     store = args.store or w.store
     t0 = time.perf_counter()
     X, Q = workloads.make(w)
@@ -663,10 +667,10 @@ def main():
         "config": {"workload": w.name, "n": w.n, "dim": w.dim, "nlist": w.nlist, "k": w.k,
                    "queries_per_step": nq, "nprobe": d["nprobe"], "delta_d": w.delta_d, "p_s": d["p_s"],
                    "store": store, "schedule": SCHEDULE["schedule"], "fill_min": SCHEDULE["fill_min"],
-                   "growth": SCHEDULE["growth"], "recall@10": round(d["recall"], 4)},
+                   "growth": SCHEDULE["growth"], f"recall@{w.k}": round(d["recall"], 4)},
         "p50_ms": round(d["p50_ms"], 4), "p99_ms": round(d["p99_ms"], 4),
         "full_d": {"qps": round(res["full_d"]["qps"], 1), "nprobe": res["full_d"]["nprobe"],
-                   "recall@10": round(res["full_d"]["recall"], 4),
+                   f"recall@{w.k}": round(res["full_d"]["recall"], 4),
                    "ms_per_step": round(res["full_d"]["ms_per_step"], 4),
                    "p50_ms": round(res["full_d"]["p50_ms"], 4), "p99_ms": round(res["full_d"]["p99_ms"], 4)},
         "speedup_vs_full_d": round(d["qps"] / res["full_d"]["qps"], 3),
