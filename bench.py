@@ -356,7 +356,7 @@ def serving_sweep(dade, ix, Q, gt, k, ks, nprobes, n_req=2000, budget=512 << 20,
 
 
 GRAPH_EF = (16, 32, 64)
-GRAPH_ENTRY = (4, 16, 64)
+GRAPH_ENTRY = (2, 4, 16)
 
 
 def graph_study(dade, torch, target, steps, degree=16, reverse=8, nprobe_build=4):

@@ -330,28 +330,29 @@ int dade_autotune(dade_index* ix, const float* Q, int64_t nq, int32_t k, int32_t
  * degree nearest other rows by this index's FDScanning search (K = degree + 1 over `nprobe`
  * lists, ties by id, the row itself dropped), followed by up to `reverse` back links: rows that
  * list it and that it does not list, nearest first by (squared distance in FP64 over the FP32
- * vectors, row id); rows are degree + reverse (<= 64) wide, -1 padded.  Each list's entry point
- * is its medoid (the member nearest its centroid in FP32, ties to the lower id).  X: device
+ * vectors, row id); rows are degree + reverse (<= 64) wide, -1 padded.  Each list has two entry
+ * points: its medoid (the member nearest its centroid in FP32, ties to the lower id) and the
+ * member farthest from the medoid (ties to the lower id; -1 for a list of one).  X: device
  * [n x dim] FP32, the vectors the index was built from.  Replaces a previous graph.
  * Requires n <= 20000 (DADE_EINVAL above): larger builds are switched off while a GPU fault seen
  * in a 1M-row build is unexplained.  Synchronises `stream`.
  *
  * dade_graph_search -- per query, a beam of at most ef (1..64) (squared distance, id) entries:
- * seeded with the medoids of the query's n_entry (1..64) nearest lists at their full-D
+ * seeded with the entry points of the query's n_entry (1..32) nearest lists at their full-D
  * distance; each step expands the nearest unexpanded entry: its unvisited neighbours are
  * marked visited and each gets one DCO (Algorithm 1 at opts->delta_d, a multiple of 8, or
  * FDScanning in FULL_D mode) against the beam's ef-th entry as it was when the step began
  * (no test while the beam holds fewer than ef), kept as dade_search keeps candidates, and
  * merged in (the ef nearest stay).  The search ends when every beam entry is expanded or after
- * max_iters steps (0 means 2 ef; n_entry + max_iters x width must be <= 4096).  The beam
+ * max_iters steps (0 means 2 ef; 2 n_entry + max_iters x width must be <= 4096).  The beam
  * uses the stored coordinates; the final beam is reranked with the original FP32 vectors and
  * the k (<= ef) nearest by (squared distance, id) are returned as dade_search returns them.
  * opts: delta_d, mode and stats (device [nq x 4] int64: DCOs, dimensions read, steps, visited)
  * are used; NULL means DADE at Delta_d 32.  Q: device [nq x dim] FP32.  Asynchronous on `stream`.
  *
  * dade_graph_export -- the graph as row ids (host): *degree, the row width (degree + reverse);
- * neighbors [n x width] (row i's neighbours), entries [nlist] (-1 for an empty list); NULL
- * arrays are skipped.
+ * neighbors [n x width] (row i's neighbours), entries [nlist x 2] (-1 where a list has no
+ * such member); NULL arrays are skipped.
  */
 int dade_graph_build(dade_index* ix, const float* X, int32_t degree, int32_t reverse, int32_t nprobe,
                      void* stream);

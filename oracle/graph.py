@@ -8,8 +8,9 @@ discards a neighbour whose DCO answers no.  This oracle follows that search on a
   out-neighbours are its ``degree`` nearest other objects by the index's exact IVF search
   (FDScanning with K = degree + 1 over ``nprobe`` lists), ordered by (dist^2, id), the object
   itself removed, -1 padded; then up to ``reverse`` back links (``add_reverse_edges``).
-* Entry points (reading): each IVF list's medoid, the member nearest its centroid (ties to the
-  lower id); a query starts from the medoids of its ``n_entry`` nearest lists (probe order).
+* Entry points (reading): each IVF list's medoid (the member nearest its centroid, ties to the
+  lower id) and the member farthest from the medoid (``list_entries``); a query starts from the
+  entry points of its ``n_entry`` nearest lists (probe order).
 * Beam: a pool of at most ``ef`` (dist^2, id) entries, each marked expanded or not.  Seeds enter
   with their full-D distance.  Each step expands the first unexpanded entry of the pool in
   (dist^2, id) order: its unvisited neighbours are marked visited and each gets one DCO (Algorithm
@@ -69,6 +70,24 @@ def add_reverse_edges(neighbors, X, reverse: int) -> np.ndarray:
     return out
 
 
+def list_entries(index: ivf.Index, X) -> np.ndarray:
+    """[nlist x 2] row ids: each list's medoid, then the member farthest from the medoid (ties to
+    the lower id; -1 when the list has fewer than two members).  A two-point farthest-first cover
+    of the list (reading): a k-means list that spans two mixture components gets an entry in
+    each, and a kNN graph has no edges between components."""
+    X = np.asarray(X, dtype=np.float64)
+    med = list_medoids(index, X)
+    out = np.full((index.nlist, 2), -1, dtype=np.int64)
+    out[:, 0] = med
+    for l in range(index.nlist):
+        members = index.ids[index.offsets[l]:index.offsets[l + 1]]
+        if len(members) < 2:
+            continue
+        d2 = np.sum((X[members] - X[med[l]]) ** 2, axis=1)
+        out[l, 1] = members[np.lexsort((members, -d2))[0]]
+    return out
+
+
 def list_medoids(index: ivf.Index, X) -> np.ndarray:
     """[nlist] row id of each list's member nearest its centroid (ties: lower id), -1 if empty."""
     X = np.asarray(X, dtype=np.float64)
@@ -113,7 +132,8 @@ def search(index: ivf.Index, neighbors, entries, Q, K: int, ef: int, n_entry: in
             with np.errstate(divide="ignore", invalid="ignore"):
                 g = np.abs(np.diff(head)) / np.maximum(head[:-1], 1e-300)
             logs["probe_gap"][qi] = float(g.min())
-        seeds = np.array([entries[l] for l in lists if entries[l] >= 0], dtype=np.int64)
+        ent = np.asarray(entries).reshape(index.nlist, -1)   # one or two entry points per list
+        seeds = np.array([int(e) for l in lists for e in ent[l] if e >= 0], dtype=np.int64)
         visited = set(seeds.tolist())
         diff = index.Y[seeds] - q
         sd = np.sum(diff * diff, axis=1)

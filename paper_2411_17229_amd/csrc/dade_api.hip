@@ -104,7 +104,7 @@ struct dade_index {
   std::vector<unsigned char> graph_key;
   // kNN graph (dade_graph_build)
   int32_t* d_nbr = nullptr;    // [n x graph_degree] out-neighbour positions, by position
-  int32_t* d_entry = nullptr;  // [nlist] medoid position per list
+  int32_t* d_entry = nullptr;  // [nlist x 2] entry positions per list: medoid, farthest from it
   int graph_degree = 0;         // row width of a usable graph (0: none)
   int graph_width = 0;          // row width of d_nbr's allocation
   std::vector<int64_t> pos_h;   // row id -> packed position (host)
@@ -1005,7 +1005,7 @@ int dade_graph_build(dade_index* ix, const float* X, int32_t degree, int32_t rev
   }
   if (!ix->d_nbr && (rc = alloc_t(ix, &ix->d_nbr, size_t(n) * width))) return rc;
   ix->graph_width = width;
-  if (!ix->d_entry && (rc = alloc_t(ix, &ix->d_entry, size_t(ix->nlist)))) return rc;
+  if (!ix->d_entry && (rc = alloc_t(ix, &ix->d_entry, size_t(ix->nlist) * 2))) return rc;
   // forward lists first, at stride `width`, then the back links merged in on the host
   const int64_t chunk = std::min<int64_t>(n, 65536);
   int64_t* res = nullptr;
@@ -1100,9 +1100,9 @@ int dade_graph_export(const dade_index* ix, int32_t* degree, int64_t* neighbors,
     }
   }
   if (entries) {
-    std::vector<int32_t> en(size_t(ix->nlist));
+    std::vector<int32_t> en(size_t(ix->nlist) * 2);
     HIPC(hipMemcpy(en.data(), ix->d_entry, sizeof(int32_t) * en.size(), hipMemcpyDeviceToHost));
-    for (int l = 0; l < ix->nlist; ++l) entries[l] = en[size_t(l)] < 0 ? -1 : ix->ids_h[size_t(en[size_t(l)])];
+    for (size_t i = 0; i < en.size(); ++i) entries[i] = en[i] < 0 ? -1 : ix->ids_h[size_t(en[i])];
   }
   return DADE_OK;
 }
@@ -1115,7 +1115,7 @@ int dade_graph_search(dade_index* ix, const float* Q, int64_t nq, int32_t k, int
   if (nq < 0 || nq >= (int64_t(1) << 31)) FAIL(DADE_EINVAL, "nq must be in [0, 2^31)");
   if (ef < 1 || ef > kGraphMax) FAIL(DADE_EINVAL, "ef must be in [1, 64]");
   if (k < 1 || k > ef) FAIL(DADE_EINVAL, "k must be in [1, ef]");
-  if (n_entry < 1 || n_entry > kGraphMax) FAIL(DADE_EINVAL, "n_entry must be in [1, 64]");
+  if (n_entry < 1 || 2 * n_entry > kGraphMax) FAIL(DADE_EINVAL, "n_entry must be in [1, 32]");
   if (max_iters < 0) FAIL(DADE_EINVAL, "max_iters must be >= 0");
   dade_search_opts o{};
   o.mode = DADE_MODE_DADE;
@@ -1130,11 +1130,11 @@ int dade_graph_search(dade_index* ix, const float* Q, int64_t nq, int32_t k, int
   const int npm = std::min<int>(n_entry, ix->nlist);
   const int iters = max_iters > 0 ? max_iters : 2 * ef;
   // the visited table: at least twice the most insertions (seeds + iters x degree), <= 8192 slots
-  const int64_t most = int64_t(npm) + int64_t(iters) * deg;
+  const int64_t most = 2 * int64_t(npm) + int64_t(iters) * deg;
   int slots_log2 = 6;
   while ((int64_t(1) << slots_log2) < 2 * most) ++slots_log2;
   if (slots_log2 > 13)
-    FAIL(DADE_EINVAL, "graph search: n_entry + max_iters x degree must be <= 4096 (visited table of 8192 slots)");
+    FAIL(DADE_EINVAL, "graph search: 2 n_entry + max_iters x width must be <= 4096 (visited table of 8192 slots)");
   if (nq == 0) return DADE_OK;
   int rc;
   if ((rc = check_device_pointer(Q, "Q")) || (rc = check_device_pointer(out_ids, "out_ids")) ||

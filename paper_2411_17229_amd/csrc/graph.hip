@@ -120,14 +120,14 @@ __global__ __launch_bounds__(64) void graph_search_kernel(GraphArgs a) {
   const int ef = a.ef, deg = a.degree;
   long long n_dco = 0, n_dims = 0, n_vis = 0;
 
-  // seeds: the medoids of the query's n_entry nearest lists, full-D distances
+  // seeds: the entry points of the query's n_entry nearest lists, full-D distances
   unsigned long long pk = kEmpty;
   int pp = -1, pe = 1;
   unsigned long long nk = kEmpty;
   int np = -1;
-  if (lane < a.n_entry) {
-    const int l = a.probes[int64_t(q) * a.npm + lane];
-    const int p = a.entry[l];
+  if (lane < 2 * a.n_entry) {   // two entry points per list: lanes 2j and 2j + 1 take list j's
+    const int l = a.probes[int64_t(q) * a.npm + (lane >> 1)];
+    const int p = a.entry[2 * l + (lane & 1)];
     if (p >= 0 && visit(tab, mask, p)) {
       ++n_vis;
       float S;
@@ -245,39 +245,65 @@ __global__ void graph_collect_kernel(const int64_t* res, int cn, int64_t c0, int
   for (; w < degree; ++w) out[w] = -1;
 }
 
-// Each list's medoid: the member with the smallest (FP32 squared distance to the centroid, row
-// id), as a position; -1 for an empty list.  One workgroup per list.
+// Squared FP32 distance between two padded rows.
+__device__ inline float row_d2(const float* x, const float* y, int dp) {
+  float s = 0.f;
+  for (int k = 0; k < dp; k += 4) {
+    const float4 xv = *reinterpret_cast<const float4*>(x + k), yv = *reinterpret_cast<const float4*>(y + k);
+    float t = xv.x - yv.x; s = fmaf(t, t, s);
+    t = xv.y - yv.y; s = fmaf(t, t, s);
+    t = xv.z - yv.z; s = fmaf(t, t, s);
+    t = xv.w - yv.w; s = fmaf(t, t, s);
+  }
+  return s;
+}
+
+// The smallest key of the workgroup (256 threads), to every thread.
+__device__ inline unsigned long long block_min(unsigned long long v, unsigned long long* red) {
+  for (int o = 32; o > 0; o >>= 1) {
+    const unsigned long long u = __shfl_down(v, o);
+    v = u < v ? u : v;
+  }
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  v = red[0];
+  for (int w = 1; w < 4; ++w) v = red[w] < v ? red[w] : v;
+  __syncthreads();
+  return v;
+}
+
+// Each list's two entry points, as positions: its medoid (the member with the smallest (FP32
+// squared distance to the centroid, row id)), then the member farthest from the medoid (largest
+// distance, then smallest row id); -1 where the list has no such member.  One workgroup per list.
 __global__ __launch_bounds__(256) void graph_entry_kernel(const float* X, const float* cent, const int64_t* off,
                                                           const int32_t* ids, const int64_t* pos, int dp,
                                                           int32_t* entry) {
   __shared__ unsigned long long red[4];
   const int l = blockIdx.x;
-  const float* c = cent + int64_t(l) * dp;
   unsigned long long best = kEmpty;
   for (int64_t p = off[l] + threadIdx.x; p < off[l + 1]; p += blockDim.x) {
     const uint32_t rid = uint32_t(ids[p]);
-    const float* x = X + int64_t(rid) * dp;
-    float s = 0.f;
-    for (int k = 0; k < dp; k += 4) {
-      const float4 xv = *reinterpret_cast<const float4*>(x + k), cv = *reinterpret_cast<const float4*>(c + k);
-      float t = xv.x - cv.x; s = fmaf(t, t, s);
-      t = xv.y - cv.y; s = fmaf(t, t, s);
-      t = xv.z - cv.z; s = fmaf(t, t, s);
-      t = xv.w - cv.w; s = fmaf(t, t, s);
-    }
-    const unsigned long long k = make_key(s, rid);
+    const unsigned long long k = make_key(row_d2(X + int64_t(rid) * dp, cent + int64_t(l) * dp, dp), rid);
     best = k < best ? k : best;
   }
-  for (int o = 32; o > 0; o >>= 1) {
-    const unsigned long long v = __shfl_down(best, o);
-    best = v < best ? v : best;
+  best = block_min(best, red);
+  unsigned long long far = kEmpty;
+  if (best != kEmpty) {
+    const uint32_t mid = uint32_t(best);
+    const float* xm = X + int64_t(mid) * dp;
+    for (int64_t p = off[l] + threadIdx.x; p < off[l + 1]; p += blockDim.x) {
+      const uint32_t rid = uint32_t(ids[p]);
+      if (rid == mid) continue;
+      // largest distance first: the complement of the distance bits orders descending
+      const unsigned long long k =
+          (static_cast<unsigned long long>(~__float_as_uint(row_d2(X + int64_t(rid) * dp, xm, dp))) << 32) | rid;
+      far = k < far ? k : far;
+    }
   }
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = best;
-  __syncthreads();
+  far = block_min(far, red);
   if (threadIdx.x == 0) {
-    for (int w = 1; w < 4; ++w) best = red[w] < best ? red[w] : best;
-    best = red[0] < best ? red[0] : best;
-    entry[l] = best == kEmpty ? -1 : int32_t(pos[uint32_t(best)]);
+    entry[2 * l] = best == kEmpty ? -1 : int32_t(pos[uint32_t(best)]);
+    entry[2 * l + 1] = far == kEmpty ? -1 : int32_t(pos[uint32_t(far)]);
   }
 }
 

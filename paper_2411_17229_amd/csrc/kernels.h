@@ -151,14 +151,14 @@ constexpr int64_t kGraphBuildMaxRows = 20000;   // largest index dade_graph_buil
 struct GraphArgs {
   int nq = 0, dim = 0, dp = 0, delta_d = 0;   // delta_d % 8 == 0 in DADE mode
   int mode = 0, dtype = 0;                    // mode 0: DADE, 1: FDScanning
-  int K = 0, ef = 0, n_entry = 0, npm = 0;    // K <= ef <= 64, n_entry <= npm <= 64
+  int K = 0, ef = 0, n_entry = 0, npm = 0;    // K <= ef <= 64, n_entry = npm <= 32
   int degree = 0, max_iters = 0, slots_log2 = 0;
   const void* head = nullptr;       // packed store, as RoundArgs
   const void* tail = nullptr;
   const float* qrot = nullptr;      // [nq x dp]
   const float* qorig = nullptr;     // [nq x dp] original queries (final rerank)
   const int32_t* probes = nullptr;  // [nq x npm] list ids in probe order
-  const int32_t* entry = nullptr;   // [nlist] medoid position per list, -1 if empty
+  const int32_t* entry = nullptr;   // [nlist x 2] entry positions per list (medoid, farthest), -1 if none
   const int32_t* nbr = nullptr;     // [n x degree] out-neighbour positions, -1 padded
   const int32_t* ids = nullptr;     // packed position -> row id
   const float* X = nullptr;         // [n x dp] original vectors by row id

@@ -308,12 +308,12 @@ def dade_graph_search(ix: Index, Q, k, ef, n_entry=4, max_iters=0, delta_d=32, m
 
 
 def dade_graph_export(ix: Index):
-    """(neighbors [n, degree] int64 row ids, entries [nlist] int64 row ids) on the host."""
+    """(neighbors [n, width] int64 row ids, entries [nlist, 2] int64 row ids) on the host."""
     inf = dade_index_info(ix)
     deg = ctypes.c_int32()
     _check(lib().dade_graph_export(ix.handle, ctypes.byref(deg), None, None))
     nb = np.empty((inf["n"], deg.value), np.int64)
-    en = np.empty(inf["nlist"], np.int64)
+    en = np.empty((inf["nlist"], 2), np.int64)
     _check(lib().dade_graph_export(ix.handle, ctypes.byref(deg), ctypes.c_void_p(nb.ctypes.data),
                                    ctypes.c_void_p(en.ctypes.data)))
     return nb, en

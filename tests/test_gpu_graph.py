@@ -67,16 +67,20 @@ def test_graph_build_matches_oracle(f32):
         np.testing.assert_allclose(dg, dw, rtol=1e-12, err_msg=f"row {r}")
 
 
-def test_entry_points_are_list_medoids(f32):
+def test_entry_points_are_medoid_and_farthest_member(f32):
     X, oi, en = f32["X"], f32["oi"], f32["en"]
+    assert en.shape == (oi.nlist, 2)
     med = graph.list_medoids(oi, X)
     Xd = X.astype(np.float64)
     for l in range(oi.nlist):
         members = oi.ids[oi.offsets[l]:oi.offsets[l + 1]]
-        assert en[l] in members
-        d_g = np.sum((Xd[en[l]] - oi.centroids[l]) ** 2)
+        assert en[l, 0] in members and en[l, 1] in members and en[l, 0] != en[l, 1]
+        d_g = np.sum((Xd[en[l, 0]] - oi.centroids[l]) ** 2)
         d_o = np.sum((Xd[med[l]] - oi.centroids[l]) ** 2)
         assert abs(d_g - d_o) <= 1e-5 * d_o, l
+        # the second entry: the member farthest from the library's medoid
+        far = np.sum((Xd[members] - Xd[en[l, 0]]) ** 2, axis=1).max()
+        assert abs(np.sum((Xd[en[l, 1]] - Xd[en[l, 0]]) ** 2) - far) <= 1e-5 * far, l
 
 
 def run_parity(env, mode, K=10, ef=48, n_entry=4, max_iters=0, dd=32):
@@ -127,7 +131,7 @@ def test_graph_search_batch_invariance(f32):
 def test_graph_argument_errors(f32):
     gi, Qd = f32["gi"], f32["Qd"]
     for kw in (dict(k=10, ef=65), dict(k=20, ef=10), dict(k=10, ef=32, delta_d=12), dict(k=10, ef=32, n_entry=0),
-               dict(k=10, ef=64, max_iters=300)):
+               dict(k=10, ef=32, n_entry=33), dict(k=10, ef=64, max_iters=300)):
         k, ef = kw.pop("k"), kw.pop("ef")
         with pytest.raises(dade.DadeError):
             dade.dade_graph_search(gi, Qd, k, ef, **kw)

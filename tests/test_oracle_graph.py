@@ -132,3 +132,38 @@ def test_reverse_edges_link_back_nearest_first():
         assert back == want, v
     # every row that has an in-link can now be reached back from it
     assert sum((H >= 0).sum(1)) > sum((G >= 0).sum(1))
+
+
+def test_second_entry_is_the_member_farthest_from_the_medoid():
+    X, oi = small_index(seed=13)
+    E = graph.list_entries(oi, X)
+    med = graph.list_medoids(oi, X)
+    Xd = X.astype(np.float64)
+    for l in range(oi.nlist):
+        members = oi.ids[oi.offsets[l]:oi.offsets[l + 1]]
+        assert E[l, 0] == med[l]
+        if len(members) < 2:
+            assert E[l, 1] == -1
+            continue
+        far = max(members, key=lambda m: (np.sum((Xd[m] - Xd[med[l]]) ** 2), -m))
+        assert E[l, 1] == far and E[l, 1] != E[l, 0]
+
+
+def test_two_entries_per_list_reach_a_component_the_medoid_misses():
+    """Two well-separated blobs in one list: the medoid sits in the larger blob; a query beside
+    the smaller blob is only reached through the second entry point (a kNN graph has no edge
+    between the blobs)."""
+    rng = np.random.default_rng(3)
+    A = rng.normal(0, 1, (60, 8))
+    B = rng.normal(0, 1, (20, 8)) + 40.0
+    X = np.concatenate([A, B]).astype(np.float32)
+    pairs = np.stack([rng.integers(0, 80, 2000), rng.integers(0, 80, 2000)], 1)
+    pairs = pairs[pairs[:, 0] != pairs[:, 1]]
+    oi = ivf.build(X, 1, np.array([0]), pairs, p_s=0.1, iters=1)
+    G = graph.build_knn_graph(oi, X, degree=5, nprobe=1)
+    q = (B[:1] + 0.1).astype(np.float32)
+    gt, _ = knn.brute_force(X, q, 5)
+    one, _, _ = graph.search(oi, G, graph.list_medoids(oi, X), q, 5, ef=8, n_entry=1, delta_d=4, mode="full_d")
+    two, _, _ = graph.search(oi, G, graph.list_entries(oi, X), q, 5, ef=8, n_entry=1, delta_d=4, mode="full_d")
+    assert not set(one[0]) & set(gt[0])
+    assert set(two[0]) == set(gt[0])
