@@ -359,26 +359,37 @@ GRAPH_EF = (16, 32, 64)
 GRAPH_ENTRY = (2, 4, 16)
 
 
-def graph_study(dade, torch, target, steps, degree=16, reverse=8, nprobe_build=4):
-    """The graph setting (one-layer kNN graph, DADE DCOs in a beam search) on the 20k x 128
-    workload (graph builds are limited to 20,000 rows): build time, then per ef the recall@k, QPS
-    and dimensions read of DADE (P_s of the workload) and FDScanning; the headline pair is each
-    mode's fastest (entry lists, ef) reaching `target`."""
+def graph_study(dade, torch, target, steps, degree=16, reverse=8, nprobe_build=4, sample=None):
+    """The graph setting (one-layer kNN graph, DADE DCOs in a beam search), on rows of at most
+    20,000 (the graph build's limit): the 20k x 128 workload, or with `sample` = (workload, X, Q,
+    P_s) the first 20,000 rows of that workload (iid draws of its mixture) with nlist scaled to
+    keep its list size.  Build time, then per (entry lists, ef) the recall@k, QPS and dimensions
+    read of DADE and FDScanning; the headline pair is each mode's fastest setting reaching
+    `target`."""
+    import dataclasses as dc
+
     from paper_2411_17229_amd import workloads
-    w = workloads.WORKLOADS["small-20k-d128"]
-    X, Q = workloads.make(w, n_queries=1000)
+    if sample is None:
+        w = workloads.WORKLOADS["small-20k-d128"]
+        X, Q = workloads.make(w, n_queries=1000)
+        p_s = w.alpha
+    else:
+        w0, X0, Q, p_s = sample
+        n = 20_000
+        X = np.ascontiguousarray(X0[:n])
+        w = dc.replace(w0, name=f"{w0.name}-first{n}", n=n, nlist=max(1, round(w0.nlist * n / w0.n)))
     Xd, Qd = torch.from_numpy(X).cuda(), torch.from_numpy(Q).cuda()
     store = w.store
     ix = dade.dade_build_index(Xd, w.nlist, store=store, init_rows=workloads.kmeans_init_rows(w.n, w.nlist, w.seed))
     dade.dade_rotate(ix)
-    dade.dade_calibrate(ix, w.alpha, pairs=workloads.calibration_pairs(w.n, 100_000, w.seed))
+    dade.dade_calibrate(ix, p_s, pairs=workloads.calibration_pairs(w.n, 100_000, w.seed))
     gt = ground_truth(torch, Xd, Qd, w.k)
     t0 = time.perf_counter()
     dade.dade_graph_build(ix, Xd, degree=degree, reverse=reverse, nprobe=nprobe_build)
     build_s = time.perf_counter() - t0
     nq = Qd.shape[0]
     s_bytes = 2 if store in ("bf16", "f16") else 4
-    out = {"workload": w.name, "n": w.n, "dim": w.dim, "queries": len(Q), "p_s": w.alpha, "store": store,
+    out = {"workload": w.name, "n": w.n, "dim": w.dim, "nlist": w.nlist, "queries": len(Q), "p_s": p_s, "store": store,
            "degree": degree, "reverse": reverse, "nprobe_build": nprobe_build, "build_s": round(build_s, 2),
            "sweep": {}}
     log(f"[bench] graph: degree {degree} + {reverse} back links built in {build_s:.1f}s")
@@ -706,6 +717,8 @@ def main():
             f"{out['autotune']['recall@10']:.4f}")
     if not args.no_graph_study:
         out["graph"] = graph_study(dade, torch, args.target, max(3, args.steps // 4))
+        out["graph_highd_sample"] = graph_study(dade, torch, args.target, max(3, args.steps // 4),
+                                                sample=(w, X, Q, d["p_s"]))
     if not args.no_variants and store != "f32":
         # the same lists and transform with the other 16-bit store and with FP32 (recall vs FP32)
         art = dade.dade_export(ix)
