@@ -13,6 +13,11 @@ Each is timed at the fastest configuration reaching the target:
   * latency: `--steps` searches, each synchronised (p50 / p99);
   * kernel times: searches with HIP events around every kernel of the scan (launched without the
     graph), for the roofline of the DCO kernel.
+Beside the metric (each leg can be skipped with its --no-* flag): the FP16 and FP32 stores on the
+same lists, the data-oblivious transform, the linear scan, the serving loop under Poisson load
+(p50 / p99 per request), an autotuner run, the graph search, and the CPU oracle baseline.
+Other modes: --serving-only (a workload's request mix), --uneven-only (per-query K and nprobe in
+one launch), --profile-only (timed steps only, for profilers).
 Prints one JSON line.
 """
 from __future__ import annotations
