@@ -174,7 +174,8 @@ __global__ __launch_bounds__(64) void graph_search_kernel(GraphArgs a) {
         }
       }
     }
-    merge_pool(pk, pp, pe, nk, np, ef, mk, mp, me, lane);
+    // nothing kept: the pool stays as it is (the expanded flag is already in its lane)
+    if (__ballot(nk != kEmpty) != 0) merge_pool(pk, pp, pe, nk, np, ef, mk, mp, me, lane);
   }
 
   // the final pool, reranked with the exact vectors; the K smallest by (exact dist^2, id)
