@@ -79,24 +79,33 @@ __device__ inline unsigned long long make_key(float d2, uint32_t id) {
   return (static_cast<unsigned long long>(__float_as_uint(d2)) << 32) | id;
 }
 
-// The pool (lane i: key, position, expanded flag) merged with one new key per lane: the ef
-// smallest of the 128 keys, in order, in lanes 0..ef-1 (kEmpty beyond).  Ranks are unique (ties
-// by slot), so every slot below ef is written exactly once.
+// The pool (lane i: key, position, expanded flag; sorted ascending in lanes 0..n_pool-1, kEmpty
+// beyond) merged with one new key per lane (kEmpty: none): the ef smallest, in order, in lanes
+// 0..ef-1 (kEmpty beyond).  Keys are unique (distinct row ids: a new key's row was unvisited), so
+// a pool entry's rank is its lane plus the new keys below it, and a new key's rank counts the
+// pool entries and new keys below it; every slot below min(ef, total) is written exactly once
+// and the slots from there to ef are cleared.
 __device__ inline void merge_pool(unsigned long long& pk, int& pp, int& pe, unsigned long long nk, int np, int ef,
                                   unsigned long long* mk, int* mp, int* me, int lane) {
-  mk[lane] = pk; mk[64 + lane] = nk;
-  mp[lane] = pp; mp[64 + lane] = np;
-  me[lane] = pe; me[64 + lane] = 0;
+  const unsigned long long mnew = __ballot(nk != kEmpty);
+  const int n_new = __popcll(mnew);
+  const int n_pool = __popcll(__ballot(pk != kEmpty));
+  const int slot = int(__builtin_amdgcn_mbcnt_hi(uint32_t(mnew >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(mnew), 0u)));
+  mk[lane] = pk; mp[lane] = pp; me[lane] = pe;
+  if (nk != kEmpty) { mk[64 + slot] = nk; mp[64 + slot] = np; }
   __syncthreads();
-  int r0 = 0, r1 = 0;
-  for (int f = 0; f < 128; ++f) {
-    const unsigned long long kf = mk[f];
-    r0 += (kf < pk || (kf == pk && f < lane)) ? 1 : 0;
-    r1 += (kf < nk || (kf == nk && f < 64 + lane)) ? 1 : 0;
+  int r0 = lane, r1 = 0;
+  for (int j = 0; j < n_new; ++j) {
+    const unsigned long long kj = mk[64 + j];
+    r0 += kj < pk ? 1 : 0;
+    r1 += kj < nk ? 1 : 0;
   }
+  for (int f = 0; f < n_pool; ++f) r1 += mk[f] < nk ? 1 : 0;
   __syncthreads();
-  if (r0 < ef) { mk[r0] = pk; mp[r0] = pp; me[r0] = pe; }
-  if (r1 < ef) { mk[r1] = nk; mp[r1] = np; me[r1] = 0; }
+  const int total = n_pool + n_new;
+  if (pk != kEmpty && r0 < ef) { mk[r0] = pk; mp[r0] = pp; me[r0] = pe; }
+  if (nk != kEmpty && r1 < ef) { mk[r1] = nk; mp[r1] = np; me[r1] = 0; }
+  if (lane >= total && lane < ef) { mk[lane] = kEmpty; mp[lane] = -1; me[lane] = 1; }
   __syncthreads();
   pk = lane < ef ? mk[lane] : kEmpty;
   pp = lane < ef ? mp[lane] : -1;
