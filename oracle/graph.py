@@ -102,12 +102,15 @@ def list_medoids(index: ivf.Index, X) -> np.ndarray:
 
 
 def search(index: ivf.Index, neighbors, entries, Q, K: int, ef: int, n_entry: int, delta_d: int,
-           mode: str = "dade", max_iters: int = 0, log: bool = False):
+           mode: str = "dade", max_iters: int = 0, log: bool = False, flips=None, event_tol: float = 1e-3):
     """Beam search per query.  Returns (ids [nq, K] int64 -1 padded, dist2 [nq, K] +inf padded,
     logs) with logs per query: dcos, dims (sum of exit d), expansions, visited (count and, in
     visited_ids, the ids), min_margin (the smallest relative margin of any test, keep compare or
-    merge boundary) and probe_gap (the smallest relative gap between consecutive centroid
-    distances up to the first list past the entry lists)."""
+    merge boundary), probe_gap (the smallest relative gap between consecutive centroid
+    distances up to the first list past the entry lists) and events (decisions within
+    ``event_tol``, keyed as in ``ivf.search``: the seeds' merge is round 0, expansion s is round
+    s, the final cut is round -1).  ``flips`` maps a query index to decision keys taken the
+    other way."""
     Q = np.asarray(Q)
     nq = len(Q)
     max_iters = max_iters or 2 * ef
@@ -123,21 +126,32 @@ def search(index: ivf.Index, neighbors, entries, Q, K: int, ef: int, n_entry: in
     logs["min_margin"] = np.full(nq, np.inf)
     logs["probe_gap"] = np.full(nq, np.inf)
     logs["visited_ids"] = []
+    logs["events"] = [[] for _ in range(nq)]
+    flips = flips or {}
     for qi in range(nq):
         q = Qr[qi]
+        fq = flips.get(qi, ())
+        ev = logs["events"][qi]
         ne = min(n_entry, index.nlist)
-        lists, cd = ivf.probe_order(q, cent, ne)
+        order, cd = ivf.probe_order(q, cent, index.nlist)
+        order = order.copy()
         head = cd[:ne + 1]   # the entry lists and the next one: a near tie can swap an entry list
         if len(head) > 1:
             with np.errstate(divide="ignore", invalid="ignore"):
-                g = np.abs(np.diff(head)) / np.maximum(head[:-1], 1e-300)
+                g = np.abs(np.diff(head)) / np.maximum(head[1:], 1e-300)
             logs["probe_gap"][qi] = float(g.min())
+            for t, rel in enumerate(g):
+                ivf._note(ev, event_tol, rel, ("probe", t))
+        for k in fq:
+            if k[0] == "probe":
+                order[k[1]], order[k[1] + 1] = order[k[1] + 1], order[k[1]]
+        lists = order[:ne]
         ent = np.asarray(entries).reshape(index.nlist, -1)   # one or two entry points per list
         seeds = np.array([int(e) for l in lists for e in ent[l] if e >= 0], dtype=np.int64)
         visited = set(seeds.tolist())
         diff = index.Y[seeds] - q
         sd = np.sum(diff * diff, axis=1)
-        hd, hi, gap = ivf._merge(np.zeros(0), np.zeros(0, dtype=np.int64), sd, seeds, ef)
+        hd, hi, gap = ivf._merge(np.zeros(0), np.zeros(0, dtype=np.int64), sd, seeds, ef, 0, fq, ev, event_tol)
         margin = gap
         expanded = set()
         it = 0
@@ -152,10 +166,11 @@ def search(index: ivf.Index, neighbors, entries, Q, K: int, ef: int, n_entry: in
             if len(cand) == 0:
                 continue
             visited.update(cand.tolist())
-            d2, ids, exit_d, m, _ = ivf._scan_round(beam, q, cand, hd, hi, ef, delta_d, mode, tests)
+            d2, ids, exit_d, m, _ = ivf._scan_round(beam, q, cand, hd, hi, ef, delta_d, mode, tests,
+                                                    rnd=it, flips=fq, events=ev, tol=event_tol)
             logs["dcos"][qi] += len(cand)
             logs["dims"][qi] += exit_d.sum()
-            hd, hi, gap = ivf._merge(hd, hi, d2, ids, ef)
+            hd, hi, gap = ivf._merge(hd, hi, d2, ids, ef, it, fq, ev, event_tol)
             margin = min(margin, m, gap)
         logs["expansions"][qi] = it
         logs["visited"][qi] = len(visited)
@@ -165,8 +180,15 @@ def search(index: ivf.Index, neighbors, entries, Q, K: int, ef: int, n_entry: in
         ex = np.sum(de * de, axis=1)
         o = np.lexsort((hi, ex))
         if len(o) > K and ex[o[K - 1]] > 0:
-            margin = min(margin, abs(ex[o[K]] - ex[o[K - 1]]) / ex[o[K - 1]])
+            rel = abs(ex[o[K]] - ex[o[K - 1]]) / ex[o[K - 1]]
+            margin = min(margin, rel)
+            key = ("cut", -1, int(hi[o[K - 1]]), int(hi[o[K]]))
+            ivf._note(ev, event_tol, rel, key)
+            if key in fq:
+                o = o.copy()
+                o[K - 1], o[K] = o[K], o[K - 1]
         o = o[:K]
+        ev.sort(key=lambda e: e[0])
         out_i[qi, :len(o)] = hi[o]
         out_d[qi, :len(o)] = ex[o]
         logs["min_margin"][qi] = margin

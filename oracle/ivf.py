@@ -27,10 +27,16 @@ Readings where the paper is silent (each is a parameter or stated rule here):
   describes.
 
 Low-precision index (not in the paper): tests use the stored coordinates; a survivor whose
-stored-precision S_D exceeds (1 + delta) r^2 is dropped; of the rest, the K smallest are
-reranked with the exact coordinates, and the others only if their stored-precision S_D is
-within (1 + delta) of the K-th exact distance known at that point (see ``_rerank``); the keep
-rule above then applies to the exact distances.
+stored-precision S_D exceeds (1 + delta) r^2 is dropped (the gate).  Two rules then give the
+survivors their exact distances: ``rerank="all"`` reranks every survivor that passed the gate
+(the plain rule, the default); ``rerank="lazy"`` reranks the K smallest and the others only if
+their stored-precision S_D is within (1 + delta) of the K-th exact distance known at that point
+(``_rerank_lazy``).  The keep rule above then applies to the exact distances.
+
+Near ties (for comparisons with a search computed in lower precision): with ``log=True`` every
+decision whose relative margin is small -- a test, a gate, a keep compare, the cut between the
+K-th and (K+1)-th key, a gap in the probe order -- is logged with a key naming it, and ``flips``
+re-runs a query with chosen decisions taken the other way.
 """
 from __future__ import annotations
 
@@ -220,61 +226,136 @@ def tested_dims(D: int, delta_d: int) -> np.ndarray:
     return np.arange(delta_d, D, delta_d, dtype=np.int64)
 
 
-def _merge(hd, hi, d2, ids, K):
+def _flipped(flips, kind, rnd):
+    """Keys of the decisions of one kind in round ``rnd`` that a re-run takes the other way."""
+    return [k for k in flips if k[0] == kind and k[1] == rnd]
+
+
+def _note(events, tol, rel, key):
+    """Record a decision whose relative margin is at most ``tol`` (a near tie)."""
+    if events is not None and rel <= tol:
+        events.append((float(rel), key))
+
+
+def _merge(hd, hi, d2, ids, K, rnd=0, flips=(), events=None, tol=0.0):
+    """The K smallest (dist^2, id) of the heap and the round's kept candidates.
+
+    The decision at the cut (which of the K-th and (K+1)-th keys stays) is a near tie when
+    their distances differ by little; ``("cut", round, id_K, id_K+1)`` in ``flips`` keeps the
+    (K+1)-th instead.  Returns (dist^2, ids, relative gap at the cut).
+    """
     d = np.concatenate([hd, d2])
     i = np.concatenate([hi, ids])
     o = np.lexsort((i, d))
     gap = math.inf
-    if len(o) > K and d[o[K - 1]] > 0:
-        gap = abs(d[o[K]] - d[o[K - 1]]) / d[o[K - 1]]
+    if len(o) > K:
+        key = ("cut", rnd, int(i[o[K - 1]]), int(i[o[K]]))
+        if d[o[K - 1]] > 0:
+            gap = abs(d[o[K]] - d[o[K - 1]]) / d[o[K - 1]]
+        elif d[o[K]] == 0:
+            gap = 0.0
+        _note(events, tol, gap, key)
+        if key in flips:
+            o = o.copy()
+            o[K - 1], o[K] = o[K], o[K - 1]
     return d[o[:K]], i[o[:K]], gap
 
 
-def _rerank(index, q, cand, SD, alive, full, r2, hd, hi, K):
-    """Low-precision rerank of one round's survivors (the rule both sides implement).
+def _gate(index, cand, SD, alive, full, r2, rnd, flips, events, tol):
+    """The low-precision gate: a survivor goes on to the exact rerank when the heap is not
+    full or its stored-precision S_D <= (1 + delta) r^2.  Returns (mask, smallest margin)."""
+    A = alive.copy()
+    margin = math.inf
+    if full:
+        gate = (1.0 + index.delta) * r2
+        ok = SD <= gate
+        for k in _flipped(flips, "gate", rnd):
+            ok[cand == k[2]] = ~ok[cand == k[2]]
+        for j in np.nonzero(alive)[0]:
+            rel = abs(SD[j] - gate) / gate if gate > 0 else math.inf
+            margin = min(margin, rel)
+            _note(events, tol, rel, ("gate", rnd, int(cand[j])))
+        A &= ok
+    return A, margin
 
-    A = survivors with stored-precision S_D <= (1 + delta) r^2 (every survivor while the heap
-    is not full).  F = the K smallest of A by (S_D, id); they are reranked with the exact
-    coordinates.  b = the K-th smallest exact distance of the heap and F (+inf if fewer than
-    K); the rest of A is reranked only where S_D <= (1 + delta) b.  Returns the reranked mask,
-    the distances to keep-test (exact where reranked) and the smallest relative margin of the
-    gates.
+
+def _exact(index, q, cand, mask, SD):
+    """Stored-precision S_D replaced by the exact squared distance where ``mask`` is set."""
+    exact = SD.copy()
+    if mask.any():
+        dx = index.Y_exact[cand[mask]] - q
+        exact[mask] = np.sum(dx * dx, axis=1)
+    return exact
+
+
+def _rerank_all(index, q, cand, SD, alive, full, r2, rnd=0, flips=(), events=None, tol=0.0):
+    """Low-precision rerank, plain rule: every survivor that passes the gate gets its exact
+    squared distance.  Returns the reranked mask, the distances to keep-test and the smallest
+    relative margin of the gates."""
+    A, margin = _gate(index, cand, SD, alive, full, r2, rnd, flips, events, tol)
+    return A, _exact(index, q, cand, A, SD), margin
+
+
+def _rerank_lazy(index, q, cand, SD, alive, full, r2, hd, hi, K, rnd=0, flips=(), events=None, tol=0.0):
+    """Low-precision rerank, lazy rule (fewer exact distances than the plain rule).
+
+    A = survivors that pass the gate.  F = the K smallest of A by (S_D, id); they are reranked
+    exactly.  b = the K-th smallest exact distance of the heap and F (+inf if fewer than K);
+    the rest of A is reranked only where S_D <= (1 + delta) b.  When no candidate it skips has
+    a stored-precision error above delta, the round keeps what the plain rule keeps (a
+    skipped candidate's exact distance then exceeds b, which bounds the round's K-th).
+    Decision keys for re-runs: ``("gate", round, id)``, ``("fsel", round, id_K, id_K+1)`` (the
+    cut between F and the rest) and ``("bound", round, id)``.
     """
     delta = index.delta
-    margin = math.inf
-    A = alive.copy()
-    if full:
-        gate = (1.0 + delta) * r2
-        if alive.any():
-            margin = min(margin, float(np.min(np.abs(SD[alive] - gate) / gate)))
-        A &= SD <= gate
+    A, margin = _gate(index, cand, SD, alive, full, r2, rnd, flips, events, tol)
     ia = np.nonzero(A)[0]
     o = ia[np.lexsort((cand[ia], SD[ia]))]
+    if len(o) > K:
+        key = ("fsel", rnd, int(cand[o[K - 1]]), int(cand[o[K]]))
+        if SD[o[K - 1]] > 0:
+            rel = abs(SD[o[K]] - SD[o[K - 1]]) / SD[o[K - 1]]
+            margin = min(margin, rel)
+            _note(events, tol, rel, key)
+        if key in flips:
+            o = o.copy()
+            o[K - 1], o[K] = o[K], o[K - 1]
     F, rest = o[:K], o[K:]
-    if len(rest) and SD[F[-1]] > 0:
-        margin = min(margin, abs(SD[rest[0]] - SD[F[-1]]) / SD[F[-1]])
-    exact = SD.copy()
-    dF = index.Y_exact[cand[F]] - q
-    exact[F] = np.sum(dF * dF, axis=1)
+    mF = np.zeros_like(alive)
+    mF[F] = True
+    exact = _exact(index, q, cand, mF, SD)
     pool_d = np.concatenate([hd, exact[F]])
     pool_i = np.concatenate([hi, cand[F]])
     b = math.inf
     if len(pool_d) >= K:
         b = float(pool_d[np.lexsort((pool_i, pool_d))[K - 1]])
     bound = (1.0 + delta) * b
-    if len(rest) and math.isfinite(bound) and bound > 0:
-        margin = min(margin, float(np.min(np.abs(SD[rest] - bound) / bound)))
-    rest = rest[SD[rest] <= bound]
-    dR = index.Y_exact[cand[rest]] - q
-    exact[rest] = np.sum(dR * dR, axis=1)
-    R = np.zeros_like(alive)
-    R[F] = True
-    R[rest] = True
-    return R, exact, margin
+    inside = SD[rest] <= bound
+    for k in _flipped(flips, "bound", rnd):
+        inside[cand[rest] == k[2]] = ~inside[cand[rest] == k[2]]
+    if math.isfinite(bound) and bound > 0:
+        for j in rest:
+            rel = abs(SD[j] - bound) / bound
+            margin = min(margin, rel)
+            _note(events, tol, rel, ("bound", rnd, int(cand[j])))
+    R = mF.copy()
+    R[rest[inside]] = True
+    return R, _exact(index, q, cand, R, exact), margin
 
 
-def _scan_round(index, q, cand, hd, hi, K, delta_d, mode, tests):
-    """DCOs of one round against the snapshot heap (hd, hi).  Returns accepted + logs."""
+# Low-precision rerank rules (the paper has no low-precision store; see the module header).
+RERANK_RULES = ("all", "lazy")
+
+
+def _scan_round(index, q, cand, hd, hi, K, delta_d, mode, tests, rerank="all", rnd=0, flips=(),
+                events=None, tol=0.0):
+    """DCOs of one round against the snapshot heap (hd, hi).  Returns accepted + logs.
+
+    ``flips`` holds decision keys to take the other way (a re-run that explains a result
+    computed in lower precision): ``("test", round, id, d)`` for the test of candidate ``id``
+    at dimension d, ``("keep", round, id)`` for its keep compare, and the rerank keys.
+    Decisions within relative margin ``tol`` are appended to ``events`` as (margin, key).
+    """
     D = index.dim
     full = len(hd) == K
     r2 = float(hd[-1]) if full else math.inf
@@ -290,6 +371,10 @@ def _scan_round(index, q, cand, hd, hi, K, delta_d, mode, tests):
         c = estimator.scale(index.lam)
         est = estimator.estimate(S[:, tests - 1], c[tests - 1][None, :])
         rej = estimator.reject(est, index.eps[tests - 1][None, :], r)
+        for k in _flipped(flips, "test", rnd):
+            rows, cols = np.nonzero(cand == k[2])[0], np.nonzero(tests == k[3])[0]
+            for i in rows:
+                rej[i, cols] = ~rej[i, cols]
         anyrej = rej.any(axis=1)
         first = np.where(anyrej, rej.argmax(axis=1), len(tests) - 1)
         exit_d = np.where(anyrej, tests[first], D)
@@ -301,14 +386,28 @@ def _scan_round(index, q, cand, hd, hi, K, delta_d, mode, tests):
         rel = np.where(seen & np.isfinite(rel), rel, math.inf)
         if rel.size:
             margin = min(margin, float(rel.min()))
+        if events is not None:
+            for i, j in zip(*np.nonzero(rel <= tol)):
+                events.append((float(rel[i, j]), ("test", rnd, int(cand[i]), int(tests[j]))))
     SD = S[:, -1]
     if index.Y_exact is not None:
-        alive, SD, m2 = _rerank(index, q, cand, SD, alive, full, r2, hd, hi, K)
+        if rerank == "all":
+            alive, SD, m2 = _rerank_all(index, q, cand, SD, alive, full, r2, rnd, flips, events, tol)
+        elif rerank == "lazy":
+            alive, SD, m2 = _rerank_lazy(index, q, cand, SD, alive, full, r2, hd, hi, K, rnd, flips, events, tol)
+        else:
+            raise ValueError(rerank)
         margin = min(margin, m2)
     if full:
-        keep = alive & ((SD < r2) | ((SD == r2) & (cand < idr)))
-        if alive.any() and r2 > 0:
-            margin = min(margin, float(np.min(np.abs(SD[alive] - r2) / r2)))
+        below = (SD < r2) | ((SD == r2) & (cand < idr))
+        for k in _flipped(flips, "keep", rnd):
+            below[cand == k[2]] = ~below[cand == k[2]]
+        keep = alive & below
+        if r2 > 0:
+            for j in np.nonzero(alive)[0]:
+                rel = abs(SD[j] - r2) / r2
+                margin = min(margin, rel)
+                _note(events, tol, rel, ("keep", rnd, int(cand[j])))
     else:
         keep = alive
     return SD[keep], cand[keep], exit_d, margin, int(alive.sum())
@@ -316,17 +415,22 @@ def _scan_round(index, q, cand, hd, hi, K, delta_d, mode, tests):
 
 def search(index: Index, Q, K, nprobe, delta_d: int, mode: str = "dade",
            schedule: str = "per_rank", log: bool = False, q_rot=None,
-           fill_min: int = FILL_MIN, growth: int = GROWTH):
+           fill_min: int = FILL_MIN, growth: int = GROWTH, rerank: str = "all", flips=None,
+           event_tol: float = 1e-3):
     """IVF search.  K and nprobe are ints or per-query arrays; rounds follow ``round_starts``.
 
     Returns (ids [nq, Kmax] int64 with -1 padding, dist2 [nq, Kmax] with +inf padding, logs).
     ``logs`` (when requested) holds per-query: dcos, dims (sum of d_exit), accepted,
     survivors (reached d = D), rounds, min_margin (smallest relative margin of any test,
-    rerank gate, keep compare or top-K boundary) and probe_gap (smallest relative gap
-    between consecutive probed centroid distances).
+    rerank gate, keep compare or top-K cut), probe_gap (smallest relative gap between
+    consecutive probe-order distances, up to the first list not probed) and ``events``: a list
+    per query of (relative margin, decision key) for every decision within ``event_tol``.
+    ``rerank`` picks the low-precision rerank rule ("all" or "lazy"); ``flips`` maps a query
+    index to decision keys taken the other way (``("probe", t)`` swaps probe ranks t, t+1).
     """
     Q = np.asarray(Q)
     nq = Q.shape[0]
+    flips = flips or {}
     Ks = np.broadcast_to(np.asarray(K, dtype=np.int64), (nq,))
     nps = np.minimum(np.broadcast_to(np.asarray(nprobe, dtype=np.int64), (nq,)), index.nlist)
     Kmax = int(Ks.max()) if nq else 0
@@ -338,15 +442,25 @@ def search(index: Index, Q, K, nprobe, delta_d: int, mode: str = "dade",
     out_d = np.full((nq, Kmax), np.inf)
     logs = {k: np.zeros(nq, dtype=np.float64) for k in
             ("dcos", "dims", "accepted", "survivors", "rounds", "min_margin", "probe_gap")}
+    logs["events"] = [[] for _ in range(nq)]
     for qi in range(nq):
         q = Qr[qi]
+        fq = flips.get(qi, ())
+        ev = logs["events"][qi]
         Kq, npq = int(Ks[qi]), int(nps[qi])
-        probes, d2c = probe_order(q, cent, npq)
-        gaps = np.diff(d2c[:min(npq + 1, len(d2c))])
-        den = d2c[1:min(npq + 1, len(d2c))]
-        with np.errstate(divide="ignore", invalid="ignore"):
-            rg = np.where(den > 0, gaps / den, math.inf)
-        logs["probe_gap"][qi] = float(rg.min()) if rg.size else math.inf
+        order, d2c = probe_order(q, cent, index.nlist)
+        order = order.copy()
+        pg = math.inf
+        for t in range(min(npq, index.nlist - 1)):   # gaps up to the first list not probed
+            a, b = d2c[t], d2c[t + 1]
+            rel = (b - a) / b if b > 0 else math.inf
+            pg = min(pg, rel)
+            _note(ev, event_tol, rel, ("probe", t))
+        for k in fq:
+            if k[0] == "probe":
+                order[k[1]], order[k[1] + 1] = order[k[1] + 1], order[k[1]]
+        logs["probe_gap"][qi] = pg
+        probes = order[:npq]
         lists = [index.ids[index.offsets[l]:index.offsets[l + 1]] for l in probes]
         seq = np.concatenate(lists) if lists else np.zeros(0, np.int64)
         if schedule == "sequential":
@@ -357,19 +471,21 @@ def search(index: Index, Q, K, nprobe, delta_d: int, mode: str = "dade",
         hd = np.zeros(0)
         hi = np.zeros(0, dtype=np.int64)
         mm = math.inf
-        for cand in rounds:
+        for ri, cand in enumerate(rounds):
             logs["rounds"][qi] += 1
             if len(cand) == 0:
                 continue
-            d2, ids, exit_d, margin, surv = _scan_round(index, q, cand, hd, hi, Kq, delta_d, mode, tests)
+            d2, ids, exit_d, margin, surv = _scan_round(index, q, cand, hd, hi, Kq, delta_d, mode, tests,
+                                                        rerank, ri, fq, ev, event_tol)
             logs["dcos"][qi] += len(cand)
             logs["dims"][qi] += float(exit_d.sum())
             logs["accepted"][qi] += len(ids)
             logs["survivors"][qi] += surv
             mm = min(mm, margin)
-            hd, hi, gap = _merge(hd, hi, d2, ids, Kq)
+            hd, hi, gap = _merge(hd, hi, d2, ids, Kq, ri, fq, ev, event_tol)
             mm = min(mm, gap)
         logs["min_margin"][qi] = mm
+        ev.sort(key=lambda e: e[0])
         out_i[qi, :len(hi)] = hi
         out_d[qi, :len(hd)] = hd
     return (out_i, out_d, logs) if log else (out_i, out_d)

@@ -235,8 +235,9 @@ def test_keep_rule_breaks_distance_ties_by_id():
     assert ids[0, 0] == 0 and logs["accepted"][0] == 3
 
 
+@pytest.mark.parametrize("rerank", ["all", "lazy"])
 @pytest.mark.parametrize("delta", [0.0, 0.01, 1e9])
-def test_rerank_rule_with_exact_store_changes_nothing(setup, delta):
+def test_rerank_rule_with_exact_store_changes_nothing(setup, delta, rerank):
     """With stored coordinates equal to the exact ones, the rerank rule (K smallest reranked,
     the rest only within (1 + delta) of the K-th exact distance) keeps exactly the results of
     the plain index for any delta >= 0: a candidate it skips is farther than the final K-th."""
@@ -245,7 +246,7 @@ def test_rerank_rule_with_exact_store_changes_nothing(setup, delta):
     lp = dataclasses.replace(index, Y_exact=index.Y, delta=delta)
     for schedule in ("per_rank", "doubling"):
         a_i, a_d = ivf.search(index, Q, 10, 6, 8, schedule=schedule)
-        b_i, b_d = ivf.search(lp, Q, 10, 6, 8, schedule=schedule)
+        b_i, b_d = ivf.search(lp, Q, 10, 6, 8, schedule=schedule, rerank=rerank)
         assert np.array_equal(a_i, b_i)
         np.testing.assert_allclose(a_d, b_d, rtol=1e-12)
 
@@ -263,9 +264,13 @@ def test_rerank_rule_reranks_few_when_heap_empty(setup):
             calls.append(len(np.atleast_1d(rows)))
             return orig[rows]
     idx.Y_exact = Counting()
-    ivf.search(idx, Q[:1], 10, 1, 8)
+    ivf.search(idx, Q[:1], 10, 1, 8, rerank="lazy")
     list_len = max(np.diff(idx.offsets))
     assert 10 <= sum(calls) < list_len
+    # the plain rule reranks every survivor of the round (the heap is empty: all of them)
+    calls.clear()
+    ivf.search(idx, Q[:1], 10, 1, 8, rerank="all", fill_min=0, growth=0)
+    assert sum(calls) >= 10 and calls[0] == 10
 
 
 def _two_list_index(stored, exact, n0, delta=0.1):
@@ -276,9 +281,10 @@ def _two_list_index(stored, exact, n0, delta=0.1):
                      Ys, Y_exact=Ye, delta=delta)
 
 
-def _search2(index, nprobe):
+def _search2(index, nprobe, rerank="lazy"):
     """K = 2, first round = the first K candidates, then one round per list."""
-    ids, d2 = ivf.search(index, np.zeros((1, 2)), 2, nprobe, 1, mode="exact", fill_min=0, growth=0)
+    ids, d2 = ivf.search(index, np.zeros((1, 2)), 2, nprobe, 1, mode="exact", fill_min=0, growth=0,
+                         rerank=rerank)
     return list(ids[0]), d2[0]
 
 
@@ -296,6 +302,8 @@ def test_rerank_rule_hand_worked_f_is_k_smallest():
     ids, d2 = _search2(index, 2)
     assert ids == [0, 4]
     np.testing.assert_allclose(d2, [1.0, 1.04], rtol=1e-12)
+    # plain rule: every gated survivor reranked (1.09, 1.04, 1.565); the keep rule drops 1.565
+    assert _search2(index, 2, "all")[0] == [0, 4]
 
 
 def test_rerank_rule_hand_worked_rest_within_bound():
@@ -308,6 +316,7 @@ def test_rerank_rule_hand_worked_rest_within_bound():
     ids, d2 = _search2(index, 2)
     assert ids == [0, 5]
     np.testing.assert_allclose(d2, [1.0, 1.21], rtol=1e-12)
+    assert _search2(index, 2, "all")[0] == [0, 5]
 
 
 def test_rerank_rule_hand_worked_bound_uses_heap():
@@ -321,3 +330,8 @@ def test_rerank_rule_hand_worked_bound_uses_heap():
     ids, d2 = _search2(index, 2)
     assert ids == [0, 2]
     np.testing.assert_allclose(d2, [1.0, 1.0201], rtol=1e-12)
+    # the plain rule reranks id4 too (exact 1.010025 < 1.0201): the two rules differ here because
+    # id4's stored-precision error (1.134225 / 1.010025 - 1 = 0.123) exceeds delta = 0.1
+    ids, d2 = _search2(index, 2, "all")
+    assert ids == [0, 4]
+    np.testing.assert_allclose(d2, [1.0, 1.010025], rtol=1e-12)
