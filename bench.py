@@ -390,7 +390,7 @@ def graph_study(dade, torch, target, steps, degree=16, reverse=8, nprobe_build=4
     dade.dade_calibrate(ix, p_s, pairs=workloads.calibration_pairs(w.n, 100_000, w.seed))
     gt = ground_truth(torch, Xd, Qd, w.k)
     t0 = time.perf_counter()
-    dade.dade_graph_build(ix, Xd, degree=degree, reverse=reverse, nprobe=nprobe_build)
+    dade.dade_graph_build(ix, degree=degree, reverse=reverse, nprobe=nprobe_build)
     build_s = time.perf_counter() - t0
     nq = Qd.shape[0]
     s_bytes = 2 if store in ("bf16", "f16") else 4

@@ -75,6 +75,36 @@ typedef struct {
   int64_t hbm_budget_bytes;   /* upper bound on device memory this index may hold; 0: none */
 } dade_build_opts;
 
+/* Low-precision rerank rules (the paper has no low-precision store).  A DCO that reaches d = D
+ * on the stored coordinates passes the gate when the heap is not full or its stored-precision
+ * S_D <= (1 + rerank_delta) r^2.  ALL gives every candidate that passed the gate its exact FP32
+ * distance from the original vectors.  LAZY gives it to the K smallest of them by stored S_D,
+ * then to the others only where S_D <= (1 + rerank_delta) b, b the K-th smallest exact distance
+ * of the heap and those K; it keeps what ALL keeps unless a skipped candidate's stored-precision
+ * error exceeds rerank_delta.  Either way the keep rule applies to exact distances. */
+typedef enum { DADE_RERANK_ALL = 0, DADE_RERANK_LAZY = 1 } dade_rerank_rule;
+
+/* What a dade_search call ran with (host, filled on success when requested): the values that
+ * define its results -- Delta_d, the mode, the round schedule and the rerank rule and margin, so
+ * that a reference implementation can replay the search -- and how it was launched. */
+typedef struct {
+  int32_t delta_d;            /* Delta_d used (after the default) */
+  int32_t mode;               /* dade_mode */
+  int32_t schedule;           /* dade_schedule */
+  int32_t fill_min;
+  int32_t growth;
+  int32_t rerank_rule;        /* dade_rerank_rule (low-precision stores) */
+  float rerank_delta;         /* the gate's margin used (low-precision stores) */
+  int32_t k;                  /* the k argument: the largest K */
+  int32_t nprobe_requested;   /* the nprobe argument */
+  int32_t nprobe;             /* after clamping to nlist */
+  int32_t nprobe_clamped;     /* 1 when nprobe > nlist was clamped */
+  int32_t rounds;             /* round launches per pass (an upper bound on any query's rounds) */
+  int32_t passes;             /* the batch ran in this many passes of the list scan */
+  int32_t graph;              /* 0: launched one by one; 1: captured into a HIP graph and
+                                 launched; 2: an earlier capture replayed */
+} dade_search_record;
+
 typedef struct {
   int32_t delta_d;            /* Delta_d of Algorithm 1, in [1, dim]; 0 means 32 (or dim if
                                  smaller) */
@@ -97,6 +127,11 @@ typedef struct {
   int32_t scan_blocks_per_cu; /* launch shape of the DCO kernel: workgroups per compute unit of
                                  its persistent grid; 0 (or more than fit) means as many as are
                                  resident at once; results are identical for every value */
+  int32_t rerank_rule;        /* dade_rerank_rule for low-precision stores; 0 means ALL */
+  dade_search_record* record; /* host, nullable: filled with what the call ran with */
+  int32_t* query_record;      /* device, nullable: [nq x 3] int32 per query: K used, nprobe used
+                                 (per-query values clamped into [1, k] and [1, nprobe], nprobe
+                                 clamped to nlist), and the query's round count */
 } dade_search_opts;
 
 /* Host copies of an index's artifacts (for checkpoints and for parity checks).  All arrays
@@ -164,8 +199,8 @@ int dade_calibrate(dade_index* ix, double alpha, const int64_t* pairs, int64_t n
  * ascending by (squared distance, id), padded with (-1, +inf) after the query's K results.
  * Requires state CALIBRATED for DADE mode and >= ROTATED for FULL_D; 1 <= k <= 128;
  * nprobe >= 1; nq >= 0 (nq == 0 is a no-op).  opts may be NULL: delta_d 32, DADE mode,
- * PER_RANK, the calibrated rerank_delta, no stats or timing, fill_min 32, growth 16, graph, a
- * full grid.
+ * PER_RANK, the calibrated rerank_delta and rule ALL, no stats, records or timing, fill_min 32,
+ * growth 16, graph, a full grid.
  * Asynchronous on `stream`.
  */
 int dade_search(dade_index* ix, const float* Q, int64_t nq, int32_t k, int32_t nprobe,
@@ -332,8 +367,9 @@ int dade_autotune(dade_index* ix, const float* Q, int64_t nq, int32_t k, int32_t
  * list it and that it does not list, nearest first by (squared distance in FP64 over the FP32
  * vectors, row id); rows are degree + reverse (<= 64) wide, -1 padded.  Each list has two entry
  * points: its medoid (the member nearest its centroid in FP32, ties to the lower id) and the
- * member farthest from the medoid (ties to the lower id; -1 for a list of one).  X: device
- * [n x dim] FP32, the vectors the index was built from.  Replaces a previous graph.
+ * member farthest from the medoid (ties to the lower id; -1 for a list of one).  The queries of
+ * the FDScanning search are the index's own copy of the vectors it was built from, so row i is
+ * searched as row i.  Replaces a previous graph.
  * Requires n <= 20000 (DADE_EINVAL above): larger builds are switched off while a GPU fault seen
  * in a 1M-row build is unexplained.  Synchronises `stream`.
  *
@@ -354,8 +390,7 @@ int dade_autotune(dade_index* ix, const float* Q, int64_t nq, int32_t k, int32_t
  * neighbors [n x width] (row i's neighbours), entries [nlist x 2] (-1 where a list has no
  * such member); NULL arrays are skipped.
  */
-int dade_graph_build(dade_index* ix, const float* X, int32_t degree, int32_t reverse, int32_t nprobe,
-                     void* stream);
+int dade_graph_build(dade_index* ix, int32_t degree, int32_t reverse, int32_t nprobe, void* stream);
 int dade_graph_search(dade_index* ix, const float* Q, int64_t nq, int32_t k, int32_t ef, int32_t n_entry,
                       int32_t max_iters, const dade_search_opts* opts, int64_t* out_ids, float* out_dist2,
                       void* stream);

@@ -218,7 +218,7 @@ int make_index(const float* X, int64_t n, int32_t dim, int32_t nlist, const dade
   ix->n = n; ix->dim = dim; ix->dp = pad_dim(dim); ix->nlist = nlist; ix->store = store;
   ix->budget = opts ? opts->hbm_budget_bytes : 0;
   if ((rc = alloc_t(ix, &ix->X, size_t(n) * ix->dp))) { dade_destroy(ix); return rc; }
-  hipError_t e = launch_pad_rows(X, n, dim, ix->X, ix->dp, s);
+  hipError_t e = launch_pad_rows(X, n, dim, dim, ix->X, ix->dp, s);
   if (e != hipSuccess) { dade_destroy(ix); FAIL(DADE_EDEVICE, hip_msg(e, "pad X")); }
   *out = ix;
   return DADE_OK;
@@ -332,6 +332,10 @@ int grow_query_workspace(dade_index* ix, int64_t nq, int64_t npm, hipStream_t s)
   return DADE_OK;
 }
 
+// Device bytes one pass of the list scan may hold in queued keys and work items (a batch that
+// needs more runs in passes); a few percent of the device's HBM.
+constexpr int64_t kPassWorkspaceBytes = int64_t(8) << 30;
+
 // Sizes of one search's round workspace, from the list sizes, K, nprobe and the schedule.
 struct SearchPlan {
   int npm = 0, widest = 1, rounds = 0;
@@ -369,10 +373,10 @@ int plan_search(dade_index* ix, int64_t nq, int32_t k, int32_t nprobe, const dad
   // work items of one query in one round: its segments cut at 16 candidates (whole-row rounds;
   // other rounds use 64)
   const int64_t items_pq = std::max<int64_t>((kb_cap + 15) / 16 + widest + 1, (first + 15) / 16 + npm);
-  // queries per pass: the round workspace stays under 1 GiB
+  // queries per pass: the round workspace stays under kPassWorkspaceBytes
   const int64_t per_q = kb_cap * 8 + rounds * (items_pq * 16 + 4) + int64_t(k) * 8 + 48;
   const int64_t chunk =
-      std::max<int64_t>(1, std::min<int64_t>({nq, (int64_t(1) << 30) / per_q, int64_t(kMaxPassQueries)}));
+      std::max<int64_t>(1, std::min<int64_t>({nq, kPassWorkspaceBytes / per_q, int64_t(kMaxPassQueries)}));
   if ((rc = grow_query_workspace(ix, nq, npm, s))) return rc;
   if ((rc = grow(ix, &ix->w_topk, ix->w_topk_n, chunk * k, s)) || (rc = grow(ix, &ix->w_keyr, ix->w_keyr_n, chunk, s)) ||
       (rc = grow(ix, &ix->w_r2, ix->w_r2_n, chunk, s)) || (rc = grow(ix, &ix->w_qint, ix->w_qint_n, chunk * 3, s)) ||
@@ -795,9 +799,11 @@ static hipError_t enqueue_rounds(dade_index* ix, const RoundArgs& a, int rounds,
   return hipSuccess;
 }
 
-int dade_search(dade_index* ix, const float* Q, int64_t nq, int32_t k, int32_t nprobe,
-                const int32_t* k_per_query, const int32_t* nprobe_per_query,
-                const dade_search_opts* opts, int64_t* out_ids, float* out_dist2, void* stream) {
+// dade_search with query rows `ldq` floats apart (the C ABI's queries are dense, ldq = dim; the
+// graph build searches the index's own padded rows, ldq = dp).
+static int search_impl(dade_index* ix, const float* Q, int64_t ldq, int64_t nq, int32_t k, int32_t nprobe,
+                       const int32_t* k_per_query, const int32_t* nprobe_per_query,
+                       const dade_search_opts* opts, int64_t* out_ids, float* out_dist2, void* stream) {
   if (!ix) FAIL(DADE_EINVAL, "index is NULL");
   if (nq < 0 || nq >= (int64_t(1) << 31)) FAIL(DADE_EINVAL, "nq must be in [0, 2^31)");
   if (k < 1 || k > kMaxK) FAIL(DADE_EINVAL, "k must be in [1, 128]");
@@ -807,6 +813,7 @@ int dade_search(dade_index* ix, const float* Q, int64_t nq, int32_t k, int32_t n
   o.fill_min = 32; o.growth = 16; o.use_graph = 1;
   if (opts) o = *opts;
   if (o.fill_min < 0 || o.growth < 0) FAIL(DADE_EINVAL, "fill_min and growth must be >= 0");
+  if (o.rerank_rule != DADE_RERANK_ALL && o.rerank_rule != DADE_RERANK_LAZY) FAIL(DADE_EINVAL, "bad rerank_rule");
   const int dd = o.delta_d > 0 ? o.delta_d : std::min(32, ix->dim);
   if (dd < 1 || dd > ix->dim) FAIL(DADE_EINVAL, "delta_d must be in [1, dim]");
   if (o.mode != DADE_MODE_DADE && o.mode != DADE_MODE_FULL_D) FAIL(DADE_EINVAL, "bad mode");
@@ -821,6 +828,7 @@ int dade_search(dade_index* ix, const float* Q, int64_t nq, int32_t k, int32_t n
   if (k_per_query && (rc = check_device_pointer(k_per_query, "k_per_query"))) return rc;
   if (nprobe_per_query && (rc = check_device_pointer(nprobe_per_query, "nprobe_per_query"))) return rc;
   if (o.stats && (rc = check_device_pointer(o.stats, "stats"))) return rc;
+  if (o.query_record && (rc = check_device_pointer(o.query_record, "query_record"))) return rc;
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int dp = ix->dp, nl = ix->nlist;
   SearchPlan pl;
@@ -843,11 +851,11 @@ int dade_search(dade_index* ix, const float* Q, int64_t nq, int32_t k, int32_t n
   // padding copy.  The captured launch sequence holds the query pointer, so with graphs on only
   // a buffer passed again (a serving loop's) is read in place; a new buffer is copied, which
   // keeps the captured sequence valid.
-  const bool q_in_place = ix->dim == dp && reinterpret_cast<uintptr_t>(Q) % 16 == 0 &&
+  const bool q_in_place = ldq == dp && reinterpret_cast<uintptr_t>(Q) % 16 == 0 &&
                           (!o.use_graph || Q == ix->last_q);
   ix->last_q = Q;
   const float* qpad = q_in_place ? Q : ix->w_qpad;
-  if (!q_in_place) HIPC(launch_pad_rows(Q, nq, ix->dim, ix->w_qpad, dp, s));
+  if (!q_in_place) HIPC(launch_pad_rows(Q, nq, ix->dim, ldq, ix->w_qpad, dp, s));
   GemmArgs g;
   g.M = int(nq); g.N = dp + nl; g.K = dp;
   g.A = qpad; g.lda = dp; g.a_shift = ix->d_mu;
@@ -872,9 +880,12 @@ int dade_search(dade_index* ix, const float* Q, int64_t nq, int32_t k, int32_t n
   ra.kb_cap = kb_cap;
   ra.rounds = rounds;
   ra.grid = ix->cus * blocks_per_cu;
-  for (int64_t c0 = 0; c0 < nq; c0 += chunk) {
-    const int64_t cn = std::min(chunk, nq - c0);
-    RoundArgs a;
+  ra.rerank_rule = o.rerank_rule;
+  const int64_t n_pass = (nq + chunk - 1) / chunk;
+  std::vector<RoundArgs> passes(static_cast<size_t>(n_pass));
+  for (int64_t pi = 0; pi < n_pass; ++pi) {
+    const int64_t c0 = pi * chunk, cn = std::min(chunk, nq - c0);
+    RoundArgs& a = passes[size_t(pi)];
     std::memcpy(&a, &ra, sizeof ra);
     a.nq = int(cn);
     a.k_pq = k_per_query ? k_per_query + c0 : nullptr;
@@ -883,6 +894,7 @@ int dade_search(dade_index* ix, const float* Q, int64_t nq, int32_t k, int32_t n
     a.probes = ix->w_probes + c0 * npm;
     a.out_ids = out_ids + c0 * k; a.out_d2 = out_dist2 + c0 * k;
     a.stats = o.stats ? o.stats + c0 * 4 : nullptr;
+    a.q_record = o.query_record ? o.query_record + c0 * 3 : nullptr;
     a.q_topk = ix->w_topk; a.q_keyr = ix->w_keyr; a.q_r2 = ix->w_r2;
     a.q_topn = ix->w_qint; a.q_kc = a.q_topn + cn; a.q_rounds = a.q_topn + 2 * cn;
     a.kb = ix->w_kb;
@@ -890,36 +902,41 @@ int dade_search(dade_index* ix, const float* Q, int64_t nq, int32_t k, int32_t n
     a.items = ix->w_items;
     a.n_items = ix->w_counter; a.overflow = ix->w_flags;
     a.item_off = ix->w_counts;
-    hipEvent_t* kev = nullptr;
-    if (o.record_times) {   // one set of events per pass; the reported times sum every pass
-      const int64_t n_pass = (nq + chunk - 1) / chunk;
-      while (ix->kev.size() < size_t(n_pass * (2 + 3 * rounds))) {
-        hipEvent_t e;
-        HIPC(hipEventCreate(&e));
-        ix->kev.push_back(e);
-      }
-      ix->kev_rounds = rounds;
-      ix->kev_passes = int(n_pass);
-      kev = ix->kev.data() + size_t(c0 / chunk) * (2 + 3 * rounds);
+  }
+  int graph_state = 0;
+  if (o.record_times) {   // one set of events per pass; the reported times sum every pass
+    while (ix->kev.size() < size_t(n_pass * (2 + 3 * rounds))) {
+      hipEvent_t e;
+      HIPC(hipEventCreate(&e));
+      ix->kev.push_back(e);
     }
-    // the launch sequence of this pass; replayed from a captured graph when it is the same as
-    // the last captured one (a whole batch in one pass).  Captures start on an internal stream
-    // (the caller's may be the null stream, which cannot be captured).
-    const bool graph = o.use_graph && !o.record_times && chunk >= nq;
-    std::vector<unsigned char> key;
-    if (graph) {
-      key.resize(sizeof(RoundArgs) + 2 * sizeof(int));
-      std::memcpy(key.data(), &a, sizeof(RoundArgs));
-      const int tail[2] = {rounds, ix->device};
-      std::memcpy(key.data() + sizeof(RoundArgs), tail, sizeof tail);
-      if (ix->graph_exec && key == ix->graph_key) {
-        HIPC(hipGraphLaunch(ix->graph_exec, s));
-        continue;
-      }
+    ix->kev_rounds = rounds;
+    ix->kev_passes = int(n_pass);
+    for (int64_t pi = 0; pi < n_pass; ++pi) {
+      const hipError_t e = enqueue_rounds(ix, passes[size_t(pi)], rounds, ix->kev.data() + size_t(pi) * (2 + 3 * rounds), s);
+      if (e != hipSuccess) FAIL(DADE_EDEVICE, hip_msg(e, "list scan launch"));
+    }
+  } else if (!o.use_graph) {
+    for (const RoundArgs& a : passes) {
+      const hipError_t e = enqueue_rounds(ix, a, rounds, nullptr, s);
+      if (e != hipSuccess) FAIL(DADE_EDEVICE, hip_msg(e, "list scan launch"));
+    }
+  } else {
+    // the launch sequence of every pass, captured into one HIP graph and replayed while it is the
+    // same as the last captured one.  Captures start on an internal stream (the caller's may be
+    // the null stream, which cannot be captured).
+    std::vector<unsigned char> key(sizeof(RoundArgs) * passes.size() + 2 * sizeof(int));
+    std::memcpy(key.data(), passes.data(), sizeof(RoundArgs) * passes.size());
+    const int tail[2] = {rounds, ix->device};
+    std::memcpy(key.data() + sizeof(RoundArgs) * passes.size(), tail, sizeof tail);
+    if (ix->graph_exec && key == ix->graph_key) {
+      HIPC(hipGraphLaunch(ix->graph_exec, s));
+      graph_state = 2;
+    } else {
       HIPC(hipStreamBeginCapture(ix->cap, hipStreamCaptureModeRelaxed));
-    }
-    hipError_t e = enqueue_rounds(ix, a, rounds, kev, graph ? ix->cap : s);
-    if (graph) {
+      hipError_t e = hipSuccess;
+      for (const RoundArgs& a : passes)
+        if (e == hipSuccess) e = enqueue_rounds(ix, a, rounds, nullptr, ix->cap);
       hipGraph_t g = nullptr;
       const hipError_t e2 = hipStreamEndCapture(ix->cap, &g);
       if (e == hipSuccess) e = e2;
@@ -932,14 +949,30 @@ int dade_search(dade_index* ix, const float* Q, int64_t nq, int32_t k, int32_t n
         ix->graph_key.swap(key);
         e = hipGraphLaunch(ix->graph_exec, s);
       }
+      if (e != hipSuccess) FAIL(DADE_EDEVICE, hip_msg(e, "list scan launch"));
+      graph_state = 1;
     }
-    if (e != hipSuccess) FAIL(DADE_EDEVICE, hip_msg(e, "list scan launch"));
   }
   if (o.record_times) {
     HIPC(hipEventRecord(ix->ev[3], s));
     ix->ev_used = true;
   }
+  if (o.record) {
+    dade_search_record& rec = *o.record;
+    rec.delta_d = dd; rec.mode = o.mode; rec.schedule = o.schedule;
+    rec.fill_min = o.fill_min; rec.growth = o.growth;
+    rec.rerank_rule = o.rerank_rule; rec.rerank_delta = ra.rerank_delta;
+    rec.k = k; rec.nprobe_requested = nprobe; rec.nprobe = npm; rec.nprobe_clamped = nprobe > nl ? 1 : 0;
+    rec.rounds = rounds; rec.passes = int(n_pass); rec.graph = graph_state;
+  }
   return DADE_OK;
+}
+
+int dade_search(dade_index* ix, const float* Q, int64_t nq, int32_t k, int32_t nprobe,
+                const int32_t* k_per_query, const int32_t* nprobe_per_query,
+                const dade_search_opts* opts, int64_t* out_ids, float* out_dist2, void* stream) {
+  if (!ix) FAIL(DADE_EINVAL, "index is NULL");
+  return search_impl(ix, Q, ix->dim, nq, k, nprobe, k_per_query, nprobe_per_query, opts, out_ids, out_dist2, stream);
 }
 
 int dade_check(dade_index* ix, void* stream) {
@@ -981,8 +1014,7 @@ int dade_stage_times(dade_index* ix, dade_times* out) {
   return DADE_OK;
 }
 
-int dade_graph_build(dade_index* ix, const float* X, int32_t degree, int32_t reverse, int32_t nprobe,
-                     void* stream) {
+int dade_graph_build(dade_index* ix, int32_t degree, int32_t reverse, int32_t nprobe, void* stream) {
   if (!ix) FAIL(DADE_EINVAL, "index is NULL");
   if (degree < 1 || reverse < 0 || degree + reverse > kGraphMax)
     FAIL(DADE_EINVAL, "degree >= 1, reverse >= 0 and degree + reverse <= 64 are required");
@@ -991,8 +1023,7 @@ int dade_graph_build(dade_index* ix, const float* X, int32_t degree, int32_t rev
   if (ix->n > kGraphBuildMaxRows)
     FAIL(DADE_EINVAL, "graph build: indexes of more than " + std::to_string(kGraphBuildMaxRows) +
                           " rows are not supported (a build of 1M x 960 rows faulted the GPU; its cause is open)");
-  int rc = check_device_pointer(X, "X");
-  if (rc) return rc;
+  int rc = DADE_OK;
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int64_t n = ix->n;
   const int width = degree + reverse;
@@ -1024,7 +1055,8 @@ int dade_graph_build(dade_index* ix, const float* X, int32_t degree, int32_t rev
   // every row's degree + 1 nearest by FDScanning over nprobe lists, then itself dropped
   for (int64_t c0 = 0; c0 < n && rc == DADE_OK; c0 += chunk) {
     const int64_t cn = std::min(chunk, n - c0);
-    rc = dade_search(ix, X + c0 * ix->dim, cn, degree + 1, nprobe, nullptr, nullptr, &o, res, rd, stream);
+    // the queries are the index's own rows (zero-padded to dp), row id c0 + i at row c0 + i
+    rc = search_impl(ix, ix->X + c0 * ix->dp, ix->dp, cn, degree + 1, nprobe, nullptr, nullptr, &o, res, rd, stream);
     if (rc == DADE_OK) {
       const hipError_t e = launch_graph_collect(res, int(cn), c0, degree, width, ix->d_pos, ix->d_nbr, s);
       if (e != hipSuccess) { dade::set_error(hip_msg(e, "graph collect")); rc = DADE_EDEVICE; }
@@ -1147,7 +1179,7 @@ int dade_graph_search(dade_index* ix, const float* Q, int64_t nq, int32_t k, int
   // rotation and entry lists: the same GEMM and selection as dade_search
   const bool q_in_place = ix->dim == dp && reinterpret_cast<uintptr_t>(Q) % 16 == 0;
   const float* qpad = q_in_place ? Q : ix->w_qpad;
-  if (!q_in_place) HIPC(launch_pad_rows(Q, nq, ix->dim, ix->w_qpad, dp, s));
+  if (!q_in_place) HIPC(launch_pad_rows(Q, nq, ix->dim, ix->dim, ix->w_qpad, dp, s));
   GemmArgs g;
   g.M = int(nq); g.N = dp + nl; g.K = dp;
   g.A = qpad; g.lda = dp; g.a_shift = ix->d_mu;

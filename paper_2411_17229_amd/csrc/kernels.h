@@ -40,7 +40,8 @@ struct GemmArgs {
 hipError_t launch_gemm(const GemmArgs& a, GemmEpilogue epi, hipStream_t s);
 
 // ---------------------------------------------------------------- small kernels (misc.hip)
-hipError_t launch_pad_rows(const float* src, int64_t rows, int cols, float* dst, int ld,
+// dst[r][c] = src[r * lds + c] for c < cols, 0 up to ld.
+hipError_t launch_pad_rows(const float* src, int64_t rows, int cols, int64_t lds, float* dst, int ld,
                            hipStream_t s);
 hipError_t launch_gather_rows(const float* src, int ld, const int64_t* rows, int64_t count,
                               float* dst, hipStream_t s);
@@ -112,6 +113,8 @@ struct RoundArgs {
   const float* X = nullptr;         // [n x dp] original vectors by row id (rerank)
   const float* T = nullptr;         // [dim] T_d
   float rerank_delta = 0.f;
+  int rerank_rule = 0;              // low-precision rerank: 0 every gated survivor, 1 lazy
+  int32_t* q_record = nullptr;      // [nq x 3] per query: K used, nprobe used, rounds (nullable)
   int64_t* out_ids = nullptr;
   float* out_d2 = nullptr;
   int64_t* stats = nullptr;

@@ -12,14 +12,14 @@ inline int blocks_for(int64_t n, int per = kBlock) {
   return int(b < 65535 * 16 ? b : 65535 * 16);
 }
 
-__global__ void pad_rows_kernel(const float* __restrict__ src, int64_t rows, int cols,
+__global__ void pad_rows_kernel(const float* __restrict__ src, int64_t rows, int cols, int64_t lds,
                                 float* __restrict__ dst, int ld) {
   const int64_t total = rows * ld;
   for (int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; e < total;
        e += int64_t(gridDim.x) * blockDim.x) {
     const int64_t r = e / ld;
     const int c = int(e % ld);
-    dst[e] = c < cols ? src[r * cols + c] : 0.f;
+    dst[e] = c < cols ? src[r * lds + c] : 0.f;
   }
 }
 
@@ -91,11 +91,11 @@ __global__ void labels_kernel(const unsigned long long* __restrict__ best, int64
 
 }  // namespace
 
-hipError_t launch_pad_rows(const float* src, int64_t rows, int cols, float* dst, int ld,
+hipError_t launch_pad_rows(const float* src, int64_t rows, int cols, int64_t lds, float* dst, int ld,
                            hipStream_t s) {
   if (rows == 0) return hipSuccess;
   hipLaunchKernelGGL(pad_rows_kernel, dim3(blocks_for(rows * ld)), dim3(kBlock), 0, s, src, rows,
-                     cols, dst, ld);
+                     cols, lds, dst, ld);
   return hipGetLastError();
 }
 

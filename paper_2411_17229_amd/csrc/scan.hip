@@ -29,10 +29,11 @@
 // A DCO's partial distance is summed in one order on every path: each 8-coordinate unit's
 // squared differences by an FMA chain from zero, then S_d = S_{d-8} + unit sum, unit after unit.
 // Low-precision stores: a survivor is queued with its stored-precision S_D when the heap is not
-// full or S_D <= (1 + delta) r^2; at the merge the K smallest queued keys are reranked exactly
-// (FP32, from the original vectors); with b the K-th smallest exact distance of the heap and
-// those, the other queued candidates are reranked only where S_D <= (1 + delta) b; the keep rule
-// (heap not full, or (S_D, id) < (r^2, id_r)) then applies to exact values.
+// full or S_D <= (1 + delta) r^2.  At the merge the plain rule reranks every queued candidate
+// exactly (FP32, from the original vectors); the lazy rule reranks the K smallest queued keys
+// and, with b the K-th smallest exact distance of the heap and those, the other queued
+// candidates only where S_D <= (1 + delta) b.  The keep rule (heap not full, or (S_D, id) <
+// (r^2, id_r)) then applies to exact values.
 #include "kernels.h"
 
 namespace dade {
@@ -846,6 +847,11 @@ __global__ __launch_bounds__(64) void plan_kernel(RoundArgs a, int* counts) {
       for (int rr = r; rr < a.rounds; ++rr) counts[int64_t(rr) * a.nq + q] = 0;
       if (t < np) atomicOr(a.overflow, 4);   // more rounds than the launch sequence holds
       a.q_rounds[q] = r;
+      if (a.q_record) {
+        a.q_record[int64_t(q) * 3 + 0] = K;
+        a.q_record[int64_t(q) * 3 + 1] = np;
+        a.q_record[int64_t(q) * 3 + 2] = r;
+      }
       a.q_topn[q] = 0;
       a.q_kc[q] = 0;
       a.q_keyr[q] = ~0ull;
@@ -993,8 +999,19 @@ __global__ __launch_bounds__(kThreads) void merge_round_kernel(RoundArgs a, int 
       if (tid == 0) st_kept += unsigned(s_below);
       merge_into(topk, topk_n, newk, cand, s_nc, K, tid);
     }
+  } else if (m > 0 && a.rerank_rule == 0) {
+    // plain rule: every queued key (a survivor that passed the gate) gets its exact distance
+    for (int base = 0; base < m; base += kMergeChunk) {
+      const int cnt = m - base < kMergeChunk ? m - base : kMergeChunk;
+      for (int i = tid; i < cnt; i += kThreads) cand[i] = queued(base + i);
+      __syncthreads();
+      exact_rerank(cand, cnt, a.X, qo, dp, dim, tid, st_rr);
+      keep_below(cand, cnt, keyr, &s_nc, tid);   // keyr is ~0 while the heap is not full
+      if (tid == 0) st_kept += unsigned(s_nc);
+      merge_into(topk, topk_n, newk, cand, s_nc, K, tid);
+    }
   } else if (m > 0) {
-    // F = the K smallest queued keys (stored-precision S_D, id), into cand[0..fn)
+    // lazy rule.  F = the K smallest queued keys (stored-precision S_D, id), into cand[0..fn)
     int fn = 0;
     unsigned long long fmax = ~0ull;
     if (m <= K) {

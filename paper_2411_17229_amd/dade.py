@@ -20,6 +20,7 @@ DADE_OK, DADE_EINVAL, DADE_ESTATE, DADE_ENOMEM, DADE_EDEVICE = 0, -1, -2, -3, -4
 DTYPES = {"f32": 0, "bf16": 1, "f16": 2}
 MODES = {"dade": 0, "full_d": 1}
 SCHEDULES = {"per_rank": 0, "doubling": 1}
+RERANK_RULES = {"all": 0, "lazy": 1}
 STATE_BUILT, STATE_ROTATED, STATE_CALIBRATED = 1, 2, 3
 EXPORTED = ("dade_build_index", "dade_rotate", "dade_calibrate", "dade_search", "dade_check", "dade_index_info",
             "dade_export", "dade_import", "dade_stage_times", "dade_serve", "dade_autotune", "dade_graph_build",
@@ -39,11 +40,21 @@ class BuildOpts(ctypes.Structure):
                 ("hbm_budget_bytes", ctypes.c_int64)]
 
 
+class SearchRecord(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_int32) for name in ("delta_d", "mode", "schedule", "fill_min", "growth",
+                                                      "rerank_rule")] + \
+               [("rerank_delta", ctypes.c_float)] + \
+               [(name, ctypes.c_int32) for name in ("k", "nprobe_requested", "nprobe", "nprobe_clamped", "rounds",
+                                                      "passes", "graph")]
+
+
 class SearchOpts(ctypes.Structure):
     _fields_ = [("delta_d", ctypes.c_int32), ("mode", ctypes.c_int32), ("schedule", ctypes.c_int32),
                 ("rerank_delta", ctypes.c_float), ("stats", ctypes.c_void_p),
                 ("record_times", ctypes.c_int32), ("fill_min", ctypes.c_int32), ("growth", ctypes.c_int32),
-                ("use_graph", ctypes.c_int32), ("scan_blocks_per_cu", ctypes.c_int32)]
+                ("use_graph", ctypes.c_int32), ("scan_blocks_per_cu", ctypes.c_int32),
+                ("rerank_rule", ctypes.c_int32), ("record", ctypes.POINTER(SearchRecord)),
+                ("query_record", ctypes.c_void_p)]
 
 
 class ServeOpts(ctypes.Structure):
@@ -102,7 +113,7 @@ def lib():
         L.dade_stage_times.argtypes = [vp, ctypes.POINTER(Times)]
         L.dade_serve.argtypes = [vp, i64, vp, vp, vp, vp, vp, ctypes.POINTER(ServeOpts), vp, vp, vp,
                                  ctypes.POINTER(ServeStats), vp]
-        L.dade_graph_build.argtypes = [vp, vp, i32, i32, i32, vp]
+        L.dade_graph_build.argtypes = [vp, i32, i32, i32, vp]
         L.dade_graph_search.argtypes = [vp, vp, i64, i32, i32, i32, i32, ctypes.POINTER(SearchOpts), vp, vp, vp]
         L.dade_graph_export.argtypes = [vp, ctypes.POINTER(i32), vp, vp]
         L.dade_autotune.argtypes = [vp, vp, i64, i32, i32, vp, vp, ctypes.c_float, i32, ctypes.POINTER(SearchOpts),
@@ -197,8 +208,12 @@ def dade_calibrate(ix: Index, alpha=0.1, pairs=None, n_pairs=100_000, seed=0, st
 def dade_search(ix: Index, Q, k, nprobe, k_per_query=None, nprobe_per_query=None, delta_d=0,
                 mode="dade", schedule="per_rank", rerank_delta=-1.0, stats=None, record_times=False,
                 out_ids=None, out_dist2=None, stream=None, fill_min=32, growth=16, use_graph=True,
-                scan_blocks_per_cu=0):
-    """Returns (ids [nq, k] int64, dist2 [nq, k] float32) device tensors (asynchronous)."""
+                scan_blocks_per_cu=0, rerank_rule="all", record=None, query_record=None):
+    """Returns (ids [nq, k] int64, dist2 [nq, k] float32) device tensors (asynchronous).
+
+    ``record``: a dict filled with what the call ran with (dade_search_record's fields, the rerank
+    rule and schedule by name); ``query_record``: a device int32 [nq, 3] tensor (K, nprobe used,
+    rounds per query)."""
     import torch
     qp = _dev(Q, torch.float32, "Q")
     nq = Q.shape[0]
@@ -206,28 +221,40 @@ def dade_search(ix: Index, Q, k, nprobe, k_per_query=None, nprobe_per_query=None
         out_ids = torch.empty((nq, k), dtype=torch.int64, device=Q.device)
     if out_dist2 is None:
         out_dist2 = torch.empty((nq, k), dtype=torch.float32, device=Q.device)
-    o = SearchOpts()
-    o.delta_d, o.mode, o.schedule = delta_d, MODES[mode], SCHEDULES[schedule]
-    o.rerank_delta = rerank_delta
+    o = _search_opts(delta_d, mode, schedule, rerank_delta, fill_min, growth, use_graph, scan_blocks_per_cu,
+                     rerank_rule)
     o.stats = None if stats is None else _dev(stats, torch.int64, "stats").value
     o.record_times = int(bool(record_times))
-    o.fill_min, o.growth, o.use_graph = fill_min, growth, int(bool(use_graph))
-    o.scan_blocks_per_cu = scan_blocks_per_cu
+    o.query_record = None if query_record is None else _dev(query_record, torch.int32, "query_record").value
+    rec = SearchRecord()
+    if record is not None:
+        o.record = ctypes.pointer(rec)
     kp = None if k_per_query is None else _dev(k_per_query, torch.int32, "k_per_query")
     npp = None if nprobe_per_query is None else _dev(nprobe_per_query, torch.int32, "nprobe_per_query")
     _check(lib().dade_search(ix.handle, qp, nq, k, nprobe, kp, npp, ctypes.byref(o),
                              _dev(out_ids, torch.int64, "out_ids"),
                              _dev(out_dist2, torch.float32, "out_dist2"), _stream(stream)))
+    if record is not None:
+        record.update(_record_dict(rec))
     return out_ids, out_dist2
 
 
+def _record_dict(rec):
+    out = {name: getattr(rec, name) for name, _ in SearchRecord._fields_}
+    out["mode"] = {v: k_ for k_, v in MODES.items()}[out["mode"]]
+    out["schedule"] = {v: k_ for k_, v in SCHEDULES.items()}[out["schedule"]]
+    out["rerank_rule"] = {v: k_ for k_, v in RERANK_RULES.items()}[out["rerank_rule"]]
+    return out
+
+
 def _search_opts(delta_d=0, mode="dade", schedule="per_rank", rerank_delta=-1.0, fill_min=32, growth=16,
-                 use_graph=True, scan_blocks_per_cu=0):
+                 use_graph=True, scan_blocks_per_cu=0, rerank_rule="all"):
     o = SearchOpts()
     o.delta_d, o.mode, o.schedule = delta_d, MODES[mode], SCHEDULES[schedule]
     o.rerank_delta = rerank_delta
     o.fill_min, o.growth = fill_min, growth
     o.use_graph, o.scan_blocks_per_cu = int(bool(use_graph)), scan_blocks_per_cu
+    o.rerank_rule = RERANK_RULES[rerank_rule]
     return o
 
 
@@ -284,10 +311,8 @@ def dade_autotune(ix: Index, Q, k, nprobe, k_per_query=None, nprobe_per_query=No
     return chosen, table
 
 
-def dade_graph_build(ix: Index, X, degree=16, reverse=8, nprobe=4, stream=None):
-    import torch
-    _check(lib().dade_graph_build(ix.handle, _dev(X, torch.float32, "X"), degree, reverse, nprobe,
-                                  _stream(stream)))
+def dade_graph_build(ix: Index, degree=16, reverse=8, nprobe=4, stream=None):
+    _check(lib().dade_graph_build(ix.handle, degree, reverse, nprobe, _stream(stream)))
 
 
 def dade_graph_search(ix: Index, Q, k, ef, n_entry=4, max_iters=0, delta_d=32, mode="dade", stats=None,

@@ -1,16 +1,29 @@
-"""Shared helpers of the GPU parity tests (oracle on the CPU, HIP path through the C ABI)."""
+"""Shared helpers of the GPU parity tests (oracle on the CPU, HIP path through the C ABI).
+
+Parity protocol.  Every returned distance must be the FP64 distance of its id within DIST_RTOL,
+and every row must ascend by (dist^2, id).  A query whose top-K id set differs from the oracle's
+is excused only when the oracle, re-run on that query with one or two of its near-tie decisions
+taken the other way, returns the GPU's id set.  A near tie is a decision whose relative margin is
+at most EXCUSE_TOL: a hypothesis test S_d vs T_d r^2, a low-precision gate, a keep compare, the
+cut between the K-th and (K+1)-th key, or a gap in the probe order.  The HIP path computes those
+quantities in FP32 from FP32-rotated coordinates, so such a decision can go the other way there.
+The count of excused queries is bounded and returned.
+"""
+import itertools
+
 import numpy as np
 
-from oracle import ivf, lowp
+from oracle import graph, ivf, lowp
 from paper_2411_17229_amd import dade, workloads
 
-# FP32 distances vs the FP64 oracle (spec tolerance).
+# FP32 distances vs the FP64 oracle, and the relative margin of a decision that FP32 rounding may
+# flip (the benchmark spec's tolerance for both).
 DIST_RTOL = 1e-5
-# A query is excused from ID-set equality when the oracle logged a decision (test, rerank
-# gate, keep compare, top-K boundary) or probe-order gap within this relative margin: the
-# HIP path computes S_d, r^2 and centroid distances in FP32 from FP32-rotated coordinates,
-# whose relative error (a few 1e-6 for D <= 1024) can flip such a decision.
-MARGIN_TOL = 1e-4
+EXCUSE_TOL = 1e-5
+# decisions the oracle logs (wider than EXCUSE_TOL, so that reports can show the nearest ones)
+EVENT_TOL = 1e-3
+# single flips tried per excused query, and the near ties combined in pairs
+MAX_SINGLE, MAX_PAIR = 12, 6
 
 
 def oracle_index(X, nlist, seed, n_pairs=100_000, alpha=0.1, store=None):
@@ -25,6 +38,42 @@ def artifacts(oi):
                 list_ids=oi.ids, T=oi.T, delta=oi.delta)
 
 
+class OracleRun:
+    """One oracle search with its logs, kept so that a single query can be re-run with chosen
+    decisions taken the other way.  ``run(Q, K, nprobe, flips, log)`` is the search itself."""
+
+    def __init__(self, run, Q, K, nprobe):
+        self.run, self.Q = run, np.asarray(Q)
+        nq = len(self.Q)
+        self.K = np.broadcast_to(np.asarray(K), (nq,))
+        self.nprobe = np.broadcast_to(np.asarray(nprobe), (nq,))
+        self.ids, _, self.logs = run(self.Q, K, nprobe, None, True)
+
+    def rerun(self, qi, keys):
+        ids, _, _ = self.run(self.Q[qi:qi + 1], int(self.K[qi]), int(self.nprobe[qi]), {0: set(keys)}, False)
+        return ids[0]
+
+    def near(self, qi, tol=EXCUSE_TOL):
+        """Decision keys of query qi within relative margin tol, nearest first."""
+        return [k for m, k in self.logs["events"][qi] if m <= tol]
+
+
+def oracle_ivf(oi, Q, K, nprobe, delta_d, **kw):
+    """The oracle's IVF search (``ivf.search`` keywords: mode, schedule, fill_min, growth, rerank)."""
+    def run(Qs, Ks, nps, flips, log):
+        out = ivf.search(oi, Qs, Ks, nps, delta_d, log=log, flips=flips, event_tol=EVENT_TOL, **kw)
+        return out if log else (*out, None)
+    return OracleRun(run, Q, K, nprobe)
+
+
+def oracle_graph(oi, nb, en, Q, K, ef, n_entry, delta_d, **kw):
+    """The oracle's beam search over an exported graph (``graph.search`` keywords)."""
+    def run(Qs, Ks, _, flips, log):
+        return graph.search(oi, nb, en, Qs, Ks, ef, n_entry, delta_d, log=log, flips=flips,
+                            event_tol=EVENT_TOL, **kw)
+    return OracleRun(run, Q, K, n_entry)
+
+
 def exact_d2(X, Q, ids):
     out = np.full(ids.shape, np.inf)
     for qi in range(ids.shape[0]):
@@ -33,13 +82,29 @@ def exact_d2(X, Q, ids):
     return out
 
 
-def compare(o_ids, logs, g_ids, g_d2, X, Q, K, rtol=DIST_RTOL, margin_tol=MARGIN_TOL, max_excused=0.02):
-    """Element-wise parity of a GPU search against the oracle.  Returns the excused count."""
-    nq = o_ids.shape[0]
-    Ks = np.broadcast_to(np.asarray(K), (nq,))
+def explain(o: OracleRun, qi, gpu_ids, k):
+    """The near-tie decision(s) whose flip makes the oracle return the GPU's id set for query qi,
+    or None."""
+    want = set(int(x) for x in gpu_ids[:k])
+    keys = o.near(qi)
+    for key in keys[:MAX_SINGLE]:
+        if set(int(x) for x in o.rerun(qi, [key])[:k]) == want:
+            return [key]
+    for pair in itertools.combinations(keys[:MAX_PAIR], 2):
+        if set(int(x) for x in o.rerun(qi, pair)[:k]) == want:
+            return list(pair)
+    return None
+
+
+def compare(o: OracleRun, g_ids, g_d2, X, Q, K, rtol=DIST_RTOL, max_excused=0.01, rows=None):
+    """Element-wise parity of a GPU search against the oracle run ``o``; ``rows`` maps the oracle's
+    queries to rows of the GPU output (default: the same rows).  Returns the excused count."""
+    nq = len(o.Q)
+    rows = np.arange(nq) if rows is None else np.asarray(rows)
+    Ks = np.broadcast_to(np.asarray(K), (len(g_ids),))
     ex = exact_d2(X, Q, g_ids)
-    excused = 0
-    for qi in range(nq):
+    excused = []
+    for j, qi in enumerate(rows):
         k = int(Ks[qi])
         gi, gd = g_ids[qi], g_d2[qi]
         assert np.all(gi[k:] == -1) and np.all(np.isinf(gd[k:])), qi
@@ -49,15 +114,16 @@ def compare(o_ids, logs, g_ids, g_d2, X, Q, K, rtol=DIST_RTOL, margin_tol=MARGIN
         # rows ascend by (dist2, id)
         keys = list(zip(gd[:k][v].tolist(), gi[:k][v].tolist()))
         assert keys == sorted(keys), qi
-        if set(gi[:k].tolist()) == set(o_ids[qi, :k].tolist()):
+        if set(gi[:k].tolist()) == set(o.ids[j, :k].tolist()):
             continue
-        if logs is not None and (logs["min_margin"][qi] <= margin_tol or logs["probe_gap"][qi] <= margin_tol):
-            excused += 1
-            continue
-        raise AssertionError(f"query {qi}: ids differ without a near tie: gpu {gi[:k]} oracle {o_ids[qi, :k]} "
-                             f"margin {logs['min_margin'][qi] if logs else None}")
-    assert excused <= max(1, int(max_excused * nq)), excused
-    return excused
+        why = explain(o, j, gi, k)
+        if why is None:
+            ev = o.logs["events"][j][:5]
+            raise AssertionError(f"query {qi}: ids differ and no flip of a decision within {EXCUSE_TOL} explains it: "
+                                 f"gpu {gi[:k]} oracle {o.ids[j, :k]}; nearest decisions {ev}")
+        excused.append((int(qi), why))
+    assert len(excused) <= max(1, int(max_excused * nq)), excused
+    return len(excused)
 
 
 def to_np(t):

@@ -68,7 +68,37 @@ def test_new_entry_points_reject_null_handles_before_touching_a_device():
         pytest.skip("libdade.so not built")
     L = dade.lib()
     assert L.dade_autotune(None, None, 1, 10, 8, None, None, 0.5, 1, None, None, None, None) == dade.DADE_EINVAL
-    assert L.dade_graph_build(None, None, 16, 8, 4, None) == dade.DADE_EINVAL
+    assert L.dade_graph_build(None, 16, 8, 4, None) == dade.DADE_EINVAL
     assert L.dade_graph_search(None, None, 1, 10, 32, 4, 0, None, None, None, None) == dade.DADE_EINVAL
     assert L.dade_graph_export(None, None, None, None) == dade.DADE_EINVAL
     assert "NULL" in dade.dade_last_error()
+
+
+def _c_layout(struct, fields):
+    """sizeof and field offsets of a struct of include/dade.h, from a C program built with gcc."""
+    import subprocess
+    import tempfile
+    body = "\n".join(f'  printf("%zu ", offsetof({struct}, {f}));' for f in fields)
+    prog = (f'#include <stddef.h>\n#include <stdio.h>\n#include "dade.h"\nint main(void) {{\n'
+            f'  printf("%zu ", sizeof({struct}));\n{body}\n  return 0;\n}}\n')
+    with tempfile.TemporaryDirectory() as d:
+        src, exe = os.path.join(d, "layout.c"), os.path.join(d, "layout")
+        open(src, "w").write(prog)
+        subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), src, "-o", exe], check=True)
+        return [int(v) for v in subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split()]
+
+
+@pytest.mark.parametrize("struct,cls", [("dade_search_opts", "SearchOpts"), ("dade_search_record", "SearchRecord"),
+                                        ("dade_serve_opts", "ServeOpts"), ("dade_times", "Times")])
+def test_binding_structs_match_the_header_layout(struct, cls):
+    """The ctypes mirrors of the option and record structs have the C layout field for field (the
+    search record carries Delta_d, the schedule, the rerank rule and the nprobe clamp)."""
+    import shutil
+    if shutil.which("gcc") is None:
+        pytest.skip("no C compiler")
+    from paper_2411_17229_amd import dade
+    c = getattr(dade, cls)
+    names = [f for f, _ in c._fields_]
+    layout = _c_layout(struct, ["lambda" if n == "lambda_" else n for n in names])
+    assert layout[0] == ctypes.sizeof(c)
+    assert layout[1:] == [getattr(c, n).offset for n in names]

@@ -7,7 +7,7 @@ import pytest
 
 from oracle import ivf
 from paper_2411_17229_amd import dade, workloads
-from gpu_helpers import artifacts, compare, oracle_index, to_np
+from gpu_helpers import artifacts, compare, oracle_ivf, oracle_index, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -57,9 +57,9 @@ def test_chosen_options_match_the_oracle(env):
     chosen, _ = dade.dade_autotune(env["gi"], env["Qd"], w.k, w.nprobe, min_agreement=0.9, reps=2)
     ids, d2 = dade.dade_search(env["gi"], env["Qd"], w.k, w.nprobe, **chosen)
     torch.cuda.synchronize()
-    o_ids, _, logs = ivf.search(env["oi"], env["Q"], w.k, w.nprobe, chosen["delta_d"], log=True,
-                                schedule=chosen["schedule"], fill_min=chosen["fill_min"], growth=chosen["growth"])
-    compare(o_ids, logs, to_np(ids), to_np(d2), env["X"], env["Q"], w.k)
+    o = oracle_ivf(env["oi"], env["Q"], w.k, w.nprobe, chosen["delta_d"],
+                   schedule=chosen["schedule"], fill_min=chosen["fill_min"], growth=chosen["growth"])
+    compare(o, to_np(ids), to_np(d2), env["X"], env["Q"], w.k)
 
 
 def test_launch_shape_does_not_change_results(env):
@@ -86,11 +86,11 @@ def test_autotune_uneven_batch(env):
         best = max(t["agreement"] for t in grid)
         assert [t for t in grid if t["delta_d"] == chosen["delta_d"] and t["schedule"] == chosen["schedule"]
                 and t["growth"] == chosen["growth"]][0]["agreement"] == best
-    o_ids, _, logs = ivf.search(env["oi"], env["Q"], K, np.minimum(npb, w.nlist), chosen["delta_d"], log=True,
-                                schedule=chosen["schedule"], fill_min=chosen["fill_min"], growth=chosen["growth"])
+    o = oracle_ivf(env["oi"], env["Q"], K, np.minimum(npb, w.nlist), chosen["delta_d"],
+                   schedule=chosen["schedule"], fill_min=chosen["fill_min"], growth=chosen["growth"])
     ids, d2 = dade.dade_search(env["gi"], env["Qd"], 100, 40, k_per_query=kp, nprobe_per_query=npp, **chosen)
     torch.cuda.synchronize()
-    compare(o_ids, logs, to_np(ids), to_np(d2), env["X"], env["Q"], K)
+    compare(o, to_np(ids), to_np(d2), env["X"], env["Q"], K)
 
 
 def test_autotune_argument_errors(env):

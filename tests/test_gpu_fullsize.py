@@ -11,11 +11,12 @@ import pytest
 
 from oracle import estimator, ivf, lowp
 from paper_2411_17229_amd import dade, workloads
-from gpu_helpers import DIST_RTOL, MARGIN_TOL, exact_d2, to_np
+from gpu_helpers import DIST_RTOL, EXCUSE_TOL, compare, exact_d2, oracle_ivf, to_np
 
 pytestmark = pytest.mark.gpu
 
 SCHEDULE = dict(schedule="doubling", fill_min=32, growth=0)   # the bench's
+RERANK = "all"                                                 # the bench's low-precision rerank rule
 
 
 def _need_gpu():
@@ -47,7 +48,7 @@ def run_workload(name, p_s, nprobe, n_sample, k_per_query=None, nprobe_per_query
     dade.dade_rotate(gi)
     dade.dade_calibrate(gi, p_s, pairs=workloads.calibration_pairs(w.n, 100_000, w.seed))
     K = k or w.k
-    kw = dict(delta_d=w.delta_d, **SCHEDULE)
+    kw = dict(delta_d=w.delta_d, rerank_rule=RERANK, **SCHEDULE)
     kp = None if k_per_query is None else torch.from_numpy(k_per_query).to(dev)
     npp = None if nprobe_per_query is None else torch.from_numpy(nprobe_per_query).to(dev)
     if tune is not None:   # Delta_d, round and launch shape from the autotuner on the first `tune` queries
@@ -73,25 +74,21 @@ def run_workload(name, p_s, nprobe, n_sample, k_per_query=None, nprobe_per_query
         np.testing.assert_allclose(d2[qi, :kq], ex[qi, :kq], rtol=DIST_RTOL, err_msg=f"query {qi}")
         keys = list(zip(d2[qi, :kq].tolist(), ids[qi, :kq].tolist()))
         assert keys == sorted(keys), qi
-    # sampled queries: the oracle on the library's artifacts
+    # sampled queries: the oracle on the library's artifacts, every differing id set explained by
+    # a flipped near-tie decision
     oi = oracle_from_library(gi, X, w.store)
     sample = np.sort(np.random.default_rng(7).choice(len(Q), n_sample, replace=False))
     Ko = Ks[sample]
     npo = nprobe if nprobe_per_query is None else nprobe_per_query[sample]
-    o_ids, _, logs = ivf.search(oi, Q[sample], Ko, npo, kw["delta_d"], log=True, schedule=kw["schedule"],
-                                fill_min=kw["fill_min"], growth=kw["growth"])
-    excused = 0
-    same_probes = logs["probe_gap"] > MARGIN_TOL   # no near tie in the probe order
+    o = oracle_ivf(oi, Q[sample], Ko, npo, kw["delta_d"], schedule=kw["schedule"], fill_min=kw["fill_min"],
+                   growth=kw["growth"], rerank=RERANK)
+    logs = o.logs
+    excused = compare(o, ids, d2, X, Q, Ks, rows=sample, max_excused=0.02)
+    print(f"[{name}] {n_sample} sampled queries against the oracle, {excused} excused by a flipped near tie")
+    same_probes = logs["probe_gap"] > EXCUSE_TOL   # no near tie in the probe order: the same candidates
     for j, qi in enumerate(sample):
-        kq = int(Ks[qi])
-        if same_probes[j]:   # the same candidates: one DCO each
+        if same_probes[j]:   # one DCO each
             assert st[qi, 0] == logs["dcos"][j], (qi, st[qi, 0], logs["dcos"][j])
-        if set(ids[qi, :kq].tolist()) == set(o_ids[j, :kq].tolist()):
-            continue
-        assert logs["min_margin"][j] <= MARGIN_TOL or not same_probes[j], \
-            f"query {qi}: gpu {ids[qi, :kq]} oracle {o_ids[j, :kq]} margin {logs['min_margin'][j]}"
-        excused += 1
-    assert excused <= max(1, n_sample // 4), excused
     # dimensions read agree in aggregate (single decisions may differ at near ties)
     dims_g, dims_o = st[sample, 1][same_probes].sum(), logs["dims"][same_probes].sum()
     assert abs(dims_g - dims_o) <= 0.01 * dims_o, (dims_g, dims_o)
@@ -104,12 +101,12 @@ def run_workload(name, p_s, nprobe, n_sample, k_per_query=None, nprobe_per_query
 def test_fullsize_highd_bench_configuration():
     """1M x 960, BF16 store + FP32 rerank, 1000 queries, K 10, nprobe 8, P_s 0.005: the bench's
     operating point and launch configuration."""
-    run_workload("highd-1m-d960", p_s=0.005, nprobe=8, n_sample=6)
+    run_workload("highd-1m-d960", p_s=0.005, nprobe=8, n_sample=60)
 
 
 def test_fullsize_scale_f32():
     """1M x 128, FP32 store, 10,000 queries, nlist 1024, nprobe 16, Delta_d 16."""
-    run_workload("scale-1m-d128", p_s=0.1, nprobe=16, n_sample=8)
+    run_workload("scale-1m-d128", p_s=0.1, nprobe=16, n_sample=40)
 
 
 def test_fullsize_uneven_batch():
@@ -118,7 +115,7 @@ def test_fullsize_uneven_batch():
     autotuner (on the first 512 queries), the oracle run with the chosen values."""
     w = workloads.WORKLOADS["uneven-2m-d256"]
     K, npb = workloads.uneven_batch(w.n_queries, 8, 128, (1, 10, 50, 100), seed=w.seed)
-    run_workload("uneven-2m-d256", p_s=0.1, nprobe=128, n_sample=6, k_per_query=K, nprobe_per_query=npb, k=100,
+    run_workload("uneven-2m-d256", p_s=0.1, nprobe=128, n_sample=20, k_per_query=K, nprobe_per_query=npb, k=100,
                  tune=512)
 
 
@@ -136,7 +133,7 @@ def test_fullsize_serving_mix():
     K = np.repeat(ks[:n_req], sizes[:n_req]).astype(np.int32)
     npb = np.repeat(nps[:n_req], sizes[:n_req]).astype(np.int32)
     assert nq == len(K) and nq > 100
-    ids, d2, gi, Qd, kw = run_workload("serve-5m-d768", p_s=0.1, nprobe=96, n_sample=3, k_per_query=K,
+    ids, d2, gi, Qd, kw = run_workload("serve-5m-d768", p_s=0.1, nprobe=96, n_sample=10, k_per_query=K,
                                        nprobe_per_query=npb, k=100, keep=True, n_queries=nq)
     for r in sorted({0, n_req // 2, n_req - 1}):
         a, b = int(starts[r]), int(starts[r + 1])

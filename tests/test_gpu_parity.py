@@ -5,8 +5,8 @@ import numpy as np
 import pytest
 from scipy.spatial.distance import cdist
 
-from gpu_helpers import artifacts, compare, exact_d2, gpu_search, oracle_index, to_np
-from oracle import ivf, knn, pca
+from gpu_helpers import artifacts, compare, oracle_ivf, exact_d2, gpu_search, oracle_index, to_np
+from oracle import estimator, ivf, knn, pca
 from paper_2411_17229_amd import dade, workloads
 
 pytestmark = pytest.mark.gpu
@@ -32,19 +32,20 @@ def small():
 @pytest.mark.parametrize("schedule", ["per_rank", "doubling"])
 def test_full_d_matches_oracle(small, schedule):
     w, oi = small["w"], small["oi"]
-    o_ids, _, logs = ivf.search(oi, small["Q"], w.k, w.nprobe, w.delta_d, mode="exact", log=True)
+    o = oracle_ivf(oi, small["Q"], w.k, w.nprobe, w.delta_d, mode="exact")
     g_ids, g_d2 = gpu_search(small["gi"], small["Qd"], w.k, w.nprobe, mode="full_d", schedule=schedule)
-    compare(o_ids, logs, g_ids, g_d2, small["X"], small["Q"], w.k)
+    compare(o, g_ids, g_d2, small["X"], small["Q"], w.k)
 
 
 @pytest.mark.parametrize("schedule", ["per_rank", "doubling"])
 def test_dade_matches_oracle(small, schedule):
     w, oi = small["w"], small["oi"]
-    o_ids, _, logs = ivf.search(oi, small["Q"], w.k, w.nprobe, w.delta_d, schedule=schedule, log=True)
+    o = oracle_ivf(oi, small["Q"], w.k, w.nprobe, w.delta_d, schedule=schedule)
+    logs = o.logs
     stats = torch.zeros((w.n_queries, 4), dtype=torch.int64, device="cuda")
     g_ids, g_d2 = gpu_search(small["gi"], small["Qd"], w.k, w.nprobe, delta_d=w.delta_d, schedule=schedule,
                              stats=stats)
-    compare(o_ids, logs, g_ids, g_d2, small["X"], small["Q"], w.k)
+    compare(o, g_ids, g_d2, small["X"], small["Q"], w.k)
     st = to_np(stats)
     # DCO counts are exact; dimensions read match the oracle's Algorithm 1 logs up to
     # near-tie decisions
@@ -60,12 +61,13 @@ def test_round_size_options(small, fill_min, growth, schedule):
     """First-round minimum and growth cap: the same round cuts as the oracle's, so DCO counts
     agree exactly and results agree up to near ties."""
     w, oi = small["w"], small["oi"]
-    o_ids, _, logs = ivf.search(oi, small["Q"], w.k, w.nprobe, w.delta_d, schedule=schedule, log=True,
-                                fill_min=fill_min, growth=growth)
+    o = oracle_ivf(oi, small["Q"], w.k, w.nprobe, w.delta_d, schedule=schedule,
+                   fill_min=fill_min, growth=growth)
+    logs = o.logs
     stats = torch.zeros((w.n_queries, 4), dtype=torch.int64, device="cuda")
     g_ids, g_d2 = gpu_search(small["gi"], small["Qd"], w.k, w.nprobe, delta_d=w.delta_d, schedule=schedule,
                              stats=stats, fill_min=fill_min, growth=growth)
-    compare(o_ids, logs, g_ids, g_d2, small["X"], small["Q"], w.k)
+    compare(o, g_ids, g_d2, small["X"], small["Q"], w.k)
     st = to_np(stats)
     np.testing.assert_array_equal(st[:, 0], logs["dcos"].astype(np.int64))
     rel = np.abs(st[:, 1] - logs["dims"]) / logs["dims"]
@@ -92,21 +94,76 @@ def test_graph_replays_match_eager(small, schedule):
 
 
 def test_all_lists_full_d_is_brute_force(small):
+    """FDScanning over every list is brute-force KNN: the same ids, except where the FP64
+    distances of the ids that differ tie with the K-th within the FP32 tolerance."""
     w = small["w"]
-    g_ids, g_d2 = gpu_search(small["gi"], small["Qd"][:20], 10, w.nlist, mode="full_d")
-    gt, gd = knn.brute_force(small["X"], small["Q"][:20], 10)
-    assert (g_ids == gt).mean() > 0.99
+    g_ids, g_d2 = gpu_search(small["gi"], small["Qd"][:40], 10, w.nlist, mode="full_d")
+    gt, gd = knn.brute_force(small["X"], small["Q"][:40], 10)
     np.testing.assert_allclose(g_d2, gd, rtol=1e-5)
+    ex = exact_d2(small["X"], small["Q"][:40], g_ids)
+    for qi in range(len(gt)):
+        for i in set(g_ids[qi].tolist()) ^ set(gt[qi].tolist()):
+            d = ex[qi][g_ids[qi] == i][0] if i in g_ids[qi] else gd[qi][gt[qi] == i][0]
+            assert abs(d - gd[qi, -1]) <= 1e-5 * gd[qi, -1], (qi, i)
+
+
+def _integer_index(store, delta):
+    """An index on which every FP32 operation of the search is exact: integer coordinates in
+    [0, 3] (duplicate rows included), W = I, mu = 0, integer centroids (some rows), lists by
+    nearest centroid (ties to the lower list id), and thresholds T_d = (128 d + 1) / 4096, whose
+    products with the integer r^2 (< 4096) are exact in FP32 and never equal an integer S_d."""
+    rng = np.random.default_rng(77)
+    D, n, nlist = 32, 3000, 16
+    X = rng.integers(0, 4, (n, D)).astype(np.float32)
+    X[2500:2800] = X[rng.integers(0, 2500, 300)]            # duplicate rows
+    Q = rng.integers(0, 4, (60, D)).astype(np.float32)
+    Q[:15] = X[rng.integers(0, n, 15)]                      # queries at distance 0 from some rows
+    C = X[rng.choice(2500, nlist, replace=False)].astype(np.float64)
+    lab = ivf.assign(X, C)
+    off, ids = ivf.build_lists(lab, nlist)
+    lam = np.arange(D, 0, -1, dtype=np.float64)
+    T = np.array([(128 * d + 1) / 4096 for d in range(1, D)] + [1.0])
+    eps = np.sqrt(T * estimator.scale(lam)) - 1.0
+    Y = X.astype(np.float64)
+    oi = ivf.Index(np.zeros(D), np.eye(D), lam, eps, C, off, ids, Y, T=T,
+                   Y_exact=None if store == "f32" else Y, delta=0.0 if store == "f32" else delta)
+    return X, Q, oi
+
+
+@pytest.mark.parametrize("store,rule", [("f32", "all"), ("bf16", "all"), ("bf16", "lazy")])
+def test_exact_integer_inputs_match_bit_for_bit(store, rule):
+    """Where FP32 is exact, nothing may be excused: every query's ids, distances (bit for bit),
+    DCO count and dimensions read equal the oracle's, over schedules, round shapes, K and
+    Delta_d -- including exact distance ties (duplicate rows) broken by id on the device."""
+    _need_gpu()
+    delta = 2.0 ** -10
+    X, Q, oi = _integer_index(store, delta)
+    gi = dade.dade_import(artifacts(oi), torch.from_numpy(X).cuda(), store=store)
+    Qd = torch.from_numpy(Q).cuda()
+    for K, npb, dd, sched, fill, growth in ((10, 3, 8, "per_rank", 32, 16), (10, 4, 8, "doubling", 32, 0),
+                                            (1, 2, 8, "per_rank", 0, 0), (25, 5, 16, "doubling", 0, 2),
+                                            (7, 16, 4, "doubling", 32, 0)):
+        kw = dict(schedule=sched, fill_min=fill, growth=growth)
+        o_ids, o_d2, logs = ivf.search(oi, Q, K, npb, dd, log=True, rerank=rule, **kw)
+        stats = torch.zeros((len(Q), 4), dtype=torch.int64, device="cuda")
+        g_ids, g_d2 = gpu_search(gi, Qd, K, npb, delta_d=dd, stats=stats, rerank_delta=delta, rerank_rule=rule, **kw)
+        st = to_np(stats)
+        assert np.array_equal(g_ids, o_ids), (K, npb, dd, sched)
+        assert np.array_equal(g_d2.astype(np.float64), o_d2), (K, npb, dd, sched)
+        np.testing.assert_array_equal(st[:, 0], logs["dcos"].astype(np.int64))
+        np.testing.assert_array_equal(st[:, 1], logs["dims"].astype(np.int64))
+        assert (g_d2[:15, 0] == 0).all()          # the queries that are rows find them at distance 0
+    gi.close()
 
 
 def test_uneven_k_and_nprobe(small):
     w, oi = small["w"], small["oi"]
     K, npb = workloads.uneven_batch(w.n_queries, 1, 40, (1, 10, 50, 100), seed=3)
-    o_ids, _, logs = ivf.search(oi, small["Q"], K, np.minimum(npb, w.nlist), w.delta_d, log=True)
+    o = oracle_ivf(oi, small["Q"], K, np.minimum(npb, w.nlist), w.delta_d)
     g_ids, g_d2 = gpu_search(small["gi"], small["Qd"], 100, 40, delta_d=w.delta_d,
                              k_per_query=torch.from_numpy(K).cuda(),
                              nprobe_per_query=torch.from_numpy(npb).cuda())
-    compare(o_ids, logs, g_ids, g_d2, small["X"], small["Q"], K)
+    compare(o, g_ids, g_d2, small["X"], small["Q"], K)
 
 
 def test_batch_invariance_bitwise(small):
@@ -128,9 +185,9 @@ def test_batch_invariance_bitwise(small):
 def test_delta_d_variants(small, dd):
     """Delta_d not a multiple of 8 (per-dimension tests), several tests per chunk, none."""
     w, oi = small["w"], small["oi"]
-    o_ids, _, logs = ivf.search(oi, small["Q"], w.k, w.nprobe, dd, log=True)
+    o = oracle_ivf(oi, small["Q"], w.k, w.nprobe, dd)
     g_ids, g_d2 = gpu_search(small["gi"], small["Qd"], w.k, w.nprobe, delta_d=dd)
-    compare(o_ids, logs, g_ids, g_d2, small["X"], small["Q"], w.k)
+    compare(o, g_ids, g_d2, small["X"], small["Q"], w.k)
 
 
 def test_k_larger_than_candidates_pads():
@@ -138,9 +195,9 @@ def test_k_larger_than_candidates_pads():
     X, Q = workloads.make_mixture(300, 40, 4, 1.2, 6, seed=8)
     oi, _, _ = oracle_index(X, 32, 8, n_pairs=5000)
     gi = dade.dade_import(artifacts(oi), torch.from_numpy(X).cuda())
-    o_ids, _, logs = ivf.search(oi, Q, 128, 1, 8, log=True)
+    o = oracle_ivf(oi, Q, 128, 1, 8)
     g_ids, g_d2 = gpu_search(gi, torch.from_numpy(Q).cuda(), 128, 1, delta_d=8)
-    compare(o_ids, logs, g_ids, g_d2, X, Q, 128)
+    compare(o, g_ids, g_d2, X, Q, 128)
     assert (g_ids == -1).any()   # one list holds fewer than 128 rows
 
 
@@ -151,9 +208,9 @@ def test_odd_dimension_and_nprobe_clamp():
     oi, _, _ = oracle_index(X, 16, 9, n_pairs=20000)
     gi = dade.dade_import(artifacts(oi), torch.from_numpy(X).cuda())
     for K, npb, dd in ((1, 100, 24), (7, 3, 25)):
-        o_ids, _, logs = ivf.search(oi, Q, K, npb, dd, log=True)
+        o = oracle_ivf(oi, Q, K, npb, dd)
         g_ids, g_d2 = gpu_search(gi, torch.from_numpy(Q).cuda(), K, npb, delta_d=dd)
-        compare(o_ids, logs, g_ids, g_d2, X, Q, K)
+        compare(o, g_ids, g_d2, X, Q, K)
 
 
 def test_empty_batch_is_a_noop(small):
@@ -223,8 +280,9 @@ def test_low_precision_store(small, store):
     gl.close()
 
 
+@pytest.mark.parametrize("rule", ["all", "lazy"])
 @pytest.mark.parametrize("store,delta", [("bf16", 0.02), ("f16", 0.002), ("bf16", 0.0)])
-def test_low_precision_rerank_rule_parity(store, delta):
+def test_low_precision_rerank_rule_parity(store, delta, rule):
     """With W = I and mu = 0 the library's stored coordinates are exactly the oracle's rounded
     X, so the rerank rule (gate, K smallest, bound from the K-th exact) is compared ID for ID."""
     _need_gpu()
@@ -241,10 +299,10 @@ def test_low_precision_rerank_rule_parity(store, delta):
                    Y_exact=X.astype(np.float64), delta=delta, T=T)
     gi = dade.dade_import(artifacts(oi), torch.from_numpy(X).cuda(), store=store)
     for K, npb, sched in ((10, 4, "per_rank"), (25, 6, "doubling"), (1, 3, "per_rank")):
-        o_ids, _, logs = ivf.search(oi, Q, K, npb, 16, schedule=sched, log=True)
+        o = oracle_ivf(oi, Q, K, npb, 16, schedule=sched, rerank=rule)
         g_ids, g_d2 = gpu_search(gi, torch.from_numpy(Q).cuda(), K, npb, delta_d=16, schedule=sched,
-                                 rerank_delta=delta)
-        compare(o_ids, logs, g_ids, g_d2, X, Q, K)
+                                 rerank_delta=delta, rerank_rule=rule)
+        compare(o, g_ids, g_d2, X, Q, K)
     gi.close()
 
 
@@ -265,10 +323,11 @@ def test_data_oblivious_rotation_matches_oracle():
     gi = dade.dade_import(art, Xd)
     dade.dade_calibrate(gi, w.alpha, pairs=pairs)
     assert np.max(np.abs(dade.dade_export(gi)["T"] - oi.T)) < 1e-9
-    o_ids, _, logs = ivf.search(oi, Q, w.k, w.nprobe, w.delta_d, schedule="doubling", log=True)
+    o = oracle_ivf(oi, Q, w.k, w.nprobe, w.delta_d, schedule="doubling")
+    logs = o.logs
     stats = torch.zeros((w.n_queries, 4), dtype=torch.int64, device="cuda")
     g_ids, g_d2 = gpu_search(gi, Qd, w.k, w.nprobe, delta_d=w.delta_d, schedule="doubling", stats=stats)
-    compare(o_ids, logs, g_ids, g_d2, X, Q, w.k)
+    compare(o, g_ids, g_d2, X, Q, w.k)
     st = to_np(stats)
     np.testing.assert_array_equal(st[:, 0], logs["dcos"].astype(np.int64))
     rel = np.abs(st[:, 1] - logs["dims"]) / logs["dims"]
@@ -287,10 +346,11 @@ def test_linear_scan_one_list(dd):
     gi = dade.dade_import(artifacts(oi), torch.from_numpy(X).cuda())
     Qd = torch.from_numpy(Q).cuda()
     sched = dict(schedule="doubling", fill_min=32, growth=16)
-    o_ids, _, logs = ivf.search(oi, Q, w.k, 1, dd, log=True, **sched)
+    o = oracle_ivf(oi, Q, w.k, 1, dd, **sched)
+    logs = o.logs
     stats = torch.zeros((len(Q), 4), dtype=torch.int64, device="cuda")
     g_ids, g_d2 = gpu_search(gi, Qd, w.k, 1, delta_d=dd, stats=stats, **sched)
-    compare(o_ids, logs, g_ids, g_d2, X, Q, w.k)
+    compare(o, g_ids, g_d2, X, Q, w.k)
     st = to_np(stats)
     np.testing.assert_array_equal(st[:, 0], logs["dcos"].astype(np.int64))
     rel = np.abs(st[:, 1] - logs["dims"]) / logs["dims"]

@@ -7,7 +7,7 @@ import pytest
 
 from oracle import ivf
 from paper_2411_17229_amd import dade, workloads
-from gpu_helpers import artifacts, compare, oracle_index, to_np
+from gpu_helpers import artifacts, compare, oracle_ivf, oracle_index, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -103,9 +103,9 @@ def test_poisson_arrivals_match_alone_and_oracle(env):
     check_against_alone(env, sizes, ks, nps, ids, d2)
     K = np.repeat(ks, sizes)
     npb = np.repeat(nps, sizes)
-    o_ids, _, logs = ivf.search(env["oi"], Qs, K, np.minimum(npb, env["w"].nlist), 32, log=True, schedule="doubling",
-                                fill_min=32, growth=0)
-    compare(o_ids, logs, ids, d2, env["X"], Qs, K)
+    o = oracle_ivf(env["oi"], Qs, K, np.minimum(npb, env["w"].nlist), 32, schedule="doubling",
+                   fill_min=32, growth=0)
+    compare(o, ids, d2, env["X"], Qs, K)
 
 
 @pytest.mark.parametrize("pinned", [False, True])
