@@ -208,6 +208,23 @@ int dade_search(dade_index* ix, const float* Q, int64_t nq, int32_t k, int32_t n
                 const dade_search_opts* opts, int64_t* out_ids, float* out_dist2,
                 void* stream);
 
+/*
+ * dade_search_noalloc -- dade_search for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.  Same arguments,
+ * results (bit for bit) and stream semantics as dade_search; it calls no hipMalloc, hipFree or
+ * other allocating routine.  Its workspace is a fixed scratch array of 64 MiB per device, held by
+ * the library from the first call on that device until the process ends, instead of the index's
+ * growable workspace.  The batch runs in slices of as many queries as the scratch holds; a search
+ * one query of which needs more than 64 MiB (a huge widest round: large lists, nprobe and K) is
+ * rejected with DADE_EINVAL before any device work.  Nothing is captured into a graph: use_graph
+ * is ignored and record_times is rejected (DADE_EINVAL).  The index must live on the current
+ * device.  Every call on one device shares that device's scratch: calls that overlap on one
+ * device (other streams, other threads) race and give undefined results; serialise them.
+ */
+int dade_search_noalloc(dade_index* ix, const float* Q, int64_t nq, int32_t k, int32_t nprobe,
+                        const int32_t* k_per_query, const int32_t* nprobe_per_query,
+                        const dade_search_opts* opts, int64_t* out_ids, float* out_dist2, void* stream);
+
 /* dade_check -- synchronises `stream` and reports DADE_EDEVICE if any search on this index
  * since its creation exceeded an internal capacity of the list scan (its results would be
  * incomplete); DADE_OK otherwise.  The capacities are sized so that this does not happen; the

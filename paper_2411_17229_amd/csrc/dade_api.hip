@@ -218,6 +218,8 @@ int make_index(const float* X, int64_t n, int32_t dim, int32_t nlist, const dade
   ix->n = n; ix->dim = dim; ix->dp = pad_dim(dim); ix->nlist = nlist; ix->store = store;
   ix->budget = opts ? opts->hbm_budget_bytes : 0;
   if ((rc = alloc_t(ix, &ix->X, size_t(n) * ix->dp))) { dade_destroy(ix); return rc; }
+  if ((rc = alloc_t(ix, &ix->w_flags, 1))) { dade_destroy(ix); return rc; }
+  if (launch_fill_i32(ix->w_flags, 1, 0, s) != hipSuccess) { dade_destroy(ix); FAIL(DADE_EDEVICE, "clear flags"); }
   hipError_t e = launch_pad_rows(X, n, dim, dim, ix->X, ix->dp, s);
   if (e != hipSuccess) { dade_destroy(ix); FAIL(DADE_EDEVICE, hip_msg(e, "pad X")); }
   *out = ix;
@@ -339,14 +341,29 @@ constexpr int64_t kPassWorkspaceBytes = int64_t(8) << 30;
 // Sizes of one search's round workspace, from the list sizes, K, nprobe and the schedule.
 struct SearchPlan {
   int npm = 0, widest = 1, rounds = 0;
-  int64_t kb_cap = 0, first = 0, items_pq = 0, chunk = 0;
+  int64_t kb_cap = 0, first = 0, items_pq = 0;
+  int64_t per_q = 0;   // round-workspace bytes per query of a pass
 };
 
-// The plan of a search of nq queries (k, nprobe: the largest per-query values) and its workspace,
-// grown on demand (growing synchronises `s`; a workspace already large enough is reused as is).
-int plan_search(dade_index* ix, int64_t nq, int32_t k, int32_t nprobe, const dade_search_opts& o,
-                hipStream_t s, SearchPlan& pl) {
-  int rc;
+// Where one search's buffers live: the index's workspace (grown on demand) or a fixed region.
+struct Workspace {
+  float* qpad = nullptr;             // [nq x dp] padded queries (when not read in place)
+  float* qrot = nullptr;             // [nq x dp] rotated queries
+  float* pd = nullptr;               // [nq x nlist] centroid terms
+  int32_t* probes = nullptr;         // [nq x npm]
+  unsigned long long* topk = nullptr;   // [chunk x k]
+  unsigned long long* keyr = nullptr;   // [chunk]
+  float* r2 = nullptr;               // [chunk]
+  int* qint = nullptr;               // [chunk x 3]
+  unsigned long long* kb = nullptr;  // [chunk x kb_cap]
+  int4* items = nullptr;             // [rounds x chunk x items_pq]
+  int* counter = nullptr;            // [rounds]
+  int* counts = nullptr;             // [rounds x chunk]
+  int64_t chunk = 0;                 // queries per pass of the list scan
+};
+
+// The plan of a search (k, nprobe: the largest per-query values); no device work.
+SearchPlan plan_sizes(const dade_index* ix, int32_t k, int32_t nprobe, const dade_search_opts& o) {
   const int nl = ix->nlist;
   const int npm = std::min<int>(nprobe, nl);
   // the most candidates one round can hold (per-rank: one list; doubling: its widest round)
@@ -373,24 +390,32 @@ int plan_search(dade_index* ix, int64_t nq, int32_t k, int32_t nprobe, const dad
   // work items of one query in one round: its segments cut at 16 candidates (whole-row rounds;
   // other rounds use 64)
   const int64_t items_pq = std::max<int64_t>((kb_cap + 15) / 16 + widest + 1, (first + 15) / 16 + npm);
+  SearchPlan pl;
+  pl.npm = npm; pl.widest = widest; pl.rounds = rounds;
+  pl.kb_cap = kb_cap; pl.first = first; pl.items_pq = items_pq;
+  pl.per_q = kb_cap * 8 + rounds * (items_pq * 16 + 4) + int64_t(k) * 8 + 48;
+  return pl;
+}
+
+// The index's workspace for a search of nq queries under plan pl, grown on demand (growing
+// synchronises `s`; a workspace already large enough is reused as is).
+int grow_workspace(dade_index* ix, int64_t nq, int32_t k, const SearchPlan& pl, hipStream_t s, Workspace& ws) {
+  int rc;
   // queries per pass: the round workspace stays under kPassWorkspaceBytes
-  const int64_t per_q = kb_cap * 8 + rounds * (items_pq * 16 + 4) + int64_t(k) * 8 + 48;
   const int64_t chunk =
-      std::max<int64_t>(1, std::min<int64_t>({nq, kPassWorkspaceBytes / per_q, int64_t(kMaxPassQueries)}));
-  if ((rc = grow_query_workspace(ix, nq, npm, s))) return rc;
+      std::max<int64_t>(1, std::min<int64_t>({nq, kPassWorkspaceBytes / pl.per_q, int64_t(kMaxPassQueries)}));
+  if ((rc = grow_query_workspace(ix, nq, pl.npm, s))) return rc;
   if ((rc = grow(ix, &ix->w_topk, ix->w_topk_n, chunk * k, s)) || (rc = grow(ix, &ix->w_keyr, ix->w_keyr_n, chunk, s)) ||
       (rc = grow(ix, &ix->w_r2, ix->w_r2_n, chunk, s)) || (rc = grow(ix, &ix->w_qint, ix->w_qint_n, chunk * 3, s)) ||
-      (rc = grow(ix, &ix->w_kb, ix->w_kb_n, chunk * kb_cap, s)) ||
-      (rc = grow(ix, &ix->w_items, ix->w_items_n, int64_t(rounds) * chunk * items_pq, s)) ||
-      (rc = grow(ix, &ix->w_counter, ix->w_counter_n, rounds, s)) ||
-      (rc = grow(ix, &ix->w_counts, ix->w_counts_n, int64_t(rounds) * chunk, s)))
+      (rc = grow(ix, &ix->w_kb, ix->w_kb_n, chunk * pl.kb_cap, s)) ||
+      (rc = grow(ix, &ix->w_items, ix->w_items_n, int64_t(pl.rounds) * chunk * pl.items_pq, s)) ||
+      (rc = grow(ix, &ix->w_counter, ix->w_counter_n, pl.rounds, s)) ||
+      (rc = grow(ix, &ix->w_counts, ix->w_counts_n, int64_t(pl.rounds) * chunk, s)))
     return rc;
-  if (!ix->w_flags) {
-    if ((rc = alloc_t(ix, &ix->w_flags, 1))) return rc;
-    HIPC(launch_fill_i32(ix->w_flags, 1, 0, s));
-  }
-  pl.npm = npm; pl.widest = widest; pl.rounds = rounds;
-  pl.kb_cap = kb_cap; pl.first = first; pl.items_pq = items_pq; pl.chunk = chunk;
+  ws.qpad = ix->w_qpad; ws.qrot = ix->w_qrot; ws.pd = ix->w_pd; ws.probes = ix->w_probes;
+  ws.topk = ix->w_topk; ws.keyr = ix->w_keyr; ws.r2 = ix->w_r2; ws.qint = ix->w_qint;
+  ws.kb = ix->w_kb; ws.items = ix->w_items; ws.counter = ix->w_counter; ws.counts = ix->w_counts;
+  ws.chunk = chunk;
   return DADE_OK;
 }
 
@@ -403,8 +428,9 @@ int index_alloc(dade_index* ix, void** p, size_t bytes) { return dev_alloc(ix, p
 void index_free(dade_index* ix, void* p, size_t bytes) { dev_free(ix, p, bytes); }
 int index_prepare_search(dade_index* ix, int64_t nq, int32_t k, int32_t nprobe, const dade_search_opts& o,
                          hipStream_t s, int64_t* workspace_bytes) {
-  SearchPlan pl;
-  const int rc = plan_search(ix, nq, k, nprobe, o, s, pl);
+  const SearchPlan pl = plan_sizes(ix, k, nprobe, o);
+  Workspace ws;
+  const int rc = grow_workspace(ix, nq, k, pl, s, ws);
   if (rc) return rc;
   const int64_t dp = ix->dp, nl = ix->nlist;
   *workspace_bytes = ix->w_nq * (2 * dp * 4 + nl * 4 + ix->w_np * 4) + ix->w_topk_n * 8 + ix->w_keyr_n * 8 +
@@ -414,6 +440,75 @@ int index_prepare_search(dade_index* ix, int64_t nq, int32_t k, int32_t nprobe, 
 }
 int index_dim(const dade_index* ix) { return ix->dim; }
 }  // namespace dade
+
+// ------------------------------------------------------------------------------------------------
+// Scratch of dade_search_noalloc: one array per device (the runtime places it when the library's
+// code object is loaded on that device; it is held until the process ends).  Host code never uses
+// its name as an address: each device's address is looked up once, with that device current, and
+// kept in g_scratch_addr.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_addr[kMaxDevices] = {};
+
+// The scratch array's device address on the current device `dev`.
+int scratch_address(int dev, void** out) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (dev < 0 || dev >= kMaxDevices) FAIL(DADE_EDEVICE, "device id out of range for the scratch table");
+  if (!g_scratch_addr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      (void)hipGetLastError();
+      FAIL(DADE_EDEVICE, hip_msg(e, "hipGetSymbolAddress(scratch)"));
+    }
+    g_scratch_addr[dev] = p;
+  }
+  *out = g_scratch_addr[dev];
+  return DADE_OK;
+}
+
+constexpr size_t kScratchAlign = 256;
+size_t align_up(size_t x) { return (x + kScratchAlign - 1) / kScratchAlign * kScratchAlign; }
+
+// Bytes of scratch one slice of cn queries takes under plan pl (each region 256-byte aligned).
+size_t slice_bytes(const dade_index* ix, const SearchPlan& pl, int32_t k, int64_t cn) {
+  const size_t dp = size_t(ix->dp), nl = size_t(ix->nlist), c = size_t(cn);
+  return align_up(c * dp * 4) * 2 + align_up(c * nl * 4) + align_up(c * size_t(pl.npm) * 4) +
+         align_up(c * size_t(k) * 8) + align_up(c * 8) + align_up(c * 4) + align_up(c * 12) +
+         align_up(c * size_t(pl.kb_cap) * 8) + align_up(size_t(pl.rounds) * c * size_t(pl.items_pq) * 16) +
+         align_up(size_t(pl.rounds) * 4) + align_up(size_t(pl.rounds) * c * 4);
+}
+
+// A workspace for cn queries carved out of the scratch at `base` (slice_bytes(...) bytes).
+Workspace carve(char* base, const dade_index* ix, const SearchPlan& pl, int32_t k, int64_t cn) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    char* p = base + off;
+    off += align_up(bytes);
+    return p;
+  };
+  const size_t dp = size_t(ix->dp), nl = size_t(ix->nlist), c = size_t(cn);
+  Workspace ws;
+  ws.qpad = reinterpret_cast<float*>(take(c * dp * 4));
+  ws.qrot = reinterpret_cast<float*>(take(c * dp * 4));
+  ws.pd = reinterpret_cast<float*>(take(c * nl * 4));
+  ws.probes = reinterpret_cast<int32_t*>(take(c * size_t(pl.npm) * 4));
+  ws.topk = reinterpret_cast<unsigned long long*>(take(c * size_t(k) * 8));
+  ws.keyr = reinterpret_cast<unsigned long long*>(take(c * 8));
+  ws.r2 = reinterpret_cast<float*>(take(c * 4));
+  ws.qint = reinterpret_cast<int*>(take(c * 12));
+  ws.kb = reinterpret_cast<unsigned long long*>(take(c * size_t(pl.kb_cap) * 8));
+  ws.items = reinterpret_cast<int4*>(take(size_t(pl.rounds) * c * size_t(pl.items_pq) * 16));
+  ws.counter = reinterpret_cast<int*>(take(size_t(pl.rounds) * 4));
+  ws.counts = reinterpret_cast<int*>(take(size_t(pl.rounds) * c * 4));
+  ws.chunk = cn;
+  return ws;
+}
+}  // namespace
 
 extern "C" {
 
@@ -785,7 +880,7 @@ static hipError_t enqueue_rounds(dade_index* ix, const RoundArgs& a, int rounds,
 #define ENQ(x) \
   if ((e = (x)) != hipSuccess) return e
   if (kev) ENQ(hipEventRecord(kev[0], s));
-  ENQ(launch_plan(a, ix->w_counts, s));
+  ENQ(launch_plan(a, const_cast<int*>(a.item_off), s));
   if (kev) ENQ(hipEventRecord(kev[1], s));
   for (int r = 0; r < rounds; ++r) {
     hipEvent_t* ke = kev ? kev + 2 + 3 * r : nullptr;
@@ -801,9 +896,12 @@ static hipError_t enqueue_rounds(dade_index* ix, const RoundArgs& a, int rounds,
 
 // dade_search with query rows `ldq` floats apart (the C ABI's queries are dense, ldq = dim; the
 // graph build searches the index's own padded rows, ldq = dp).
+// fixed (nullable): a workspace laid out by the caller for exactly these nq queries, used instead of the
+// index's own (nothing is allocated, the batch is one pass, and nothing is captured into a graph).
 static int search_impl(dade_index* ix, const float* Q, int64_t ldq, int64_t nq, int32_t k, int32_t nprobe,
                        const int32_t* k_per_query, const int32_t* nprobe_per_query,
-                       const dade_search_opts* opts, int64_t* out_ids, float* out_dist2, void* stream) {
+                       const dade_search_opts* opts, int64_t* out_ids, float* out_dist2, void* stream,
+                       const Workspace* fixed = nullptr) {
   if (!ix) FAIL(DADE_EINVAL, "index is NULL");
   if (nq < 0 || nq >= (int64_t(1) << 31)) FAIL(DADE_EINVAL, "nq must be in [0, 2^31)");
   if (k < 1 || k > kMaxK) FAIL(DADE_EINVAL, "k must be in [1, 128]");
@@ -831,11 +929,18 @@ static int search_impl(dade_index* ix, const float* Q, int64_t ldq, int64_t nq, 
   if (o.query_record && (rc = check_device_pointer(o.query_record, "query_record"))) return rc;
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int dp = ix->dp, nl = ix->nlist;
-  SearchPlan pl;
-  if ((rc = plan_search(ix, nq, k, nprobe, o, s, pl))) return rc;
+  const SearchPlan pl = plan_sizes(ix, k, nprobe, o);
+  Workspace ws;
+  if (fixed) {
+    ws = *fixed;
+    o.use_graph = 0;
+    o.record_times = 0;
+  } else if ((rc = grow_workspace(ix, nq, k, pl, s, ws))) {
+    return rc;
+  }
   const int npm = pl.npm, rounds = pl.rounds;
-  const int64_t kb_cap = pl.kb_cap, items_pq = pl.items_pq, chunk = pl.chunk;
-  if (!ix->cap) HIPC(hipStreamCreateWithFlags(&ix->cap, hipStreamNonBlocking));
+  const int64_t kb_cap = pl.kb_cap, items_pq = pl.items_pq, chunk = fixed ? nq : ws.chunk;
+  if (o.use_graph && !ix->cap) HIPC(hipStreamCreateWithFlags(&ix->cap, hipStreamNonBlocking));
   if (o.scan_blocks_per_cu < 0) FAIL(DADE_EINVAL, "scan_blocks_per_cu must be >= 0");
   int& occ = ix->scan_occ[ix->store][o.mode][dd % 8 != 0];
   if (occ == 0) occ = round_blocks_per_cu(ix->store, o.mode, dd);
@@ -854,16 +959,16 @@ static int search_impl(dade_index* ix, const float* Q, int64_t ldq, int64_t nq, 
   const bool q_in_place = ldq == dp && reinterpret_cast<uintptr_t>(Q) % 16 == 0 &&
                           (!o.use_graph || Q == ix->last_q);
   ix->last_q = Q;
-  const float* qpad = q_in_place ? Q : ix->w_qpad;
-  if (!q_in_place) HIPC(launch_pad_rows(Q, nq, ix->dim, ldq, ix->w_qpad, dp, s));
+  const float* qpad = q_in_place ? Q : ws.qpad;
+  if (!q_in_place) HIPC(launch_pad_rows(Q, nq, ix->dim, ldq, ws.qpad, dp, s));
   GemmArgs g;
   g.M = int(nq); g.N = dp + nl; g.K = dp;
   g.A = qpad; g.lda = dp; g.a_shift = ix->d_mu;
-  g.B = ix->d_B; g.ldb = ix->ldB; g.C = ix->w_qrot; g.ldc = dp;
-  g.split_col = dp; g.C2 = ix->w_pd; g.ldc2 = nl; g.col_norm = ix->d_cent_norm;
+  g.B = ix->d_B; g.ldb = ix->ldB; g.C = ws.qrot; g.ldc = dp;
+  g.split_col = dp; g.C2 = ws.pd; g.ldc2 = nl; g.col_norm = ix->d_cent_norm;
   HIPC(launch_gemm(g, kEpiRotateProbe, s));
   if (o.record_times) HIPC(hipEventRecord(ix->ev[1], s));
-  HIPC(launch_select_probes(ix->w_pd, nl, int(nq), nl, npm, ix->w_probes, s));
+  HIPC(launch_select_probes(ws.pd, nl, int(nq), nl, npm, ws.probes, s));
   if (o.record_times) HIPC(hipEventRecord(ix->ev[2], s));
   // a3-a6: the list scan, in rounds, `chunk` queries at a time
   RoundArgs ra;
@@ -890,18 +995,18 @@ static int search_impl(dade_index* ix, const float* Q, int64_t ldq, int64_t nq, 
     a.nq = int(cn);
     a.k_pq = k_per_query ? k_per_query + c0 : nullptr;
     a.nprobe_pq = nprobe_per_query ? nprobe_per_query + c0 : nullptr;
-    a.qrot = ix->w_qrot + c0 * dp; a.qorig = qpad + c0 * dp;
-    a.probes = ix->w_probes + c0 * npm;
+    a.qrot = ws.qrot + c0 * dp; a.qorig = qpad + c0 * dp;
+    a.probes = ws.probes + c0 * npm;
     a.out_ids = out_ids + c0 * k; a.out_d2 = out_dist2 + c0 * k;
     a.stats = o.stats ? o.stats + c0 * 4 : nullptr;
     a.q_record = o.query_record ? o.query_record + c0 * 3 : nullptr;
-    a.q_topk = ix->w_topk; a.q_keyr = ix->w_keyr; a.q_r2 = ix->w_r2;
-    a.q_topn = ix->w_qint; a.q_kc = a.q_topn + cn; a.q_rounds = a.q_topn + 2 * cn;
-    a.kb = ix->w_kb;
+    a.q_topk = ws.topk; a.q_keyr = ws.keyr; a.q_r2 = ws.r2;
+    a.q_topn = ws.qint; a.q_kc = a.q_topn + cn; a.q_rounds = a.q_topn + 2 * cn;
+    a.kb = ws.kb;
     a.items_cap = int(std::min<int64_t>(chunk * items_pq, INT32_MAX));
-    a.items = ix->w_items;
-    a.n_items = ix->w_counter; a.overflow = ix->w_flags;
-    a.item_off = ix->w_counts;
+    a.items = ws.items;
+    a.n_items = ws.counter; a.overflow = ix->w_flags;
+    a.item_off = ws.counts;
   }
   int graph_state = 0;
   if (o.record_times) {   // one set of events per pass; the reported times sum every pass
@@ -973,6 +1078,62 @@ int dade_search(dade_index* ix, const float* Q, int64_t nq, int32_t k, int32_t n
                 const dade_search_opts* opts, int64_t* out_ids, float* out_dist2, void* stream) {
   if (!ix) FAIL(DADE_EINVAL, "index is NULL");
   return search_impl(ix, Q, ix->dim, nq, k, nprobe, k_per_query, nprobe_per_query, opts, out_ids, out_dist2, stream);
+}
+
+int dade_search_noalloc(dade_index* ix, const float* Q, int64_t nq, int32_t k, int32_t nprobe,
+                        const int32_t* k_per_query, const int32_t* nprobe_per_query,
+                        const dade_search_opts* opts, int64_t* out_ids, float* out_dist2, void* stream) {
+  if (!ix) FAIL(DADE_EINVAL, "index is NULL");
+  if (nq < 0 || nq >= (int64_t(1) << 31)) FAIL(DADE_EINVAL, "nq must be in [0, 2^31)");
+  if (k < 1 || k > kMaxK) FAIL(DADE_EINVAL, "k must be in [1, 128]");
+  if (nprobe < 1) FAIL(DADE_EINVAL, "nprobe must be >= 1");
+  dade_search_opts o{};
+  o.delta_d = 0; o.mode = DADE_MODE_DADE; o.schedule = DADE_SCHED_PER_RANK; o.rerank_delta = -1.f;
+  o.fill_min = 32; o.growth = 16;
+  if (opts) o = *opts;
+  if (o.record_times) FAIL(DADE_EINVAL, "dade_search_noalloc: record_times needs events, which it does not create");
+  o.use_graph = 0;
+  if (o.fill_min < 0 || o.growth < 0) FAIL(DADE_EINVAL, "fill_min and growth must be >= 0");
+  if (nq == 0) return search_impl(ix, Q, ix->dim, 0, k, nprobe, k_per_query, nprobe_per_query, &o, out_ids, out_dist2, stream);
+  int dev = -1;
+  HIPC(hipGetDevice(&dev));
+  if (dev != ix->device)
+    FAIL(DADE_EINVAL, "dade_search_noalloc: the index lives on device " + std::to_string(ix->device) +
+                          ", the current device is " + std::to_string(dev));
+  void* base = nullptr;
+  int rc = scratch_address(dev, &base);
+  if (rc) return rc;
+  const SearchPlan pl = plan_sizes(ix, k, nprobe, o);
+  // the most queries a slice of the scratch holds (slice_bytes is affine in the query count)
+  const size_t fixed = slice_bytes(ix, pl, k, 0), per = slice_bytes(ix, pl, k, 1) - fixed;
+  int64_t slice = 0;
+  if (kScratchBytes > fixed + 13 * kScratchAlign) slice = int64_t((kScratchBytes - fixed - 13 * kScratchAlign) / per);
+  while (slice > 0 && slice_bytes(ix, pl, k, slice) > kScratchBytes) --slice;
+  if (slice < 1)
+    FAIL(DADE_EINVAL, "dade_search_noalloc: one query of this search needs " + std::to_string(fixed + per) +
+                          " bytes of scratch (k, nprobe and the round schedule set it), more than the " +
+                          std::to_string(kScratchBytes) + " bytes it has");
+  dade_search_record rec{};
+  int64_t passes = 0;
+  for (int64_t s0 = 0; s0 < nq; s0 += slice) {
+    const int64_t cn = std::min(slice, nq - s0);
+    const Workspace ws = carve(static_cast<char*>(base), ix, pl, k, cn);
+    dade_search_opts os = o;
+    os.stats = o.stats ? o.stats + s0 * 4 : nullptr;
+    os.query_record = o.query_record ? o.query_record + s0 * 3 : nullptr;
+    os.record = &rec;
+    rc = search_impl(ix, Q + s0 * ix->dim, ix->dim, cn, k, nprobe, k_per_query ? k_per_query + s0 : nullptr,
+                     nprobe_per_query ? nprobe_per_query + s0 : nullptr, &os, out_ids + s0 * k, out_dist2 + s0 * k,
+                     stream, &ws);
+    if (rc) return rc;
+    ++passes;
+  }
+  if (o.record) {
+    *o.record = rec;
+    o.record->passes = int(passes);
+    o.record->graph = 0;
+  }
+  return DADE_OK;
 }
 
 int dade_check(dade_index* ix, void* stream) {

@@ -22,7 +22,8 @@ MODES = {"dade": 0, "full_d": 1}
 SCHEDULES = {"per_rank": 0, "doubling": 1}
 RERANK_RULES = {"all": 0, "lazy": 1}
 STATE_BUILT, STATE_ROTATED, STATE_CALIBRATED = 1, 2, 3
-EXPORTED = ("dade_build_index", "dade_rotate", "dade_calibrate", "dade_search", "dade_check", "dade_index_info",
+EXPORTED = ("dade_build_index", "dade_rotate", "dade_calibrate", "dade_search", "dade_search_noalloc",
+            "dade_check", "dade_index_info",
             "dade_export", "dade_import", "dade_stage_times", "dade_serve", "dade_autotune", "dade_graph_build",
             "dade_graph_search", "dade_graph_export", "dade_destroy", "dade_last_error")
 TUNE_MAX = 24
@@ -106,6 +107,7 @@ def lib():
         L.dade_rotate.argtypes = [vp, vp]
         L.dade_calibrate.argtypes = [vp, ctypes.c_double, vp, i64, u64, vp]
         L.dade_search.argtypes = [vp, vp, i64, i32, i32, vp, vp, ctypes.POINTER(SearchOpts), vp, vp, vp]
+        L.dade_search_noalloc.argtypes = L.dade_search.argtypes
         L.dade_check.argtypes = [vp, vp]
         L.dade_index_info.argtypes = [vp] + [ctypes.POINTER(t) for t in (i64, i32, i32, i32, i32)]
         L.dade_export.argtypes = [vp, ctypes.POINTER(Artifacts)]
@@ -139,6 +141,23 @@ def _stream(stream):
     return ctypes.c_void_p(s.cuda_stream)
 
 
+def _shape(t, shape, name):
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, not {tuple(t.shape)}")
+
+
+def _search_args(ix, Q, k, out_ids, out_dist2, k_per_query, nprobe_per_query, stats, query_record):
+    """Shape checks of a search's tensors (the library reads and writes exactly these extents)."""
+    nq = Q.shape[0]
+    _shape(Q, (nq, ix.dim), "Q")
+    _shape(out_ids, (nq, k), "out_ids")
+    _shape(out_dist2, (nq, k), "out_dist2")
+    for t, shape, name in ((k_per_query, (nq,), "k_per_query"), (nprobe_per_query, (nq,), "nprobe_per_query"),
+                           (stats, (nq, 4), "stats"), (query_record, (nq, 3), "query_record")):
+        if t is not None:
+            _shape(t, shape, name)
+
+
 def _dev(t, dtype, name):
     import torch
     if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != dtype or not t.is_contiguous():
@@ -151,6 +170,13 @@ class Index:
 
     def __init__(self, handle):
         self.handle = handle
+        self._dim = None
+
+    @property
+    def dim(self):
+        if self._dim is None:
+            self._dim = dade_index_info(self)["dim"]
+        return self._dim
 
     def info(self):
         return dade_index_info(self)
@@ -221,6 +247,7 @@ def dade_search(ix: Index, Q, k, nprobe, k_per_query=None, nprobe_per_query=None
         out_ids = torch.empty((nq, k), dtype=torch.int64, device=Q.device)
     if out_dist2 is None:
         out_dist2 = torch.empty((nq, k), dtype=torch.float32, device=Q.device)
+    _search_args(ix, Q, k, out_ids, out_dist2, k_per_query, nprobe_per_query, stats, query_record)
     o = _search_opts(delta_d, mode, schedule, rerank_delta, fill_min, growth, use_graph, scan_blocks_per_cu,
                      rerank_rule)
     o.stats = None if stats is None else _dev(stats, torch.int64, "stats").value
@@ -234,6 +261,31 @@ def dade_search(ix: Index, Q, k, nprobe, k_per_query=None, nprobe_per_query=None
     _check(lib().dade_search(ix.handle, qp, nq, k, nprobe, kp, npp, ctypes.byref(o),
                              _dev(out_ids, torch.int64, "out_ids"),
                              _dev(out_dist2, torch.float32, "out_dist2"), _stream(stream)))
+    if record is not None:
+        record.update(_record_dict(rec))
+    return out_ids, out_dist2
+
+
+def dade_search_noalloc(ix: Index, Q, k, nprobe, out_ids, out_dist2, k_per_query=None, nprobe_per_query=None,
+                        delta_d=0, mode="dade", schedule="per_rank", rerank_delta=-1.0, stats=None, stream=None,
+                        fill_min=32, growth=16, scan_blocks_per_cu=0, rerank_rule="all", record=None,
+                        query_record=None):
+    """dade_search without device allocation: the caller passes the output tensors ([nq, k] int64 and
+    float32), the library works in its fixed per-device scratch.  Asynchronous."""
+    import torch
+    _search_args(ix, Q, k, out_ids, out_dist2, k_per_query, nprobe_per_query, stats, query_record)
+    o = _search_opts(delta_d, mode, schedule, rerank_delta, fill_min, growth, False, scan_blocks_per_cu,
+                     rerank_rule)
+    o.stats = None if stats is None else _dev(stats, torch.int64, "stats").value
+    o.query_record = None if query_record is None else _dev(query_record, torch.int32, "query_record").value
+    rec = SearchRecord()
+    if record is not None:
+        o.record = ctypes.pointer(rec)
+    kp = None if k_per_query is None else _dev(k_per_query, torch.int32, "k_per_query")
+    npp = None if nprobe_per_query is None else _dev(nprobe_per_query, torch.int32, "nprobe_per_query")
+    _check(lib().dade_search_noalloc(ix.handle, _dev(Q, torch.float32, "Q"), Q.shape[0], k, nprobe, kp, npp,
+                                     ctypes.byref(o), _dev(out_ids, torch.int64, "out_ids"),
+                                     _dev(out_dist2, torch.float32, "out_dist2"), _stream(stream)))
     if record is not None:
         record.update(_record_dict(rec))
     return out_ids, out_dist2
