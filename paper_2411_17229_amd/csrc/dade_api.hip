@@ -66,7 +66,6 @@ struct dade_index {
   int32_t* d_ids = nullptr;    // [n] packed position -> row id
   int64_t* d_pos = nullptr;    // [n] row id -> packed position
   float* d_B = nullptr;        // [dp x ldB] FP32 [W | (C - mu)^T] (zero padded)
-  uint16_t* d_B3 = nullptr;    // the same split into three bf16 parts, MFMA fragment order (split_b3)
   int ldB = 0;                 // dp + nlist rounded up to a multiple of 4 (float4 rows)
   float* d_mu = nullptr;       // [dp]
   float* d_cent_norm = nullptr;// [nlist] ||c - mu||^2
@@ -79,7 +78,6 @@ struct dade_index {
   std::vector<int64_t> sizes_desc;   // list sizes, largest first (round capacities)
   // search workspace (grown on demand, each with its element count)
   float* w_qpad = nullptr; float* w_qrot = nullptr; float* w_pd = nullptr;
-  void* w_a3 = nullptr;        // [split_a_bytes(w_nq, dp)] the query GEMM's split queries
   int32_t* w_probes = nullptr;
   int64_t w_nq = 0, w_np = 0;
   unsigned long long* w_topk = nullptr; int64_t w_topk_n = 0;
@@ -276,12 +274,6 @@ int apply_transform(dade_index* ix, hipStream_t s) {
     cn[l] = float(nrm);
   }
   for (int i = 0; i < dim; ++i) muf[i] = float(ix->mu[i]);
-  // the query GEMM's operand for the bf16 matrix cores: [W | (C - mu)^T] split into three bf16 parts
-  const size_t npad = size_t(dp + nl + kSplitNPad - 1) / kSplitNPad * kSplitNPad;
-  std::vector<uint16_t> B3(3 * npad * size_t(dp));
-  split_b3(Bf.data(), int(ldb), dp, dp + nl, B3.data());
-  if (!ix->d_B3 && (rc = alloc_t(ix, &ix->d_B3, B3.size()))) return rc;
-  HIPC(hipMemcpyAsync(ix->d_B3, B3.data(), sizeof(uint16_t) * B3.size(), hipMemcpyHostToDevice, s));
   if (!ix->d_B && (rc = alloc_t(ix, &ix->d_B, Bf.size()))) return rc;
   if (!ix->d_mu && (rc = alloc_t(ix, &ix->d_mu, dp))) return rc;
   if (!ix->d_cent_norm && (rc = alloc_t(ix, &ix->d_cent_norm, nl))) return rc;
@@ -323,23 +315,18 @@ int grow_query_workspace(dade_index* ix, int64_t nq, int64_t npm, hipStream_t s)
     dev_free(ix, ix->w_qrot, sizeof(float) * ix->w_nq * dp);
     dev_free(ix, ix->w_pd, sizeof(float) * ix->w_nq * nl);
     dev_free(ix, ix->w_probes, sizeof(int32_t) * ix->w_nq * ix->w_np);
-    dev_free(ix, ix->w_a3, split_a_bytes(int(ix->w_nq), dp));
     ix->w_qpad = ix->w_qrot = ix->w_pd = nullptr;
     ix->w_probes = nullptr;
-    ix->w_a3 = nullptr;
     ix->w_nq = ix->w_np = 0;
     if ((rc = alloc_t(ix, &ix->w_qpad, size_t(new_nq) * dp)) || (rc = alloc_t(ix, &ix->w_qrot, size_t(new_nq) * dp)) ||
-        (rc = alloc_t(ix, &ix->w_pd, size_t(new_nq) * nl)) || (rc = alloc_t(ix, &ix->w_probes, size_t(new_nq) * new_np)) ||
-        (rc = dev_alloc(ix, &ix->w_a3, split_a_bytes(int(new_nq), dp)))) {
+        (rc = alloc_t(ix, &ix->w_pd, size_t(new_nq) * nl)) || (rc = alloc_t(ix, &ix->w_probes, size_t(new_nq) * new_np))) {
       // leave no part of the workspace behind (the next search grows it again)
       dev_free(ix, ix->w_qpad, sizeof(float) * new_nq * dp);
       dev_free(ix, ix->w_qrot, sizeof(float) * new_nq * dp);
       dev_free(ix, ix->w_pd, sizeof(float) * new_nq * nl);
       dev_free(ix, ix->w_probes, sizeof(int32_t) * new_nq * new_np);
-      dev_free(ix, ix->w_a3, split_a_bytes(int(new_nq), dp));
       ix->w_qpad = ix->w_qrot = ix->w_pd = nullptr;
       ix->w_probes = nullptr;
-      ix->w_a3 = nullptr;
       return rc;
     }
     ix->w_nq = new_nq; ix->w_np = new_np;
@@ -364,7 +351,6 @@ struct Workspace {
   float* qrot = nullptr;             // [nq x dp] rotated queries
   float* pd = nullptr;               // [nq x nlist] centroid terms
   int32_t* probes = nullptr;         // [nq x npm]
-  void* a3 = nullptr;                // [split_a_bytes(nq, dp)] the query GEMM's split queries
   unsigned long long* topk = nullptr;   // [chunk x k]
   unsigned long long* keyr = nullptr;   // [chunk]
   float* r2 = nullptr;               // [chunk]
@@ -426,7 +412,7 @@ int grow_workspace(dade_index* ix, int64_t nq, int32_t k, const SearchPlan& pl, 
       (rc = grow(ix, &ix->w_counter, ix->w_counter_n, pl.rounds, s)) ||
       (rc = grow(ix, &ix->w_counts, ix->w_counts_n, int64_t(pl.rounds) * chunk, s)))
     return rc;
-  ws.qpad = ix->w_qpad; ws.qrot = ix->w_qrot; ws.pd = ix->w_pd; ws.probes = ix->w_probes; ws.a3 = ix->w_a3;
+  ws.qpad = ix->w_qpad; ws.qrot = ix->w_qrot; ws.pd = ix->w_pd; ws.probes = ix->w_probes;
   ws.topk = ix->w_topk; ws.keyr = ix->w_keyr; ws.r2 = ix->w_r2; ws.qint = ix->w_qint;
   ws.kb = ix->w_kb; ws.items = ix->w_items; ws.counter = ix->w_counter; ws.counts = ix->w_counts;
   ws.chunk = chunk;
@@ -447,8 +433,7 @@ int index_prepare_search(dade_index* ix, int64_t nq, int32_t k, int32_t nprobe, 
   const int rc = grow_workspace(ix, nq, k, pl, s, ws);
   if (rc) return rc;
   const int64_t dp = ix->dp, nl = ix->nlist;
-  *workspace_bytes = ix->w_nq * (2 * dp * 4 + nl * 4 + ix->w_np * 4) + int64_t(split_a_bytes(int(ix->w_nq), int(dp))) +
-                     ix->w_topk_n * 8 + ix->w_keyr_n * 8 +
+  *workspace_bytes = ix->w_nq * (2 * dp * 4 + nl * 4 + ix->w_np * 4) + ix->w_topk_n * 8 + ix->w_keyr_n * 8 +
                      ix->w_r2_n * 4 + ix->w_qint_n * 4 + ix->w_kb_n * 8 + ix->w_items_n * 16 + ix->w_counter_n * 4 +
                      ix->w_counts_n * 4;
   return DADE_OK;
@@ -493,7 +478,6 @@ size_t align_up(size_t x) { return (x + kScratchAlign - 1) / kScratchAlign * kSc
 size_t slice_bytes(const dade_index* ix, const SearchPlan& pl, int32_t k, int64_t cn) {
   const size_t dp = size_t(ix->dp), nl = size_t(ix->nlist), c = size_t(cn);
   return align_up(c * dp * 4) * 2 + align_up(c * nl * 4) + align_up(c * size_t(pl.npm) * 4) +
-         align_up(split_a_bytes(int(cn), ix->dp)) +
          align_up(c * size_t(k) * 8) + align_up(c * 8) + align_up(c * 4) + align_up(c * 12) +
          align_up(c * size_t(pl.kb_cap) * 8) + align_up(size_t(pl.rounds) * c * size_t(pl.items_pq) * 16) +
          align_up(size_t(pl.rounds) * 4) + align_up(size_t(pl.rounds) * c * 4);
@@ -513,7 +497,6 @@ Workspace carve(char* base, const dade_index* ix, const SearchPlan& pl, int32_t 
   ws.qrot = reinterpret_cast<float*>(take(c * dp * 4));
   ws.pd = reinterpret_cast<float*>(take(c * nl * 4));
   ws.probes = reinterpret_cast<int32_t*>(take(c * size_t(pl.npm) * 4));
-  ws.a3 = take(split_a_bytes(int(cn), ix->dp));
   ws.topk = reinterpret_cast<unsigned long long*>(take(c * size_t(k) * 8));
   ws.keyr = reinterpret_cast<unsigned long long*>(take(c * 8));
   ws.r2 = reinterpret_cast<float*>(take(c * 4));
@@ -983,7 +966,7 @@ static int search_impl(dade_index* ix, const float* Q, int64_t ldq, int64_t nq, 
   g.A = qpad; g.lda = dp; g.a_shift = ix->d_mu;
   g.B = ix->d_B; g.ldb = ix->ldB; g.C = ws.qrot; g.ldc = dp;
   g.split_col = dp; g.C2 = ws.pd; g.ldc2 = nl; g.col_norm = ix->d_cent_norm;
-  HIPC(launch_gemm_split3(g, ix->d_B3, ws.a3, s));
+  HIPC(launch_gemm(g, kEpiRotateProbe, s));
   if (o.record_times) HIPC(hipEventRecord(ix->ev[1], s));
   HIPC(launch_select_probes(ws.pd, nl, int(nq), nl, npm, ws.probes, s));
   if (o.record_times) HIPC(hipEventRecord(ix->ev[2], s));
@@ -1363,7 +1346,7 @@ int dade_graph_search(dade_index* ix, const float* Q, int64_t nq, int32_t k, int
   g.A = qpad; g.lda = dp; g.a_shift = ix->d_mu;
   g.B = ix->d_B; g.ldb = ix->ldB; g.C = ix->w_qrot; g.ldc = dp;
   g.split_col = dp; g.C2 = ix->w_pd; g.ldc2 = nl; g.col_norm = ix->d_cent_norm;
-  HIPC(launch_gemm_split3(g, ix->d_B3, ix->w_a3, s));
+  HIPC(launch_gemm(g, kEpiRotateProbe, s));
   HIPC(launch_select_probes(ix->w_pd, nl, int(nq), nl, npm, ix->w_probes, s));
   GraphArgs a;
   a.nq = int(nq); a.dim = ix->dim; a.dp = dp; a.delta_d = dd;

@@ -39,22 +39,6 @@ struct GemmArgs {
 };
 hipError_t launch_gemm(const GemmArgs& a, GemmEpilogue epi, hipStream_t s);
 
-// ---------------------------------------------------------------- the query GEMM on bf16 matrix cores
-// C = (A - a_shift) B with FP32 inputs, computed as six bf16 MFMA products: every FP32 operand x is
-// split into x0 + x1 + x2 (x0 = bf16(x), x1 = bf16(x - x0), x2 = bf16(x - x0 - x1), 24 significand
-// bits in all) and C = A0 B0 + (A0 B1 + A1 B0 + A0 B2 + A1 B1 + A2 B0), the leading product and the
-// corrections in separate FP32 accumulators (the dropped terms are below 2^-24 relative).  B is split
-// once, at index build, into MFMA fragments (split_b3); A is split per call into the scratch a3
-// (split_a_bytes(M, K) bytes).  The epilogue is kEpiRotateProbe's.  Requires K % 32 == 0,
-// lda % 4 == 0, N <= the padded width of the split B.
-constexpr int kSplitNPad = 256;   // the split B's columns are padded to a multiple of this
-// Host: the three bf16 parts of B [K x N] (ldb), in fragment order: for split s, 32-column block nb
-// and 16-deep K step ks, 64 lanes x 8 bf16 where lane = 32 ((k % 16) / 8) + n % 32 and element k % 8.
-// out holds 3 x Npad x K values, Npad = N rounded up to kSplitNPad (zero padded).
-void split_b3(const float* B, int ldb, int K, int N, uint16_t* out);
-size_t split_a_bytes(int M, int K);
-hipError_t launch_gemm_split3(const GemmArgs& a, const uint16_t* b3, void* a3, hipStream_t s);
-
 // ---------------------------------------------------------------- small kernels (misc.hip)
 // dst[r][c] = src[r * lds + c] for c < cols, 0 up to ld.
 hipError_t launch_pad_rows(const float* src, int64_t rows, int cols, int64_t lds, float* dst, int ld,
