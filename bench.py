@@ -37,7 +37,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "QPS at recall@10≥0.95, DADE vs full-D exact DCO, 1 GPU; p50/p99 latency"
 PEAK_HBM_GBS = 8000.0
-NPROBE_SWEEP = (8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256)
+NPROBE_SWEEP = (1, 2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256)
 PS_SWEEP = (0.1, 0.05, 0.02, 0.01, 0.005, 0.002, 0.001, 0.0005)
 
 
@@ -130,76 +130,101 @@ def kernel_times(dade, torch, ix, Qd, k, nprobe, steps, **kw):
     return {key: v / steps for key, v in acc.items()}
 
 
-def cpu_baseline(w, X, Q, nprobe, p_s, seconds=20.0):
-    """The FP64 oracle timed on one host core (BLAS limited to one thread) on a bounded sample:
-    an oracle-built index over a 5% row subsample with nlist scaled by the same factor (so lists
-    keep the workload's size and a query scans the same number of candidates of the same
-    dimension), DADE mode with the timed runs' round schedule and P_s, queries until ~`seconds`."""
+def _oracle_index(art, X, store):
+    """The oracle's view of the library's index (its lists, W, mu, lambda, T and delta, exported):
+    stored rows rotated on demand from X (and rounded as the store rounds them), exact rows for
+    the low-precision rerank."""
+    from oracle import estimator, ivf, lowp
+    lam, T = art["lam"], art["T"]
+    eps = np.sqrt(np.maximum(T * estimator.scale(lam), 0.0)) - 1.0
+    rnd = None if store == "f32" else (lambda y: lowp.store(y, store))
+    Y = ivf.LazyRotated(X, art["mu"], art["W"], rnd)
+    Ye = ivf.LazyRotated(X, art["mu"], art["W"]) if rnd is not None else None
+    return ivf.Index(art["mu"], art["W"], lam, eps, art["centroids"], art["list_offsets"], art["list_ids"], Y,
+                     Y_exact=Ye, delta=art["delta"], T=T)
+
+
+CPU_ART_KEYS = ("W", "mu", "lam", "T", "centroids", "list_offsets", "list_ids")
+
+
+def cpu_baseline(w, X, Q, art, store, nprobe, p_s, rerank, gt, seconds=20.0):
+    """The FP64 oracle timed on the host on a bounded sample of the workload itself: the library's
+    index (exported lists, transform, thresholds and rerank margin; rows rotated on demand), the
+    timed runs' schedule, nprobe, P_s and rerank rule, queries in order until ~`seconds`; the rate is
+    extrapolated from that query subsample.  One thread (BLAS limited to one), the same in exact
+    mode (FDScanning) for half the time, and every usable core in a child process.  Beside it, not
+    timed: the round schedule against the paper's sequential one (heap updated after every DCO) on
+    a query sample, recall@K against FP64 brute force and dimensions read."""
     from threadpoolctl import threadpool_limits
 
     from oracle import ivf
-    from paper_2411_17229_amd import workloads
-    frac = 20
-    n_s = len(X) // frac
-    nl_s = max(1, w.nlist // frac)
-    rows = np.sort(np.random.default_rng(1).choice(len(X), n_s, replace=False))
-    Xs = np.ascontiguousarray(X[rows])
-    t0 = time.perf_counter()
-    oi = ivf.build(Xs, nl_s, workloads.kmeans_init_rows(n_s, nl_s, 0),
-                   workloads.calibration_pairs(n_s, 100_000, 0), p_s=p_s, iters=10)
-    build_s = time.perf_counter() - t0
-    with threadpool_limits(limits=1):
-        done, t0 = 0, time.perf_counter()
-        while done < len(Q) and time.perf_counter() - t0 < seconds:
-            ivf.search(oi, Q[done:done + 1], w.k, nprobe, w.delta_d, **SCHEDULE)
-            done += 1
-        el = time.perf_counter() - t0
+    oi = _oracle_index(art, X, store)
+    kw = dict(SCHEDULE, rerank=rerank)
+
+    def timed(mode, budget):
+        with threadpool_limits(limits=1):
+            done, t0 = 0, time.perf_counter()
+            while done < len(Q) and time.perf_counter() - t0 < budget:
+                ivf.search(oi, Q[done:done + 1], w.k, nprobe, w.delta_d, mode=mode, **kw)
+                done += 1
+            return done, time.perf_counter() - t0
+
+    done, el = timed("dade", seconds)
     out = {"value": done / el, "unit": "queries/s", "cores": 1, "kind": "oracle",
-           "sample": f"{done} queries, DADE {SCHEDULE['schedule']} schedule, P_s {p_s}, nprobe {nprobe}, "
-                     f"K {w.k}, over an oracle-built index of a {n_s}-row subsample with nlist {nl_s} "
-                     f"(same list size and D as the workload); one thread; index build {build_s:.1f} s "
-                     f"not timed"}
-    # the oracle's exact mode (FDScanning) on the same index, one thread, half the time
-    with threadpool_limits(limits=1):
-        done_f, t0 = 0, time.perf_counter()
-        while done_f < len(Q) and time.perf_counter() - t0 < seconds / 2:
-            ivf.search(oi, Q[done_f:done_f + 1], w.k, nprobe, w.delta_d, mode="full_d", **SCHEDULE)
-            done_f += 1
-        el_f = time.perf_counter() - t0
+           "sample": f"the first {done} of the workload's {len(Q)} queries (rate extrapolated) on the library's "
+                     f"{w.n} x {w.dim} index (exported lists, W, T and delta; {store} rows rotated on demand "
+                     f"from X), DADE, {SCHEDULE['schedule']} rounds, P_s {p_s}, nprobe {nprobe}, K {w.k}, "
+                     f"rerank rule {rerank}; one thread (BLAS limited to one)"}
+    done_f, el_f = timed("full_d", seconds / 2)
     out["full_d"] = {"value": done_f / el_f, "unit": "queries/s", "cores": 1, "kind": "oracle",
-                     "sample": f"{done_f} queries, FULL_D mode, same index, nprobe and K; one thread"}
-    # the same search on every host core this job may use: a child process (this one holds the
-    # GPU) builds the same index and forks one single-threaded worker per core over query shards
+                     "sample": f"the first {done_f} queries, FULL_D mode (FDScanning), same index, nprobe and K; "
+                               f"one thread"}
+    # the same search on every usable core: a child process (this one holds the GPU) regenerates
+    # the workload, loads the exported artifacts and forks one single-threaded worker per core
     import subprocess
     import tempfile
     with tempfile.TemporaryDirectory() as tmp:
-        path = os.path.join(tmp, "sample.npz")
-        np.savez(path, X=Xs, Q=Q)
+        path = os.path.join(tmp, "index.npz")
+        np.savez(path, **{k_: art[k_] for k_ in CPU_ART_KEYS}, delta=np.array(art["delta"]))
         r = subprocess.run([sys.executable, os.path.abspath(__file__), "--oracle-pool", path, "--workload", w.name,
-                            "--nprobe", str(nprobe), "--p-s", str(p_s), "--cpu-seconds", str(seconds)],
-                           capture_output=True, text=True, timeout=600)
+                            "--store", store, "--nprobe", str(nprobe), "--p-s", str(p_s), "--rerank", rerank,
+                            "--cpu-seconds", str(seconds)], capture_output=True, text=True, timeout=900)
     if r.returncode == 0 and r.stdout.strip():
         out["all_cores"] = json.loads(r.stdout.strip().splitlines()[-1])
     else:
         out["all_cores"] = {"error": (r.stderr or "")[-300:]}
+    out["schedule_gap"] = schedule_gap(oi, w, Q, gt, nprobe, rerank)
     return out
 
 
-def oracle_pool(path, w, nprobe, p_s, seconds):
-    """Child of cpu_baseline (no GPU here): the oracle index over the given subsample, then one
-    single-threaded worker per usable core (at most 16) searching every P-th query for ~`seconds`."""
+def schedule_gap(oi, w, Q, gt, nprobe, rerank, n_sample=20):
+    """The round schedule's snapshots against the paper's sequential heap (one candidate per round)
+    in the oracle: recall@K and the fraction of dimensions read on the first queries."""
+    from oracle import ivf
+    out = {"queries": n_sample, "nprobe": nprobe}
+    for name, kw in (("rounds", dict(SCHEDULE)), ("sequential", dict(schedule="sequential"))):
+        t0 = time.perf_counter()
+        ids, _, logs = ivf.search(oi, Q[:n_sample], w.k, nprobe, w.delta_d, log=True, rerank=rerank, **kw)
+        out[name] = {"recall@%d" % w.k: round(recall_at(ids, gt[:n_sample], w.k), 4),
+                     "dims_frac": round(float(logs["dims"].sum()) / float(logs["dcos"].sum() * w.dim), 5),
+                     "oracle_s": round(time.perf_counter() - t0, 1)}
+    log(f"[bench] schedule gap: {out}")
+    return out
+
+
+def oracle_pool(path, w, store, nprobe, p_s, rerank, seconds):
+    """Child of cpu_baseline (no GPU here): the workload regenerated, the oracle's view of the exported
+    index, then one single-threaded worker per usable core (at most 16) searching every P-th query
+    for ~`seconds`."""
     import multiprocessing as mp
 
-    from threadpoolctl import threadpool_limits
-
-    from oracle import ivf
     from paper_2411_17229_amd import workloads
     d = np.load(path)
-    Xs, Q = d["X"], d["Q"]
-    n_s, nl_s = len(Xs), max(1, w.nlist // 20)
+    art = {k_: d[k_] for k_ in CPU_ART_KEYS}
+    art["delta"] = float(d["delta"])
+    X, Q = workloads.make(w)
     global _POOL_INDEX
-    _POOL_INDEX = (ivf.build(Xs, nl_s, workloads.kmeans_init_rows(n_s, nl_s, 0),
-                             workloads.calibration_pairs(n_s, 100_000, 0), p_s=p_s, iters=10), Q, w, nprobe, seconds)
+    _POOL_INDEX = (_oracle_index(art, X, store), Q, w, nprobe, rerank, seconds)
     cores = min(16, len(os.sched_getaffinity(0)))
     ctx = mp.get_context("fork")
     t0 = time.perf_counter()
@@ -208,7 +233,7 @@ def oracle_pool(path, w, nprobe, p_s, seconds):
     el = time.perf_counter() - t0
     return {"value": sum(counts) / el, "unit": "queries/s", "cores": cores, "kind": "oracle",
             "sample": f"{sum(counts)} queries over {cores} single-threaded worker processes, same index and "
-                      f"settings as the one-thread run; wall time includes the pool's start"}
+                      f"settings as the one-thread run (rate extrapolated); wall time includes the pool's start"}
 
 
 def _pool_worker(arg):
@@ -216,13 +241,13 @@ def _pool_worker(arg):
 
     from oracle import ivf
     i, cores = arg
-    oi, Q, w, nprobe, seconds = _POOL_INDEX
+    oi, Q, w, nprobe, rerank, seconds = _POOL_INDEX
     done, t0 = 0, time.perf_counter()
     with threadpool_limits(limits=1):
         for qi in range(i, len(Q), cores):
             if time.perf_counter() - t0 >= seconds:
                 break
-            ivf.search(oi, Q[qi:qi + 1], w.k, nprobe, w.delta_d, **SCHEDULE)
+            ivf.search(oi, Q[qi:qi + 1], w.k, nprobe, w.delta_d, rerank=rerank, **SCHEDULE)
             done += 1
     return done
 
@@ -472,10 +497,11 @@ def uneven_study(dade, torch, ix, Xd, Qd, w, store, target, steps, warmup):
            "nprobe_mean": round(float(npb.mean()), 1), "p_s": chosen_ps, "recall_by_p_s": by_ps, "autotuned": tuned}
     for mode, kw in (("dade", dict(tuned)), ("full_d", dict(base, mode="full_d"))):
         ms = throughput(dade, torch, ix, Qd, kmax, npmax, steps, warmup, k_per_query=kp, nprobe_per_query=npp, **kw)
-        ids, _ = dade.dade_search(ix, Qd, kmax, npmax, k_per_query=kp, nprobe_per_query=npp, **kw)
+        record = {}
+        ids, _ = dade.dade_search(ix, Qd, kmax, npmax, k_per_query=kp, nprobe_per_query=npp, record=record, **kw)
         rec, per_k = recall(ids.cpu().numpy())
         out[mode] = {"qps": round(nq / (ms / 1e3), 1), "ms_per_step": round(ms, 4), "recall": round(rec, 4),
-                     "recall_by_k": per_k}
+                     "recall_by_k": per_k, "search_record": record}
         log(f"[bench] uneven {mode}: {out[mode]['qps']:.0f} QPS ({ms:.3f} ms per batch), recall {rec:.4f} {per_k}")
     out["speedup_vs_full_d"] = round(out["dade"]["qps"] / out["full_d"]["qps"], 3)
     return out
@@ -512,6 +538,9 @@ def main():
     ap.add_argument("--nprobe", type=int, default=None)
     ap.add_argument("--p-s", type=float, default=None)
     ap.add_argument("--mode", default="dade")
+    ap.add_argument("--rerank", default="lazy", choices=("all", "lazy"),
+                    help="low-precision rerank rule of the timed runs: every survivor that passes the gate, or "
+                         "the lazy rule (the default; the other rule is timed beside it)")
     ap.add_argument("--no-graph", action="store_true",
                     help="with --profile-only: launch the scan kernels one by one (counter collection "
                          "does not see kernels replayed from a graph)")
@@ -521,8 +550,8 @@ def main():
     args = ap.parse_args()
     if args.oracle_pool:
         from paper_2411_17229_amd import workloads
-        print(json.dumps(oracle_pool(args.oracle_pool, workloads.WORKLOADS[args.workload], args.nprobe, args.p_s,
-                                     args.cpu_seconds)), flush=True)
+        print(json.dumps(oracle_pool(args.oracle_pool, workloads.WORKLOADS[args.workload], args.store, args.nprobe,
+                                     args.p_s, args.rerank, args.cpu_seconds)), flush=True)
         return
     if args.copy_probe:
         import torch
@@ -562,7 +591,7 @@ def main():
 
     if args.profile_only:
         npb = args.nprobe or w.nprobe
-        kw = dict(delta_d=w.delta_d, mode=args.mode, use_graph=not args.no_graph, **SCHEDULE)
+        kw = dict(delta_d=w.delta_d, mode=args.mode, use_graph=not args.no_graph, rerank_rule=args.rerank, **SCHEDULE)
         ms = throughput(dade, torch, ix, Qd, w.k, npb, args.steps, args.warmup, **kw)
         log(f"[bench] profile run ({args.mode}, nprobe {npb}, P_s {args.p_s or w.alpha}): {ms:.3f} ms/step")
         return
@@ -598,6 +627,7 @@ def main():
         return
 
     pairs = workloads.calibration_pairs(w.n, 100_000, w.seed)
+    RR = dict(rerank_rule=args.rerank)
 
     def first_reaching(mode, kw):
         """(nprobe, recall, curve): smallest swept nprobe with recall >= target (else best)."""
@@ -605,7 +635,7 @@ def main():
         for npb in NPROBE_SWEEP:
             if npb > w.nlist:
                 break
-            ids, _ = dade.dade_search(ix, Qd, w.k, npb, delta_d=w.delta_d, mode=mode, **kw)
+            ids, _ = dade.dade_search(ix, Qd, w.k, npb, delta_d=w.delta_d, mode=mode, **kw, **RR)
             torch.cuda.synchronize()
             curve[npb] = recall_at(ids.cpu().numpy(), gt, w.k)
             if curve[npb] >= args.target:
@@ -615,8 +645,9 @@ def main():
         best = max(curve, key=lambda p: curve[p])
         return best, curve[best], curve
 
-    # operating points (untimed sweeps): full-D over nprobe; DADE over (P_s, nprobe), keeping the
-    # fastest configuration that reaches the target
+    # operating points (untimed sweeps), each method at its own fastest configuration reaching the
+    # target: full-D at its smallest such nprobe (its work grows with nprobe); DADE over (P_s, the
+    # smallest nprobe reaching the target at that P_s), the fastest of those timed
     sweep = {"full_d": {}, "dade": {}}
     chosen = {}
     npb, r, sweep["full_d"] = first_reaching("full_d", SCHEDULE)
@@ -629,10 +660,8 @@ def main():
         sweep["dade"][str(ps)] = curve
         log(f"[bench] dade P_s {ps}: nprobe {npb} recall {r:.4f}")
         if r >= args.target:
-            ms = throughput(dade, torch, ix, Qd, w.k, npb, 5, 2, delta_d=w.delta_d, **SCHEDULE)
+            ms = throughput(dade, torch, ix, Qd, w.k, npb, 5, 2, delta_d=w.delta_d, **SCHEDULE, **RR)
             cands.append((ms, ps, npb, r))
-            if len(cands) >= 2 and cands[-1][0] > cands[-2][0]:
-                break   # smaller P_s reads more dimensions; past the best already
     if cands:
         _, ps, npb, r = min(cands)
     else:
@@ -645,9 +674,10 @@ def main():
     res = {}
     for mode in ("dade", "full_d"):
         ps_m, npb, r_m = chosen[mode]
-        kw = dict(delta_d=w.delta_d, mode=mode, **SCHEDULE)
+        kw = dict(delta_d=w.delta_d, mode=mode, **SCHEDULE, **RR)
         stats = torch.zeros((nq, 4), dtype=torch.int64, device=dev)
-        ids, d2 = dade.dade_search(ix, Qd, w.k, npb, stats=stats, **kw)
+        rec = {}
+        ids, d2 = dade.dade_search(ix, Qd, w.k, npb, stats=stats, record=rec, **kw)
         torch.cuda.synchronize()
         dade.dade_check(ix)
         st = stats.cpu().numpy().sum(0)
@@ -663,7 +693,7 @@ def main():
         res[mode] = dict(nprobe=npb, p_s=ps_m, recall=r_m, qps=nq / (ms / 1e3), ms_per_step=ms,
                          p50_ms=float(np.percentile(walls, 50)), p99_ms=float(np.percentile(walls, 99)),
                          times=kt, dcos=int(st[0]), dims_frac=float(st[1]) / max(1, st[0] * w.dim),
-                         kept=int(st[2]), reranked=int(st[3]), alg_round=alg_round,
+                         kept=int(st[2]), reranked=int(st[3]), alg_round=alg_round, record=rec,
                          max_rel_err=float(rel.max()), mean_rel_err=float(rel.mean()))
         log(f"[bench] {mode}: nprobe {npb} recall {r_m:.4f} {res[mode]['qps']:.0f} QPS ({ms:.3f} ms/step) "
             f"round kernels {kt['round_kernel_ms']:.3f} ms over {kt['round_launches']:.0f} launches, "
@@ -675,33 +705,60 @@ def main():
     avg_ms = kt["round_kernel_ms"] / launches
     achieved = d["alg_round"] / (kt["round_kernel_ms"] * 1e-3) / 1e9
     traffic = traffic_from_profile(w.name, store, d["nprobe"], d["p_s"])
+    traffic_gbs = traffic / (avg_ms * 1e-3) / 1e9 if traffic else None
     out = {
         "metric": METRIC, "value": round(d["qps"], 1), "unit": "queries/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(d["ms_per_step"], 4),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": f"{store} store, f32 accumulate" if store != "f32" else "f32",
         "data": "synthetic",
         "config": {"workload": w.name, "n": w.n, "dim": w.dim, "nlist": w.nlist, "k": w.k,
                    "queries_per_step": nq, "nprobe": d["nprobe"], "delta_d": w.delta_d, "p_s": d["p_s"],
                    "store": store, "schedule": SCHEDULE["schedule"], "fill_min": SCHEDULE["fill_min"],
-                   "growth": SCHEDULE["growth"], f"recall@{w.k}": round(d["recall"], 4)},
+                   "growth": SCHEDULE["growth"], "rerank_rule": args.rerank, f"recall@{w.k}": round(d["recall"], 4)},
+        "search_record": d["record"],
         "p50_ms": round(d["p50_ms"], 4), "p99_ms": round(d["p99_ms"], 4),
         "full_d": {"qps": round(res["full_d"]["qps"], 1), "nprobe": res["full_d"]["nprobe"],
                    f"recall@{w.k}": round(res["full_d"]["recall"], 4),
                    "ms_per_step": round(res["full_d"]["ms_per_step"], 4),
                    "p50_ms": round(res["full_d"]["p50_ms"], 4), "p99_ms": round(res["full_d"]["p99_ms"], 4)},
         "speedup_vs_full_d": round(d["qps"] / res["full_d"]["qps"], 3),
+        "comparison": "each method at its own fastest configuration reaching the recall target",
         "stages_ms": {k_: round(v, 4) for k_, v in kt.items()},
         "dims_read_frac": round(d["dims_frac"], 4),
+        "reranked_per_query": round(d["reranked"] / nq, 2),
         "dist2_rel_err_vs_fp64": {"max": d["max_rel_err"], "mean": d["mean_rel_err"]},
         "recall_sweep": {"full_d": {str(k_): round(v, 4) for k_, v in sweep["full_d"].items()},
                          "dade_by_p_s": {ps_: {str(k_): round(v, 4) for k_, v in c.items()}
                                          for ps_, c in sweep["dade"].items()}},
         "roofline": {"bound": "hbm", "kernel": "scan_round_kernel", "achieved": round(achieved, 1),
                      "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
-                     "traffic": (round(traffic / (avg_ms * 1e-3) / 1e9, 1) if traffic else None),
+                     "traffic": (round(traffic_gbs, 1) if traffic else None),
+                     "frac_counted": (round(traffic_gbs / PEAK_HBM_GBS, 4) if traffic else None),
                      "alg_bytes_per_launch": round(d["alg_round"] / launches), "launches_per_step": launches,
-                     "avg_launch_ms": round(avg_ms, 5)},
+                     "avg_launch_ms": round(avg_ms, 5),
+                     "limiter": "the HBM roof applies by arithmetic intensity (1 FLOP/B for a 16-bit store); the "
+                                "kernel runs below it, limited by the latency of each round's deepest DCO chains; "
+                                "counted DRAM bytes are below the algorithmic ones where lists are re-read from "
+                                "L2 / Infinity Cache"},
     }
+    if store != "f32":
+        # the lazy rerank rule at the same operating point (fewer exact distances; it keeps what the
+        # plain rule keeps unless a skipped candidate's stored-precision error exceeds delta)
+        other = "lazy" if args.rerank == "all" else "all"
+        kw = dict(delta_d=w.delta_d, rerank_rule=other, **SCHEDULE)
+        stats = torch.zeros((nq, 4), dtype=torch.int64, device=dev)
+        ids_o, _ = dade.dade_search(ix, Qd, w.k, d["nprobe"], stats=stats, **kw)
+        torch.cuda.synchronize()
+        ms = throughput(dade, torch, ix, Qd, w.k, d["nprobe"], args.steps, args.warmup, **kw)
+        ids_main, _ = dade.dade_search(ix, Qd, w.k, d["nprobe"], delta_d=w.delta_d, **SCHEDULE, **RR)
+        torch.cuda.synchronize()
+        a_, b_ = ids_o.cpu().numpy(), ids_main.cpu().numpy()
+        out["rerank_" + other] = {"qps": round(nq / (ms / 1e3), 1), f"recall@{w.k}": round(recall_at(a_, gt, w.k), 4),
+                                  "reranked_per_query": round(float(stats[:, 3].sum().item()) / nq, 2),
+                                  "queries_differing_from_" + args.rerank: int(sum(
+                                      set(a_[i].tolist()) != set(b_[i].tolist()) for i in range(nq)))}
+        log(f"[bench] rerank rule {other}: {out['rerank_' + other]}")
     if not args.no_serving:
         mib = args.serve_budget_mib or 512
         out["serving"] = serving_sweep(dade, ix, Q, gt, w.k, (w.k,), (d["nprobe"],), budget=mib << 20, seed=w.seed,
@@ -752,7 +809,9 @@ def main():
         out["linear_scan"] = linear_scan(dade, torch, w, store, d["p_s"], max(3, args.steps // 4))
     if not args.no_cpu:
         log("[bench] CPU oracle baseline ...")
-        out["cpu_baseline"] = cpu_baseline(w, X, Q, d["nprobe"], d["p_s"], args.cpu_seconds)
+        dade.dade_calibrate(ix, d["p_s"], pairs=pairs)   # the ablation leaves another P_s behind
+        out["cpu_baseline"] = cpu_baseline(w, X, Q, dade.dade_export(ix), store, d["nprobe"], d["p_s"], args.rerank,
+                                           gt, args.cpu_seconds)
     print(json.dumps(out), flush=True)
 
 

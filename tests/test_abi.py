@@ -89,6 +89,7 @@ def _c_layout(struct, fields):
 
 
 @pytest.mark.parametrize("struct,cls", [("dade_search_opts", "SearchOpts"), ("dade_search_record", "SearchRecord"),
+                                        ("dade_tune_result", "TuneResult"),
                                         ("dade_serve_opts", "ServeOpts"), ("dade_times", "Times")])
 def test_binding_structs_match_the_header_layout(struct, cls):
     """The ctypes mirrors of the option and record structs have the C layout field for field (the
