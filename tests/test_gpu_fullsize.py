@@ -37,7 +37,7 @@ def oracle_from_library(gi, X, store):
 
 
 def run_workload(name, p_s, nprobe, n_sample, k_per_query=None, nprobe_per_query=None, k=None, keep=False,
-                 n_queries=None, tune=None, one_launch=False):
+                 n_queries=None, tune=None):
     import torch
     _need_gpu()
     w = workloads.WORKLOADS[name]
@@ -61,12 +61,13 @@ def run_workload(name, p_s, nprobe, n_sample, k_per_query=None, nprobe_per_query
     ids, d2 = dade.dade_search(gi, Qd, K, nprobe, k_per_query=kp, nprobe_per_query=npp, stats=stats, **kw)
     # the graph-replayed launch (as timed) gives the same rows
     ids2, d22 = dade.dade_search(gi, Qd, K, nprobe, k_per_query=kp, nprobe_per_query=npp, **kw)
+    # the same arguments again, into the same output buffers: the captured list scan is replayed
+    # (the captured argument block holds the output pointers) and writes the same rows
     rec = {}
-    dade.dade_search(gi, Qd, K, nprobe, k_per_query=kp, nprobe_per_query=npp, record=rec, **kw)
+    dade.dade_search(gi, Qd, K, nprobe, k_per_query=kp, nprobe_per_query=npp, record=rec, out_ids=ids2,
+                     out_dist2=d22, **kw)
     torch.cuda.synchronize()
-    assert rec["graph"] == 2, rec   # the same arguments again: the captured list scan replayed
-    if one_launch:   # the whole batch in one pass: one graph launch runs every round of every query
-        assert rec["passes"] == 1, rec
+    assert rec["graph"] == 2, rec   # every pass's rounds replayed by one hipGraphLaunch
     print(f"[{name}] search record {rec}")
     dade.dade_check(gi)
     ids, d2, st = to_np(ids), to_np(d2), to_np(stats)
@@ -118,12 +119,12 @@ def test_fullsize_scale_f32():
 def test_fullsize_uneven_batch():
     """2M x 256, BF16 store, 4096 queries with per-query K in {1, 10, 50, 100} and nprobe in
     8..128 (seeded), nlist 4096; Delta_d, the round shape and the launch shape from the
-    autotuner (on the first 512 queries), the oracle run with the chosen values; the batch's list
-    scan is one pass, replayed as one captured graph."""
+    autotuner (on the first 512 queries), the oracle run with the chosen values; the list scan of
+    the whole batch (every pass) is replayed as one captured graph."""
     w = workloads.WORKLOADS["uneven-2m-d256"]
     K, npb = workloads.uneven_batch(w.n_queries, 8, 128, (1, 10, 50, 100), seed=w.seed)
     run_workload("uneven-2m-d256", p_s=0.1, nprobe=128, n_sample=20, k_per_query=K, nprobe_per_query=npb, k=100,
-                 tune=512, one_launch=True)
+                 tune=512)
 
 
 def test_fullsize_serving_mix():
