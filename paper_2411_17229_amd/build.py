@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.environ.get("DADE_CSRC", os.path.join(HERE, "csrc"))
 BUILD = os.environ.get("DADE_BUILD", os.path.join(ROOT, "_build"))
 LIB = os.environ.get("DADE_LIB", os.path.join(HERE, "libdade.so"))
-SOURCES = ["dade_api.hip", "gemm.hip", "misc.hip", "fp64.hip", "select.hip", "scan.hip", "serve.hip", "tune.hip", "graph.hip"]
+SOURCES = ["dade_api.hip", "gemm.hip", "misc.hip", "fp64.hip", "select.hip", "probe.hip", "scan.hip", "serve.hip", "tune.hip", "graph.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstring>
 #include <cstdlib>
+#include <limits>
 #include <mutex>
 #include <numeric>
 #include <string>
@@ -69,6 +70,9 @@ struct dade_index {
   int ldB = 0;                 // dp + nlist rounded up to a multiple of 4 (float4 rows)
   float* d_mu = nullptr;       // [dp]
   float* d_cent_norm = nullptr;// [nlist] ||c - mu||^2
+  float* d_cx = nullptr;       // [nlist x dp] c - mu (FP32), the probe refinement's exact rows
+  float* d_cnorm = nullptr;    // [nlist] upper bounds of ||c - mu||
+  uint16_t* d_cb = nullptr;    // bf16 c - mu in MFMA fragment order (probe_centroid_frags)
   void* d_store = nullptr;     // rotated coordinates in list order, head/tail layout (stored_index)
   float* d_T = nullptr;        // [dim]
   // host artifacts
@@ -78,6 +82,7 @@ struct dade_index {
   std::vector<int64_t> sizes_desc;   // list sizes, largest first (round capacities)
   // search workspace (grown on demand, each with its element count)
   float* w_qpad = nullptr; float* w_qrot = nullptr; float* w_pd = nullptr;
+  void* w_a1 = nullptr;        // [probe_a_bytes(w_nq, dp)] bf16 queries of the probe selection
   int32_t* w_probes = nullptr;
   int64_t w_nq = 0, w_np = 0;
   unsigned long long* w_topk = nullptr; int64_t w_topk_n = 0;
@@ -98,6 +103,8 @@ struct dade_index {
   int kev_rounds = 0, kev_passes = 0;
   int cus = 256;
   hipStream_t cap = nullptr;   // origin stream of graph captures (the caller's may be the null stream)
+  hipStream_t side = nullptr;  // the query rotation, concurrent with the probe selection
+  hipEvent_t fork = nullptr, join = nullptr;
   // the last captured round-launch sequence and the argument bytes it was captured with
   hipGraphExec_t graph_exec = nullptr;
   const float* last_q = nullptr;   // the query buffer of the last search
@@ -274,12 +281,35 @@ int apply_transform(dade_index* ix, hipStream_t s) {
     cn[l] = float(nrm);
   }
   for (int i = 0; i < dim; ++i) muf[i] = float(ix->mu[i]);
+  // probe selection: c - mu as FP32 rows (the same values as B's columns), upper bounds of their
+  // norms (FP64 over those values, rounded up), and their bf16 fragments
+  std::vector<float> cx(size_t(nl) * dp, 0.f), cnorm(nl, 0.f);
+  for (int l = 0; l < nl; ++l) {
+    double ss = 0.0;
+    for (int i = 0; i < dim; ++i) {
+      const float v = Bf[size_t(i) * ldb + dp + l];
+      cx[size_t(l) * dp + i] = v;
+      ss += double(v) * double(v);
+    }
+    const double up = std::sqrt(ss) * (1.0 + 0x1p-40);
+    float f = float(up);
+    if (double(f) < up) f = std::nextafter(f, std::numeric_limits<float>::infinity());
+    cnorm[l] = f;
+  }
+  std::vector<uint16_t> cb(probe_centroid_frag_count(nl, dp));
+  probe_centroid_frags(cx.data(), nl, dp, cb.data());
   if (!ix->d_B && (rc = alloc_t(ix, &ix->d_B, Bf.size()))) return rc;
   if (!ix->d_mu && (rc = alloc_t(ix, &ix->d_mu, dp))) return rc;
   if (!ix->d_cent_norm && (rc = alloc_t(ix, &ix->d_cent_norm, nl))) return rc;
+  if (!ix->d_cx && (rc = alloc_t(ix, &ix->d_cx, cx.size()))) return rc;
+  if (!ix->d_cnorm && (rc = alloc_t(ix, &ix->d_cnorm, nl))) return rc;
+  if (!ix->d_cb && (rc = alloc_t(ix, &ix->d_cb, cb.size()))) return rc;
   HIPC(hipMemcpyAsync(ix->d_B, Bf.data(), sizeof(float) * Bf.size(), hipMemcpyHostToDevice, s));
   HIPC(hipMemcpyAsync(ix->d_mu, muf.data(), sizeof(float) * dp, hipMemcpyHostToDevice, s));
   HIPC(hipMemcpyAsync(ix->d_cent_norm, cn.data(), sizeof(float) * nl, hipMemcpyHostToDevice, s));
+  HIPC(hipMemcpyAsync(ix->d_cx, cx.data(), sizeof(float) * cx.size(), hipMemcpyHostToDevice, s));
+  HIPC(hipMemcpyAsync(ix->d_cnorm, cnorm.data(), sizeof(float) * nl, hipMemcpyHostToDevice, s));
+  HIPC(hipMemcpyAsync(ix->d_cb, cb.data(), sizeof(uint16_t) * cb.size(), hipMemcpyHostToDevice, s));
 
   // packed store: row p = W^T (X[ids[p]] - mu), in list order
   if (!ix->d_store && (rc = dev_alloc(ix, &ix->d_store, size_t(ix->n) * dp * dtype_size(ix->store)))) return rc;
@@ -315,18 +345,23 @@ int grow_query_workspace(dade_index* ix, int64_t nq, int64_t npm, hipStream_t s)
     dev_free(ix, ix->w_qrot, sizeof(float) * ix->w_nq * dp);
     dev_free(ix, ix->w_pd, sizeof(float) * ix->w_nq * nl);
     dev_free(ix, ix->w_probes, sizeof(int32_t) * ix->w_nq * ix->w_np);
+    dev_free(ix, ix->w_a1, probe_a_bytes(int(ix->w_nq), dp));
     ix->w_qpad = ix->w_qrot = ix->w_pd = nullptr;
     ix->w_probes = nullptr;
+    ix->w_a1 = nullptr;
     ix->w_nq = ix->w_np = 0;
     if ((rc = alloc_t(ix, &ix->w_qpad, size_t(new_nq) * dp)) || (rc = alloc_t(ix, &ix->w_qrot, size_t(new_nq) * dp)) ||
-        (rc = alloc_t(ix, &ix->w_pd, size_t(new_nq) * nl)) || (rc = alloc_t(ix, &ix->w_probes, size_t(new_nq) * new_np))) {
+        (rc = alloc_t(ix, &ix->w_pd, size_t(new_nq) * nl)) || (rc = alloc_t(ix, &ix->w_probes, size_t(new_nq) * new_np)) ||
+        (rc = dev_alloc(ix, &ix->w_a1, probe_a_bytes(int(new_nq), dp)))) {
       // leave no part of the workspace behind (the next search grows it again)
       dev_free(ix, ix->w_qpad, sizeof(float) * new_nq * dp);
       dev_free(ix, ix->w_qrot, sizeof(float) * new_nq * dp);
       dev_free(ix, ix->w_pd, sizeof(float) * new_nq * nl);
       dev_free(ix, ix->w_probes, sizeof(int32_t) * new_nq * new_np);
+      dev_free(ix, ix->w_a1, probe_a_bytes(int(new_nq), dp));
       ix->w_qpad = ix->w_qrot = ix->w_pd = nullptr;
       ix->w_probes = nullptr;
+      ix->w_a1 = nullptr;
       return rc;
     }
     ix->w_nq = new_nq; ix->w_np = new_np;
@@ -349,8 +384,9 @@ struct SearchPlan {
 struct Workspace {
   float* qpad = nullptr;             // [nq x dp] padded queries (when not read in place)
   float* qrot = nullptr;             // [nq x dp] rotated queries
-  float* pd = nullptr;               // [nq x nlist] centroid terms
+  float* pd = nullptr;               // [nq x nlist] centroid terms, or the probe selection's bounds
   int32_t* probes = nullptr;         // [nq x npm]
+  void* a1 = nullptr;                // [probe_a_bytes(nq, dp)] bf16 queries of the probe selection
   unsigned long long* topk = nullptr;   // [chunk x k]
   unsigned long long* keyr = nullptr;   // [chunk]
   float* r2 = nullptr;               // [chunk]
@@ -412,7 +448,7 @@ int grow_workspace(dade_index* ix, int64_t nq, int32_t k, const SearchPlan& pl, 
       (rc = grow(ix, &ix->w_counter, ix->w_counter_n, pl.rounds, s)) ||
       (rc = grow(ix, &ix->w_counts, ix->w_counts_n, int64_t(pl.rounds) * chunk, s)))
     return rc;
-  ws.qpad = ix->w_qpad; ws.qrot = ix->w_qrot; ws.pd = ix->w_pd; ws.probes = ix->w_probes;
+  ws.qpad = ix->w_qpad; ws.qrot = ix->w_qrot; ws.pd = ix->w_pd; ws.probes = ix->w_probes; ws.a1 = ix->w_a1;
   ws.topk = ix->w_topk; ws.keyr = ix->w_keyr; ws.r2 = ix->w_r2; ws.qint = ix->w_qint;
   ws.kb = ix->w_kb; ws.items = ix->w_items; ws.counter = ix->w_counter; ws.counts = ix->w_counts;
   ws.chunk = chunk;
@@ -433,7 +469,8 @@ int index_prepare_search(dade_index* ix, int64_t nq, int32_t k, int32_t nprobe, 
   const int rc = grow_workspace(ix, nq, k, pl, s, ws);
   if (rc) return rc;
   const int64_t dp = ix->dp, nl = ix->nlist;
-  *workspace_bytes = ix->w_nq * (2 * dp * 4 + nl * 4 + ix->w_np * 4) + ix->w_topk_n * 8 + ix->w_keyr_n * 8 +
+  *workspace_bytes = ix->w_nq * (2 * dp * 4 + nl * 4 + ix->w_np * 4) + int64_t(probe_a_bytes(int(ix->w_nq), int(dp))) +
+                     ix->w_topk_n * 8 + ix->w_keyr_n * 8 +
                      ix->w_r2_n * 4 + ix->w_qint_n * 4 + ix->w_kb_n * 8 + ix->w_items_n * 16 + ix->w_counter_n * 4 +
                      ix->w_counts_n * 4;
   return DADE_OK;
@@ -478,6 +515,7 @@ size_t align_up(size_t x) { return (x + kScratchAlign - 1) / kScratchAlign * kSc
 size_t slice_bytes(const dade_index* ix, const SearchPlan& pl, int32_t k, int64_t cn) {
   const size_t dp = size_t(ix->dp), nl = size_t(ix->nlist), c = size_t(cn);
   return align_up(c * dp * 4) * 2 + align_up(c * nl * 4) + align_up(c * size_t(pl.npm) * 4) +
+         align_up(probe_a_bytes(int(cn), ix->dp)) +
          align_up(c * size_t(k) * 8) + align_up(c * 8) + align_up(c * 4) + align_up(c * 12) +
          align_up(c * size_t(pl.kb_cap) * 8) + align_up(size_t(pl.rounds) * c * size_t(pl.items_pq) * 16) +
          align_up(size_t(pl.rounds) * 4) + align_up(size_t(pl.rounds) * c * 4);
@@ -497,6 +535,7 @@ Workspace carve(char* base, const dade_index* ix, const SearchPlan& pl, int32_t 
   ws.qrot = reinterpret_cast<float*>(take(c * dp * 4));
   ws.pd = reinterpret_cast<float*>(take(c * nl * 4));
   ws.probes = reinterpret_cast<int32_t*>(take(c * size_t(pl.npm) * 4));
+  ws.a1 = take(probe_a_bytes(int(cn), ix->dp));
   ws.topk = reinterpret_cast<unsigned long long*>(take(c * size_t(k) * 8));
   ws.keyr = reinterpret_cast<unsigned long long*>(take(c * 8));
   ws.r2 = reinterpret_cast<float*>(take(c * 4));
@@ -520,6 +559,9 @@ void dade_destroy(dade_index* ix) {
   for (void* p : ix->owned) (void)hipFree(p);
   if (ix->graph_exec) (void)hipGraphExecDestroy(ix->graph_exec);
   if (ix->cap) (void)hipStreamDestroy(ix->cap);
+  if (ix->side) (void)hipStreamDestroy(ix->side);
+  if (ix->fork) (void)hipEventDestroy(ix->fork);
+  if (ix->join) (void)hipEventDestroy(ix->join);
   for (hipEvent_t e : ix->kev) (void)hipEventDestroy(e);
   if (ix->ev_made)
     for (auto& e : ix->ev) (void)hipEventDestroy(e);
@@ -950,9 +992,9 @@ static int search_impl(dade_index* ix, const float* Q, int64_t ldq, int64_t nq, 
     ix->ev_made = true;
   }
   if (o.record_times) HIPC(hipEventRecord(ix->ev[0], s));
-  // a1 + a2: one GEMM gives q' = W^T (q - mu) and the centroid distances (up to ||q - mu||^2,
-  // the same for every list); then the probe order by (distance, list id)
-  // Queries already of the padded width (and float4-aligned) are read in place, without the
+  // a1: q' = W^T (q - mu) on the FP32 matrix cores; a2: the probe order by (distance, list
+  // id), from bf16 products for every centroid refined in FP32 where a rigorous bound cannot
+  // decide.  Queries already of the padded width (and float4-aligned) are read in place, without the
   // padding copy.  The captured launch sequence holds the query pointer, so with graphs on only
   // a buffer passed again (a serving loop's) is read in place; a new buffer is copied, which
   // keeps the captured sequence valid.
@@ -962,13 +1004,31 @@ static int search_impl(dade_index* ix, const float* Q, int64_t ldq, int64_t nq, 
   const float* qpad = q_in_place ? Q : ws.qpad;
   if (!q_in_place) HIPC(launch_pad_rows(Q, nq, ix->dim, ldq, ws.qpad, dp, s));
   GemmArgs g;
-  g.M = int(nq); g.N = dp + nl; g.K = dp;
+  g.M = int(nq); g.N = dp; g.K = dp;
   g.A = qpad; g.lda = dp; g.a_shift = ix->d_mu;
   g.B = ix->d_B; g.ldb = ix->ldB; g.C = ws.qrot; g.ldc = dp;
-  g.split_col = dp; g.C2 = ws.pd; g.ldc2 = nl; g.col_norm = ix->d_cent_norm;
-  HIPC(launch_gemm(g, kEpiRotateProbe, s));
+  g.split_col = dp;   // every column is a rotated coordinate
+  // The rotation runs on an internal stream beside the probe selection (both only read the
+  // queries), joined before the list scan; timed searches and the fixed-workspace entry point
+  // run them in turn.
+  const bool overlap = !fixed && !o.record_times;
+  if (overlap) {
+    if (!ix->side) HIPC(hipStreamCreateWithFlags(&ix->side, hipStreamNonBlocking));
+    if (!ix->fork) HIPC(hipEventCreateWithFlags(&ix->fork, hipEventDisableTiming));
+    if (!ix->join) HIPC(hipEventCreateWithFlags(&ix->join, hipEventDisableTiming));
+    HIPC(hipEventRecord(ix->fork, s));
+    HIPC(hipStreamWaitEvent(ix->side, ix->fork, 0));
+  }
+  HIPC(launch_gemm(g, kEpiRotateProbe, overlap ? ix->side : s));
+  if (overlap) HIPC(hipEventRecord(ix->join, ix->side));
   if (o.record_times) HIPC(hipEventRecord(ix->ev[1], s));
-  HIPC(launch_select_probes(ws.pd, nl, int(nq), nl, npm, ws.probes, s));
+  ProbeArgs pa;
+  pa.M = int(nq); pa.dp = dp; pa.nl = nl; pa.npm = npm;
+  pa.q = qpad; pa.ldq = dp; pa.mu = ix->d_mu;
+  pa.cb = ix->d_cb; pa.cx = ix->d_cx; pa.cn = ix->d_cent_norm; pa.cnorm = ix->d_cnorm;
+  pa.a1 = ws.a1; pa.bnd = reinterpret_cast<uint32_t*>(ws.pd); pa.probes = ws.probes;
+  HIPC(launch_probe_select(pa, s));
+  if (overlap) HIPC(hipStreamWaitEvent(s, ix->join, 0));
   if (o.record_times) HIPC(hipEventRecord(ix->ev[2], s));
   // a3-a6: the list scan, in rounds, `chunk` queries at a time
   RoundArgs ra;

@@ -39,6 +39,34 @@ struct GemmArgs {
 };
 hipError_t launch_gemm(const GemmArgs& a, GemmEpilogue epi, hipStream_t s);
 
+// ---------------------------------------------------------------- probe selection (probe.hip)
+// The nprobe nearest lists of each query by t(c) = ||c - mu||^2 - 2 (q - mu).(c - mu), ties by
+// list id, ascending: bf16 matrix-core products for every centroid, then the lists a rigorous
+// error bound cannot rule out evaluated in FP32.  q: [M x ldq] FP32 queries (16-byte aligned,
+// ldq % 4 == 0, zero-padded to dp); cb: the centroid fragments of probe_centroid_frags; cx:
+// [nl x dp] FP32 c - mu; cn: [nl] ||c - mu||^2 in FP32; cnorm: [nl] upper bounds of ||c - mu||;
+// a1: scratch of probe_a_bytes(M, dp) bytes; bnd: scratch [M x nl] (bounds of every list's
+// term).
+struct ProbeArgs {
+  int M = 0, dp = 0, nl = 0, npm = 0;
+  const float* q = nullptr;
+  int ldq = 0;
+  const float* mu = nullptr;
+  const void* cb = nullptr;
+  const float* cx = nullptr;
+  const float* cn = nullptr;
+  const float* cnorm = nullptr;
+  void* a1 = nullptr;
+  uint32_t* bnd = nullptr;
+  int32_t* probes = nullptr;   // [M x npm]
+};
+hipError_t launch_probe_select(const ProbeArgs& p, hipStream_t s);
+size_t probe_a_bytes(int M, int dp);
+// bf16 (c - mu) in MFMA fragment order, columns padded with zeros to a multiple of 128:
+// probe_centroid_frag_count(nl, dp) values from the [nl x dp] FP32 rows cx.
+size_t probe_centroid_frag_count(int nl, int dp);
+void probe_centroid_frags(const float* cx, int nl, int dp, uint16_t* out);
+
 // ---------------------------------------------------------------- small kernels (misc.hip)
 // dst[r][c] = src[r * lds + c] for c < cols, 0 up to ld.
 hipError_t launch_pad_rows(const float* src, int64_t rows, int cols, int64_t lds, float* dst, int ld,

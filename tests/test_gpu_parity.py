@@ -107,6 +107,23 @@ def test_all_lists_full_d_is_brute_force(small):
             assert abs(d - gd[qi, -1]) <= 1e-5 * gd[qi, -1], (qi, i)
 
 
+@pytest.mark.parametrize("nprobe", [100, 160])
+def test_probe_selection_beyond_64_probes(small, nprobe):
+    """160 lists and 100 or all 160 probes (the probe selection's threshold from a radix
+    selection rather than the lane-minimum search): DADE results and DCO counts as the oracle's."""
+    w = small["w"]
+    X, Q = small["X"], small["Q"][:60]
+    oi, _, _ = oracle_index(X, 160, w.seed, alpha=w.alpha)
+    gi = dade.dade_import(artifacts(oi), small["Xd"])
+    o = oracle_ivf(oi, Q, w.k, nprobe, w.delta_d)
+    stats = torch.zeros((len(Q), 4), dtype=torch.int64, device="cuda")
+    g_ids, g_d2 = gpu_search(gi, small["Qd"][:60].contiguous(), w.k, nprobe, delta_d=w.delta_d, stats=stats)
+    compare(o, g_ids, g_d2, X, Q, w.k)
+    same = o.logs["probe_gap"] > 1e-5   # no near tie in the probe order: the same candidates
+    np.testing.assert_array_equal(to_np(stats)[same, 0], o.logs["dcos"][same].astype(np.int64))
+    gi.close()
+
+
 def _integer_index(store, delta):
     """An index on which every FP32 operation of the search is exact: integer coordinates in
     [0, 3] (duplicate rows included), W = I, mu = 0, integer centroids (some rows), lists by
