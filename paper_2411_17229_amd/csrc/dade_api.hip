@@ -1019,7 +1019,7 @@ static int search_impl(dade_index* ix, const float* Q, int64_t ldq, int64_t nq, 
     HIPC(hipEventRecord(ix->fork, s));
     HIPC(hipStreamWaitEvent(ix->side, ix->fork, 0));
   }
-  HIPC(launch_gemm(g, kEpiRotateProbe, overlap ? ix->side : s));
+  HIPC(launch_gemm_rotate(g, overlap ? ix->side : s));
   if (overlap) HIPC(hipEventRecord(ix->join, ix->side));
   if (o.record_times) HIPC(hipEventRecord(ix->ev[1], s));
   ProbeArgs pa;

@@ -38,6 +38,8 @@ struct GemmArgs {
   int ldc2 = 0;
 };
 hipError_t launch_gemm(const GemmArgs& a, GemmEpilogue epi, hipStream_t s);
+// q' = (q - mu) W only (kEpiRotateProbe, N <= split_col), tiled for small M x N.
+hipError_t launch_gemm_rotate(const GemmArgs& a, hipStream_t s);
 
 // ---------------------------------------------------------------- probe selection (probe.hip)
 // The nprobe nearest lists of each query by t(c) = ||c - mu||^2 - 2 (q - mu).(c - mu), ties by

@@ -14,7 +14,7 @@
 //     2^-8 per factor), FP32 accumulation over dp terms (relative 2^-23 per addition, which also
 //     covers a truncating adder) and Cauchy-Schwarz (sum |q_i c_i| <= ||q - mu|| ||c - mu||).
 //     The kernel writes the bits of floats just above t~ + E and just below t~ - E;
-//  3. refine_kernel, one wave per query: with U such that at least nprobe upper bounds are at or
+//  3. refine_kernel, one workgroup per query: with U such that at least nprobe upper bounds are at or
 //     below it, every list whose lower bound exceeds U has t above the t of nprobe other lists,
 //     so it cannot be a probe.  The remaining lists (typically a few more than nprobe) get t in
 //     FP32 from the FP32 vectors, and the nprobe smallest by (t, list id) are the probes,
@@ -195,50 +195,61 @@ struct RefineArgs {
 };
 
 constexpr int kRefineMaxChunks = 16;   // dp <= 16 x 64
-constexpr int kBatch = 16;             // columns a lane loads per batch (1024 per wave)
+constexpr int kRefineThreads = 256;    // one workgroup (four waves) per query
+constexpr int kBatch = 16;             // columns a thread loads per batch
 
-// One wave per query; the row of packed bounds is streamed in batches of kBatch columns per lane
-// (loads clamped in range, so none waits on a branch).
-__global__ __launch_bounds__(64) void refine_kernel(RefineArgs a) {
+// One workgroup per query; the row of packed bounds is streamed in batches of kBatch columns per
+// thread (loads clamped in range, so none waits on a branch).
+__global__ __launch_bounds__(kRefineThreads) void refine_kernel(RefineArgs a) {
   extern __shared__ unsigned long long sel[];   // P entries: candidate columns, then their keys
   __shared__ uint32_t hist[256];
+  __shared__ uint32_t s_cnt[kRefineThreads / 64];
+  __shared__ int s_total;
   const int q = blockIdx.x;
-  const int lane = threadIdx.x;
-  const int g = lane >> 4, gl = lane & 15;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int g = tid >> 4, gl = tid & 15;
   const float* qrow = a.q + int64_t(q) * a.ldq;
   const uint32_t* brow = a.bnd + int64_t(q) * a.nl;
-  const int nbatch = (a.nl + 64 * kBatch - 1) / (64 * kBatch);
+  constexpr int kStride = kRefineThreads * kBatch;
+  const int nbatch = (a.nl + kStride - 1) / kStride;
+  auto col = [&](int b, int j) { return kStride * b + kRefineThreads * j + tid; };
   // upper bound of column c (16 bits), above every present one for absent columns
   auto upper = [&](uint32_t v, int c) { return c < a.nl ? v >> 16 : 0x10000u; };
+  // workgroup-wide count of a predicate
+  auto count = [&](bool pred) -> uint32_t {
+    const unsigned long long m = __ballot(pred);
+    if (lane == 0) s_cnt[wave] = uint32_t(__popcll(m));
+    __syncthreads();
+    uint32_t t = 0;
+#pragma unroll
+    for (int w = 0; w < kRefineThreads / 64; ++w) t += s_cnt[w];
+    __syncthreads();
+    return t;
+  };
   // U: a value with at least npm upper bounds at or below it.  Any such U is sound: those npm
   // lists have t <= U, and a list whose lower bound exceeds U has t > U.
   uint32_t U;
-  if (a.npm <= 64) {
-    // the npm-th smallest lane minimum (the npm smallest minima come from distinct lanes)
+  if (a.npm <= kRefineThreads) {
+    // the npm-th smallest thread minimum (the npm smallest minima come from distinct threads;
+    // at least min(nl, 256) >= npm threads hold a column)
     uint32_t mn = 0x10000u;
     for (int b = 0; b < nbatch; ++b) {
       uint32_t v[kBatch];
 #pragma unroll
       for (int j = 0; j < kBatch; ++j) {
-        const int c = 64 * (kBatch * b + j) + lane;
+        const int c = col(b, j);
         v[j] = brow[c < a.nl ? c : a.nl - 1];
       }
 #pragma unroll
       for (int j = 0; j < kBatch; ++j) {
-        const uint32_t ub = upper(v[j], 64 * (kBatch * b + j) + lane);
+        const uint32_t ub = upper(v[j], col(b, j));
         mn = ub < mn ? ub : mn;
       }
     }
-    uint32_t x = mn, y = mn;
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) {
-      const uint32_t x2 = __shfl_xor(x, o, 64), y2 = __shfl_xor(y, o, 64);
-      x = x2 < x ? x2 : x;
-      y = y2 > y ? y2 : y;
-    }
+    uint32_t x = 0u, y = 0x10000u;
     while (x < y) {
       const uint32_t mid = x + (y - x) / 2;
-      if (__popcll(__ballot(mn <= mid)) >= a.npm) y = mid;
+      if (count(mn <= mid) >= uint32_t(a.npm)) y = mid;
       else x = mid + 1;
     }
     U = x;
@@ -246,84 +257,96 @@ __global__ __launch_bounds__(64) void refine_kernel(RefineArgs a) {
     // the npm-th smallest upper bound: radix selection on its two bytes, LDS histograms
     uint32_t prefix = 0, need = uint32_t(a.npm);
     for (int digit = 1; digit >= 0; --digit) {
-      for (int i = lane; i < 256; i += 64) hist[i] = 0;
+      for (int i = tid; i < 256; i += kRefineThreads) hist[i] = 0;
       __syncthreads();
       for (int b = 0; b < nbatch; ++b) {
         uint32_t v[kBatch];
 #pragma unroll
         for (int j = 0; j < kBatch; ++j) {
-          const int c = 64 * (kBatch * b + j) + lane;
+          const int c = col(b, j);
           v[j] = brow[c < a.nl ? c : a.nl - 1];
         }
 #pragma unroll
         for (int j = 0; j < kBatch; ++j) {
-          const int c = 64 * (kBatch * b + j) + lane;
+          const int c = col(b, j);
           const uint32_t ub = upper(v[j], c);
           if (c < a.nl && (digit == 1 || (ub >> 8) == prefix)) atomicAdd(&hist[(ub >> (8 * digit)) & 0xFFu], 1u);
         }
       }
       __syncthreads();
-      // the first bin whose inclusive prefix count reaches `need`: lane l holds bins 4 l .. 4 l + 3
-      uint32_t h[4], sum = 0;
+      // the first bin whose inclusive prefix count reaches `need`, found by wave 0 (lane l holds
+      // bins 4 l .. 4 l + 3); every thread reads the result from LDS
+      if (wave == 0) {
+        uint32_t h[4], sum = 0;
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        h[k] = hist[4 * lane + k];
-        sum += h[k];
-      }
-      uint32_t incl = sum;   // inclusive scan over lanes
-#pragma unroll
-      for (int o = 1; o < 64; o <<= 1) {
-        const uint32_t y = __shfl_up(incl, o, 64);
-        if (lane >= o) incl += y;
-      }
-      uint32_t before = incl - sum;
-      int bin = -1;
-      uint32_t below = 0;
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        if (bin < 0 && before + h[k] >= need) {
-          bin = 4 * lane + k;
-          below = before;
+        for (int k = 0; k < 4; ++k) {
+          h[k] = hist[4 * lane + k];
+          sum += h[k];
         }
-        before += h[k];
+        uint32_t incl = sum;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+          const uint32_t y = __shfl_up(incl, o, 64);
+          if (lane >= o) incl += y;
+        }
+        uint32_t before = incl - sum;
+        int bin = -1;
+        uint32_t below = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          if (bin < 0 && before + h[k] >= need) {
+            bin = 4 * lane + k;
+            below = before;
+          }
+          before += h[k];
+        }
+        const unsigned long long m = __ballot(bin >= 0);
+        const int src = __builtin_ctzll(m);
+        if (lane == src) {
+          s_cnt[0] = uint32_t(bin);
+          s_cnt[1] = below;
+        }
       }
-      // the lowest lane that found the crossing holds it
-      const unsigned long long m = __ballot(bin >= 0);
-      const int src = __builtin_ctzll(m);
-      const int pick = __shfl(bin, src, 64);
-      need -= __shfl(below, src, 64);
-      prefix = (prefix << 8) | uint32_t(pick);
+      __syncthreads();
+      prefix = (prefix << 8) | s_cnt[0];
+      need -= s_cnt[1];
       __syncthreads();
     }
     U = prefix;
   }
-  // candidates, the lists whose lower bound is at most U
-  int total = 0;
+  // candidates, the lists whose lower bound is at most U (their order in sel does not matter:
+  // they are sorted by key below)
+  if (tid == 0) s_total = 0;
+  __syncthreads();
   for (int b = 0; b < nbatch; ++b) {
     uint32_t v[kBatch];
 #pragma unroll
     for (int j = 0; j < kBatch; ++j) {
-      const int c = 64 * (kBatch * b + j) + lane;
+      const int c = col(b, j);
       v[j] = brow[c < a.nl ? c : a.nl - 1];
     }
 #pragma unroll
     for (int j = 0; j < kBatch; ++j) {
-      const int c = 64 * (kBatch * b + j) + lane;
+      const int c = col(b, j);
       const bool take = c < a.nl && (v[j] & 0xFFFFu) <= U;
       const unsigned long long m = __ballot(take);
+      int base = 0;
+      if (lane == 0 && m) base = atomicAdd(&s_total, __popcll(m));
+      base = __shfl(base, 0, 64);
       if (take) {
         const int below = int(__builtin_amdgcn_mbcnt_hi(uint32_t(m >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(m), 0u)));
-        sel[total + below] = uint64_t(uint32_t(c));
+        sel[base + below] = uint64_t(uint32_t(c));
       }
-      total += __popcll(m);
     }
   }
   __syncthreads();
+  const int total = s_total;
   const int nch = a.dp / 4;   // float4 chunks of a row
-  // t in FP32 for the candidates, four at a time: lane group g takes candidate i0 + g, its lanes
-  // the float4 chunks 16 ch + lane % 16 (chunks past the row are loaded clamped and weighted zero,
-  // so no load sits behind a branch)
-  for (int i0 = 0; i0 < total; i0 += 4) {
+  // t in FP32 for the candidates, sixteen at a time: group g (16 threads) takes candidate i0 + g,
+  // its threads the float4 chunks 16 ch + tid % 16 (chunks past the row are loaded clamped and
+  // weighted zero, so no load sits behind a branch)
+  constexpr int kGroups = kRefineThreads / 16;
+  for (int i0 = 0; i0 < total; i0 += kGroups) {
     const int i = i0 + g;
     const int c = i < total ? int(uint32_t(sel[i])) : 0;
     const float* crow = a.cx + int64_t(c) * a.dp;
@@ -349,11 +372,11 @@ __global__ __launch_bounds__(64) void refine_kernel(RefineArgs a) {
   }
   int P2 = 1;
   while (P2 < total) P2 <<= 1;
-  for (int i = total + lane; i < P2; i += 64) sel[i] = ~0ull;
+  for (int i = total + tid; i < P2; i += kRefineThreads) sel[i] = ~0ull;
   __syncthreads();
   for (int k = 2; k <= P2; k <<= 1) {
     for (int j = k >> 1; j > 0; j >>= 1) {
-      for (int i = lane; i < P2; i += 64) {
+      for (int i = tid; i < P2; i += kRefineThreads) {
         const int ixj = i ^ j;
         if (ixj > i) {
           const unsigned long long x = sel[i], y = sel[ixj];
@@ -366,7 +389,7 @@ __global__ __launch_bounds__(64) void refine_kernel(RefineArgs a) {
       __syncthreads();
     }
   }
-  for (int i = lane; i < a.npm; i += 64) a.probes[int64_t(q) * a.npm + i] = int32_t(key_id(sel[i]));
+  for (int i = tid; i < a.npm; i += kRefineThreads) a.probes[int64_t(q) * a.npm + i] = int32_t(key_id(sel[i]));
 }
 
 int ks_padded(int dp) { return (dp / 16 + kPrefetch - 1) / kPrefetch * kPrefetch; }
@@ -433,7 +456,7 @@ hipError_t launch_probe_select(const ProbeArgs& p, hipStream_t s) {
   r.probes = p.probes;
   int P = 1;
   while (P < p.nl) P <<= 1;
-  hipLaunchKernelGGL(refine_kernel, dim3(p.M), dim3(64), size_t(P) * sizeof(unsigned long long), s, r);
+  hipLaunchKernelGGL(refine_kernel, dim3(p.M), dim3(kRefineThreads), size_t(P) * sizeof(unsigned long long), s, r);
   return hipGetLastError();
 }
 
