@@ -235,9 +235,8 @@ hipError_t launch_epi(const GemmArgs& a, hipStream_t s) {
 
 }  // namespace
 
-// The query rotation (kEpiRotateProbe with N = split_col).  64 x 64 tiles with 16-deep K slices
-// (measured faster here than 32- or 64-deep slices, whose larger LDS tiles leave fewer
-// workgroups resident).
+// The query rotation (kEpiRotateProbe with N = split_col): 64 x 64 tiles with 16-deep K slices
+// (at 1000 x 960 x 960, 45 us against 51 us with 64-deep slices).
 hipError_t launch_gemm_rotate(const GemmArgs& a, hipStream_t s) {
   if (a.K % 16 != 0 || a.lda % 4 != 0 || a.ldb % 4 != 0 || a.N > a.split_col) return hipErrorInvalidValue;
   return launch_tile<64, 64, 16, kEpiRotateProbe>(a, s);
