@@ -87,13 +87,14 @@ def traffic_from_profile(workload, store, nprobe, p_s):
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    e = rec.get(f"{workload}/{store}/nprobe{nprobe}/p_s{p_s}/fill{SCHEDULE['fill_min']}/growth{SCHEDULE['growth']}")
+    e = rec.get(f"{workload}/{store}/nprobe{nprobe}/p_s{p_s}/{SCHEDULE['schedule']}/fill{SCHEDULE['fill_min']}"
+                f"/growth{SCHEDULE['growth']}")
     if not e or e.get("scan_sha") != scan_source_sha():
         return None
     return e["fetch_bytes_per_launch"] + e["write_bytes_per_launch"]
 
 
-SCHEDULE = dict(schedule="doubling", fill_min=32, growth=0)   # round schedule of the timed runs (no growth cap)
+SCHEDULE = dict(schedule="whole", fill_min=32, growth=0)   # round schedule of the timed runs: the fill round, then the rest
 
 
 def throughput(dade, torch, ix, Qd, k, nprobe, steps, warmup, **kw):
@@ -188,6 +189,7 @@ def cpu_baseline(w, X, Q, art, store, nprobe, p_s, rerank, gt, seconds=20.0):
         np.savez(path, **{k_: art[k_] for k_ in CPU_ART_KEYS}, delta=np.array(art["delta"]))
         r = subprocess.run([sys.executable, os.path.abspath(__file__), "--oracle-pool", path, "--workload", w.name,
                             "--store", store, "--nprobe", str(nprobe), "--p-s", str(p_s), "--rerank", rerank,
+                            "--schedule", SCHEDULE["schedule"],
                             "--cpu-seconds", str(seconds)], capture_output=True, text=True, timeout=900)
     if r.returncode == 0 and r.stdout.strip():
         out["all_cores"] = json.loads(r.stdout.strip().splitlines()[-1])
@@ -538,6 +540,8 @@ def main():
     ap.add_argument("--nprobe", type=int, default=None)
     ap.add_argument("--p-s", type=float, default=None)
     ap.add_argument("--mode", default="dade")
+    ap.add_argument("--schedule", default=SCHEDULE["schedule"], choices=("per_rank", "doubling", "whole"),
+                    help="round schedule of the timed runs (fill 32, no growth cap)")
     ap.add_argument("--rerank", default="lazy", choices=("all", "lazy"),
                     help="low-precision rerank rule of the timed runs: every survivor that passes the gate, or "
                          "the lazy rule (the default; the other rule is timed beside it)")
@@ -548,6 +552,7 @@ def main():
                     help="only run a plain 1 GiB device copy 5 times (HBM counter calibration)")
     ap.add_argument("--oracle-pool", default=None, help=argparse.SUPPRESS)   # child of the CPU baseline
     args = ap.parse_args()
+    SCHEDULE["schedule"] = args.schedule
     if args.oracle_pool:
         from paper_2411_17229_amd import workloads
         print(json.dumps(oracle_pool(args.oracle_pool, workloads.WORKLOADS[args.workload], args.store, args.nprobe,

@@ -59,9 +59,10 @@ typedef enum { DADE_MODE_DADE = 0, DADE_MODE_FULL_D = 1 } dade_mode;
  * the heap as it was when the round started; the round's accepted candidates are merged at its
  * end.  The first round holds the first max(K, fill_min) candidates.  A later round ends at the
  * next probe-rank boundary of the schedule -- PER_RANK: every rank; DOUBLING: ranks 1, 2, 4,
- * 8, ... -- or once it holds growth times the candidates scanned before it, whichever comes
- * first (growth 0: no such cap). */
-typedef enum { DADE_SCHED_PER_RANK = 0, DADE_SCHED_DOUBLING = 1 } dade_schedule;
+ * 8, ...; WHOLE: none, the probe ranks form one range -- or once it holds growth times the
+ * candidates scanned before it, whichever comes first (growth 0: no such cap; WHOLE with
+ * growth 0 is two rounds: the first one, then the rest). */
+typedef enum { DADE_SCHED_PER_RANK = 0, DADE_SCHED_DOUBLING = 1, DADE_SCHED_WHOLE = 2 } dade_schedule;
 
 /* Index state machine: BUILT -> ROTATED -> CALIBRATED. */
 typedef enum { DADE_STATE_BUILT = 1, DADE_STATE_ROTATED = 2, DADE_STATE_CALIBRATED = 3 } dade_state;

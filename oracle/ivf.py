@@ -20,9 +20,10 @@ Readings where the paper is silent (each is a parameter or stated rule here):
   concatenated in probe order) is split into rounds; every candidate of a round is compared
   against the heap as it was when the round started, and the round's accepted candidates
   are merged in at its end.  The first round is the first max(K, fill_min) candidates (they
-  fill the heap); after it, ``per_rank`` ends a round at every list end and ``doubling`` at
-  the ends of probe ranks 1, 2, 4, 8, ..., and a round is also cut once it holds growth
-  times the candidates scanned before it (``round_starts``); ``sequential`` = one candidate
+  fill the heap); after it, ``per_rank`` ends a round at every list end, ``doubling`` at
+  the ends of probe ranks 1, 2, 4, 8, ..., and ``whole`` only at the end of the sequence; a
+  round is also cut once it holds growth times the candidates scanned before it
+  (``round_starts``); ``sequential`` = one candidate
   per round in list order, i.e. the heap is updated after every DCO exactly as the paper
   describes.
 
@@ -188,6 +189,8 @@ def round_bounds(nprobe: int, schedule: str):
             x *= 2
         b.append(nprobe)
         return list(zip(b[:-1], b[1:]))
+    if schedule == "whole":   # the probe ranks form one range: no cut at a list end
+        return [(0, nprobe)]
     raise ValueError(schedule)
 
 

@@ -402,13 +402,17 @@ struct Workspace {
 SearchPlan plan_sizes(const dade_index* ix, int32_t k, int32_t nprobe, const dade_search_opts& o) {
   const int nl = ix->nlist;
   const int npm = std::min<int>(nprobe, nl);
-  // the most candidates one round can hold (per-rank: one list; doubling: its widest round)
+  // the most candidates one round can hold (per-rank: one list; doubling: its widest round;
+  // whole: every probed list)
   const std::vector<int64_t>& sizes = ix->sizes_desc;
   int widest = 1, rounds = npm + 1;
   if (o.schedule == DADE_SCHED_DOUBLING) {
     int b = 1, nb = 0;
     while (b < npm) { widest = std::max(widest, std::min(2 * b, npm) - b); b *= 2; ++nb; }
     rounds = nb + 2;
+  } else if (o.schedule == DADE_SCHED_WHOLE) {
+    widest = npm;
+    rounds = 2;
   }
   int64_t kb_cap = 0, most = 0;   // most: the largest candidate count a query can have
   for (int i = 0; i < widest && i < nl; ++i) kb_cap += sizes[i];
@@ -957,7 +961,8 @@ static int search_impl(dade_index* ix, const float* Q, int64_t ldq, int64_t nq, 
   const int dd = o.delta_d > 0 ? o.delta_d : std::min(32, ix->dim);
   if (dd < 1 || dd > ix->dim) FAIL(DADE_EINVAL, "delta_d must be in [1, dim]");
   if (o.mode != DADE_MODE_DADE && o.mode != DADE_MODE_FULL_D) FAIL(DADE_EINVAL, "bad mode");
-  if (o.schedule != DADE_SCHED_PER_RANK && o.schedule != DADE_SCHED_DOUBLING) FAIL(DADE_EINVAL, "bad schedule");
+  if (o.schedule != DADE_SCHED_PER_RANK && o.schedule != DADE_SCHED_DOUBLING && o.schedule != DADE_SCHED_WHOLE)
+    FAIL(DADE_EINVAL, "bad schedule");
   if (ix->state < DADE_STATE_ROTATED) FAIL(DADE_ESTATE, "search needs a rotated index");
   if (o.mode == DADE_MODE_DADE && ix->state < DADE_STATE_CALIBRATED) FAIL(DADE_ESTATE, "DADE mode needs a calibrated index");
   if (nq == 0) return DADE_OK;

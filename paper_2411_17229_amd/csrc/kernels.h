@@ -123,7 +123,7 @@ struct RoundArgs {
   int dim = 0;          // real dimensionality D
   int dp = 0;           // padded row length of stored coordinates
   int delta_d = 32;
-  int schedule = 0;     // 0 per-rank, 1 doubling
+  int schedule = 0;     // 0 per-rank, 1 doubling, 2 whole
   int fill_min = 32;    // the first round holds at least this many candidates
   int growth = 16;      // a later round holds at most growth x the candidates before it (0: any)
   int mode = 0;         // 0 DADE, 1 FULL_D

@@ -4,7 +4,7 @@
 //
 // Rounds.  A query's candidate sequence (its probed lists in probe order) is cut into rounds:
 // the first round is its first max(K, fill_min) candidates (they fill the heap), later rounds
-// end where the schedule's probe ranks end (every rank, or ranks 1, 2, 4, 8, ...) or once they
+// end where the schedule's probe ranks end (every rank, ranks 1, 2, 4, 8, ..., or only the last) or once they
 // hold growth times the candidates scanned before them.  Every DCO of a round sees
 // the query's heap as it was when the round started (r^2 and the thresholds T_d r^2 are a
 // snapshot), and the round's kept candidates are merged at its end.  Queries never interact, so
@@ -725,8 +725,8 @@ __device__ inline int4 make_item(int q, int cnt, int p) {
 
 // End (t1, off1) of the round that starts at (t, off) after pos candidates; returns its
 // candidate count.  The first round holds the first max(K, fill_min) candidates; a later round
-// ends at the schedule's next probe-rank boundary (every rank, or ranks 1, 2, 4, ...) or after
-// growth * pos candidates if that comes first (growth 0: no cap).
+// ends at the schedule's next probe-rank boundary (every rank, ranks 1, 2, 4, ..., or none before
+// the last) or after growth * pos candidates if that comes first (growth 0: no cap).
 template <typename LenFn>
 __device__ int64_t round_end(const RoundArgs& a, int t, int off, int64_t pos, bool first, int K, int np,
                              LenFn len_of, int& t1, int& off1) {
@@ -737,11 +737,11 @@ __device__ int64_t round_end(const RoundArgs& a, int t, int off, int64_t pos, bo
   } else {
     if (a.schedule == 0) {
       tb = t + 1;
-    } else {
+    } else if (a.schedule == 1) {
       int B = 1;
       while (B <= t) B <<= 1;
       tb = B < np ? B : np;
-    }
+    }   // schedule 2 (whole): no boundary before np
     rem = a.growth > 0 ? int64_t(a.growth) * pos : INT64_MAX;
   }
   int tt = t, oo = off;

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(HERE, "libdade.so")
 DADE_OK, DADE_EINVAL, DADE_ESTATE, DADE_ENOMEM, DADE_EDEVICE = 0, -1, -2, -3, -4
 DTYPES = {"f32": 0, "bf16": 1, "f16": 2}
 MODES = {"dade": 0, "full_d": 1}
-SCHEDULES = {"per_rank": 0, "doubling": 1}
+SCHEDULES = {"per_rank": 0, "doubling": 1, "whole": 2}
 RERANK_RULES = {"all": 0, "lazy": 1}
 STATE_BUILT, STATE_ROTATED, STATE_CALIBRATED = 1, 2, 3
 EXPORTED = ("dade_build_index", "dade_rotate", "dade_calibrate", "dade_search", "dade_search_noalloc",

@@ -15,8 +15,8 @@ from gpu_helpers import DIST_RTOL, EXCUSE_TOL, compare, exact_d2, oracle_ivf, to
 
 pytestmark = pytest.mark.gpu
 
-SCHEDULE = dict(schedule="doubling", fill_min=32, growth=0)   # the bench's
-RERANK = "all"                                                 # the bench's low-precision rerank rule
+SCHEDULE = dict(schedule="whole", fill_min=32, growth=0)      # the bench's
+RERANK = "lazy"                                                # the bench's low-precision rerank rule
 
 
 def _need_gpu():
@@ -106,9 +106,9 @@ def run_workload(name, p_s, nprobe, n_sample, k_per_query=None, nprobe_per_query
 
 
 def test_fullsize_highd_bench_configuration():
-    """1M x 960, BF16 store + FP32 rerank, 1000 queries, K 10, nprobe 8, P_s 0.005: the bench's
-    operating point and launch configuration."""
-    run_workload("highd-1m-d960", p_s=0.005, nprobe=8, n_sample=60)
+    """1M x 960, BF16 store + FP32 rerank, 1000 queries, K 10, nprobe 2, P_s 0.01, the whole
+    schedule: the bench's operating point and launch configuration."""
+    run_workload("highd-1m-d960", p_s=0.01, nprobe=2, n_sample=60)
 
 
 def test_fullsize_scale_f32():

@@ -37,7 +37,7 @@ def test_full_d_matches_oracle(small, schedule):
     compare(o, g_ids, g_d2, small["X"], small["Q"], w.k)
 
 
-@pytest.mark.parametrize("schedule", ["per_rank", "doubling"])
+@pytest.mark.parametrize("schedule", ["per_rank", "doubling", "whole"])
 def test_dade_matches_oracle(small, schedule):
     w, oi = small["w"], small["oi"]
     o = oracle_ivf(oi, small["Q"], w.k, w.nprobe, w.delta_d, schedule=schedule)
@@ -56,7 +56,7 @@ def test_dade_matches_oracle(small, schedule):
 
 
 @pytest.mark.parametrize("fill_min,growth,schedule", [(0, 0, "per_rank"), (0, 1, "per_rank"), (8, 2, "doubling"),
-                                                      (200, 4, "per_rank")])
+                                                      (200, 4, "per_rank"), (0, 2, "whole")])
 def test_round_size_options(small, fill_min, growth, schedule):
     """First-round minimum and growth cap: the same round cuts as the oracle's, so DCO counts
     agree exactly and results agree up to near ties."""

@@ -169,7 +169,24 @@ def test_round_starts_fill_minimum_and_growth_cap():
     assert rs(np.array([0, 0]), 3, "per_rank") == [0]
 
 
+def test_round_starts_whole_schedule():
+    rs = ivf.round_starts
+    sizes = np.array([5, 7, 3, 4])
+    # no cut at a list end: the fill round, then everything else
+    assert rs(sizes, 3, "whole", 0, 0) == [0, 3, 19]
+    # growth 1 alone cuts the rest: 3 -> 6 -> 12 -> 19
+    assert rs(sizes, 3, "whole", 0, 1) == [0, 3, 6, 12, 19]
+    # one probed list: the same cuts as per-rank and doubling
+    for g in (0, 1, 4):
+        assert rs(np.array([40]), 3, "whole", 8, g) == rs(np.array([40]), 3, "per_rank", 8, g) == \
+            rs(np.array([40]), 3, "doubling", 8, g)
+    # two probed lists: the same cuts as doubling with the rank-1 cut taken away
+    assert rs(np.array([20, 30]), 3, "doubling", 8, 0) == [0, 8, 20, 50]
+    assert rs(np.array([20, 30]), 3, "whole", 8, 0) == [0, 8, 50]
+
+
 def test_round_bounds():
+    assert ivf.round_bounds(8, "whole") == [(0, 8)]
     assert ivf.round_bounds(8, "doubling") == [(0, 1), (1, 2), (2, 4), (4, 8)]
     assert ivf.round_bounds(6, "doubling") == [(0, 1), (1, 2), (2, 4), (4, 6)]
     assert ivf.round_bounds(3, "per_rank") == [(0, 1), (1, 2), (2, 3)]
