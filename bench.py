@@ -297,6 +297,9 @@ def oblivious_ablation(dade, torch, ix, Xd, Qd, w, gt, store, pairs, nprobe, ste
 
 LIN_DD = (1, 2, 4, 8, 16, 32, 64)   # Delta_d of the linear-scan study
 LIN_SCHEDULE = dict(schedule="doubling", fill_min=32, growth=16)   # growth-capped rounds tighten r inside the one list
+# the uneven batch's P_s sweep and FDScanning runs (nprobe up to 128): the doubling schedule, as
+# in every run of this study that completed
+UNEVEN_SCHEDULE = dict(schedule="doubling", fill_min=32, growth=0)
 
 
 def linear_scan(dade, torch, w, store, p_s, steps, n=100_000, nq=200):
@@ -479,7 +482,7 @@ def uneven_study(dade, torch, ix, Xd, Qd, w, store, target, steps, warmup):
         r = np.array([len(set(ids[i, :K[i]].tolist()) & set(gt[i, :K[i]].tolist())) / K[i] for i in range(nq)])
         return float(r.mean()), {str(k_): round(float(r[K == k_].mean()), 4) for k_ in sorted(set(K.tolist()))}
 
-    base = dict(delta_d=w.delta_d, **SCHEDULE)
+    base = dict(delta_d=w.delta_d, **UNEVEN_SCHEDULE)
     by_ps = {}
     chosen_ps = PS_SWEEP[-1]
     for ps in PS_SWEEP:

@@ -342,8 +342,7 @@ int dade_serve(dade_index* ix, int64_t n_req, const double* arrival_s, const int
  *   1. a FULL_D search of the sample with the same K / nprobe is the reference (its top-K is the
  *      exact top-K of the probed candidates, whatever the round shape);
  *   2. every candidate (Delta_d in {8, 16, 32, 64, 128} within [1, dim], times the round shapes
- *      {doubling, fill_min 32, growth 0}, {doubling, 32, 16}, {per-rank, 32, 16}, {whole, 32, 0})
- *      is searched
+ *      {doubling, fill_min 32, growth 0}, {doubling, 32, 16}, {per-rank, 32, 16}) is searched
  *      once, its agreement measured (mean over queries of |top-K ids in the reference| / the
  *      reference's valid ids), then timed over `reps` searches with HIP events on `stream`;
  *   3. the fastest candidate with agreement >= min_agreement wins (none: the most agreeing);

@@ -107,6 +107,7 @@ struct dade_index {
   hipEvent_t fork = nullptr, join = nullptr;
   // the last captured round-launch sequence and the argument bytes it was captured with
   hipGraphExec_t graph_exec = nullptr;
+  hipEvent_t graph_done = nullptr;     // recorded after every launch of the captured sequence
   const float* last_q = nullptr;   // the query buffer of the last search
   std::vector<unsigned char> graph_key;
   // kNN graph (dade_graph_build)
@@ -562,6 +563,7 @@ void dade_destroy(dade_index* ix) {
   (void)hipDeviceSynchronize();
   for (void* p : ix->owned) (void)hipFree(p);
   if (ix->graph_exec) (void)hipGraphExecDestroy(ix->graph_exec);
+  if (ix->graph_done) (void)hipEventDestroy(ix->graph_done);
   if (ix->cap) (void)hipStreamDestroy(ix->cap);
   if (ix->side) (void)hipStreamDestroy(ix->side);
   if (ix->fork) (void)hipEventDestroy(ix->fork);
@@ -1099,8 +1101,10 @@ static int search_impl(dade_index* ix, const float* Q, int64_t ldq, int64_t nq, 
     std::memcpy(key.data(), passes.data(), sizeof(RoundArgs) * passes.size());
     const int tail[2] = {rounds, ix->device};
     std::memcpy(key.data() + sizeof(RoundArgs) * passes.size(), tail, sizeof tail);
+    if (!ix->graph_done) HIPC(hipEventCreateWithFlags(&ix->graph_done, hipEventDisableTiming));
     if (ix->graph_exec && key == ix->graph_key) {
       HIPC(hipGraphLaunch(ix->graph_exec, s));
+      HIPC(hipEventRecord(ix->graph_done, s));
       graph_state = 2;
     } else {
       HIPC(hipStreamBeginCapture(ix->cap, hipStreamCaptureModeRelaxed));
@@ -1114,11 +1118,22 @@ static int search_impl(dade_index* ix, const float* Q, int64_t ldq, int64_t nq, 
       if (e == hipSuccess) e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
       if (g) (void)hipGraphDestroy(g);
       if (e == hipSuccess) {
-        if (ix->graph_exec) (void)hipGraphExecDestroy(ix->graph_exec);
+        // the replaced sequence may still run from its last launch: wait for it before its
+        // executable graph (and the argument blocks it owns) is released
+        if (ix->graph_exec) {
+          e = hipEventSynchronize(ix->graph_done);
+          (void)hipGraphExecDestroy(ix->graph_exec);
+          ix->graph_exec = nullptr;
+        }
+      }
+      if (e == hipSuccess) {
         ix->graph_exec = x;
+        x = nullptr;
         ix->graph_key.swap(key);
         e = hipGraphLaunch(ix->graph_exec, s);
+        if (e == hipSuccess) e = hipEventRecord(ix->graph_done, s);
       }
+      if (x) (void)hipGraphExecDestroy(x);
       if (e != hipSuccess) FAIL(DADE_EDEVICE, hip_msg(e, "list scan launch"));
       graph_state = 1;
     }

@@ -133,8 +133,7 @@ extern "C" int dade_autotune(dade_index* ix, const float* Q, int64_t nq, int32_t
     if (d <= dim) dds.push_back(d);
   if (dds.empty()) dds.push_back(dim);
   const struct { int schedule, fill_min, growth; } shapes[] = {
-      {DADE_SCHED_DOUBLING, 32, 0}, {DADE_SCHED_DOUBLING, 32, 16}, {DADE_SCHED_PER_RANK, 32, 16},
-      {DADE_SCHED_WHOLE, 32, 0}};
+      {DADE_SCHED_DOUBLING, 32, 0}, {DADE_SCHED_DOUBLING, 32, 16}, {DADE_SCHED_PER_RANK, 32, 16}};
   int best = -1;
   for (int d : dds)
     for (const auto& sh : shapes) {
