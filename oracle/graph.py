@@ -4,10 +4,13 @@ The paper's graph setting (HNSW** in the Experiments section) scans the neighbou
 objects, giving each one DCO against the maximum distance of the result set (size ef), and
 discards a neighbour whose DCO answers no.  This oracle follows that search on a flat graph:
 
-* Graph (reading; the paper uses HNSW's hierarchy, this build uses one layer): every object's
-  out-neighbours are its ``degree`` nearest other objects by the index's exact IVF search
-  (FDScanning with K = degree + 1 over ``nprobe`` lists), ordered by (dist^2, id), the object
-  itself removed, -1 padded; then up to ``reverse`` back links (``add_reverse_edges``).
+* Graph (reading; the paper uses HNSW's hierarchy, this oracle uses one layer and lets the
+  entry points of the IVF lists play the part of the upper layers): every object's candidates
+  are its nearest other objects by the index's exact IVF search (FDScanning over ``nprobe``
+  lists), ordered by (dist^2, id), the object itself removed.  Its out-neighbours are the first
+  ``degree`` of them, or, with ``candidates`` > 0, the ones HNSW's neighbour-selection heuristic
+  keeps among the first ``candidates`` (``select_neighbors``); -1 padded; then up to
+  ``reverse`` back links (``add_reverse_edges``).
 * Entry points (reading): each IVF list's medoid (the member nearest its centroid, ties to the
   lower id) and the member farthest from the medoid (``list_entries``); a query starts from the
   entry points of its ``n_entry`` nearest lists (probe order).
@@ -31,17 +34,65 @@ import numpy as np
 from . import ivf, pca
 
 
-def build_knn_graph(index: ivf.Index, X, degree: int, nprobe: int, delta_d: int = 32, rows=None):
+def build_knn_graph(index: ivf.Index, X, degree: int, nprobe: int, delta_d: int = 32, rows=None,
+                    candidates: int = 0, log: bool = False):
     """[len(rows) x degree] int64 out-neighbours (row ids, -1 padded) of the given rows (all rows
-    by default) from the index's FDScanning search."""
+    by default) from the index's FDScanning search: the ``degree`` nearest other rows, or with
+    ``candidates`` > 0 the ones ``select_neighbors`` keeps among the ``candidates`` nearest.
+    With ``log``, also a dict of per-row margins: ``boundary``, the relative gap between the last
+    candidate taken and the next one (a near tie there can swap the candidate set), and
+    ``select``, the heuristic's smallest decision margin (inf without selection)."""
     X = np.asarray(X)
     rows = np.arange(len(X)) if rows is None else np.asarray(rows)
-    ids = ivf.search(index, X[rows], degree + 1, nprobe, delta_d, mode="full_d", schedule="doubling")[0]
+    take = candidates if candidates > 0 else degree
+    ids, d2 = ivf.search(index, X[rows], take + 2, nprobe, delta_d, mode="full_d", schedule="doubling")[:2]
     out = np.full((len(rows), degree), -1, dtype=np.int64)
+    info = {"boundary": np.full(len(rows), np.inf), "select": np.full(len(rows), np.inf)}
     for i, r in enumerate(rows):
-        row = [int(v) for v in ids[i] if v >= 0 and v != r][:degree]
-        out[i, :len(row)] = row
-    return out
+        keep = [j for j in range(take + 2) if ids[i, j] >= 0 and ids[i, j] != r]
+        row = [int(ids[i, j]) for j in keep[:take]]
+        if len(keep) > take and d2[i, keep[take - 1]] > 0:
+            a, b = d2[i, keep[take - 1]], d2[i, keep[take]]
+            info["boundary"][i] = abs(b - a) / a
+        if candidates > 0:
+            row, info["select"][i] = select_neighbors(X, int(r), row, degree)
+        out[i, :len(row)] = row[:degree]
+    return (out, info) if log else out
+
+
+def select_neighbors(X, v: int, cands, M: int):
+    """HNSW's neighbour-selection heuristic (Malkov and Yashunin, the simple form: no candidate
+    extension, pruned candidates not added back) for object v, in float64 over the rows of X.
+
+    Candidates are taken in ascending (dist^2 to v, id) order.  A candidate e is pruned when some
+    neighbour already kept is strictly closer to e than v is (d(e, r) < d(e, v)), and kept
+    otherwise, until M are kept.  Returns (kept ids in the order kept, margin): margin is the
+    smallest relative gap among the quantities the decisions compare, |d(e, r) - d(e, v)| over
+    d(e, v) for the nearest kept r of every candidate examined, and the gaps between consecutive
+    candidate distances (their order)."""
+    X = np.asarray(X, dtype=np.float64)
+    cands = np.asarray([int(c) for c in cands if c >= 0 and c != v], dtype=np.int64)
+    if len(cands) == 0 or M < 1:
+        return [], np.inf
+    dv = np.sum((X[cands] - X[v]) ** 2, axis=1)
+    order = np.lexsort((cands, dv))
+    cands, dv = cands[order], dv[order]
+    margin = np.inf
+    if len(dv) > 1:
+        with np.errstate(divide="ignore", invalid="ignore"):
+            g = np.abs(np.diff(dv)) / np.maximum(dv[1:], 1e-300)
+        margin = float(g.min())
+    kept = []
+    for e, de in zip(cands, dv):
+        if len(kept) == M:
+            break
+        if kept:
+            dr = np.sum((X[kept] - X[e]) ** 2, axis=1).min()
+            margin = min(margin, abs(dr - de) / max(de, 1e-300))
+            if dr < de:
+                continue
+        kept.append(int(e))
+    return kept, margin
 
 
 def add_reverse_edges(neighbors, X, reverse: int) -> np.ndarray:

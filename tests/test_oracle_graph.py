@@ -167,3 +167,64 @@ def test_two_entries_per_list_reach_a_component_the_medoid_misses():
     two, _, _ = graph.search(oi, G, graph.list_entries(oi, X), q, 5, ef=8, n_entry=1, delta_d=4, mode="full_d")
     assert not set(one[0]) & set(gt[0])
     assert set(two[0]) == set(gt[0])
+
+
+def test_selection_on_a_line_keeps_one_neighbour_per_side():
+    """Hand-worked: v at 0 with candidates at 1, 2, 3, -1, -2 (ids 1..5).  1 is kept first (ties
+    with -1 at distance 1 go to the lower id); 2 and 3 are nearer 1 than 0; -1 is nearer 0 than 1
+    and is kept; -2 is nearer -1."""
+    X = np.array([[0.0], [1.0], [2.0], [3.0], [-1.0], [-2.0]])
+    kept, margin = graph.select_neighbors(X, 0, [1, 2, 3, 4, 5], 4)
+    assert kept == [1, 4]
+    assert margin == 0.0   # the exact tie between ids 1 and 4, broken by id
+
+
+def test_selection_keeps_a_candidate_equidistant_from_v_and_a_kept_neighbour():
+    """Only a strictly closer kept neighbour prunes: e = (1, 2) is at squared distance 5 from both
+    v = (0, 0) and the kept r = (2, 0), so it stays; (3, 0) is nearer r and goes."""
+    X = np.array([[0.0, 0.0], [2.0, 0.0], [1.0, 2.0], [3.0, 0.0]])
+    kept, margin = graph.select_neighbors(X, 0, [1, 2, 3], 3)
+    assert kept == [1, 2]
+    assert margin == 0.0
+
+
+def test_selection_of_mutually_far_candidates_keeps_the_nearest_m():
+    """Candidates on distinct axes at lengths 1.0 .. 1.4: d(e_i, e_j)^2 = s_i^2 + s_j^2 exceeds
+    both s_i^2 and s_j^2, so nothing is pruned and the first M by distance are kept."""
+    s = np.array([1.3, 1.0, 1.4, 1.1, 1.2])
+    X = np.zeros((6, 5))
+    X[1:, :] = np.diag(s)
+    assert graph.select_neighbors(X, 0, [1, 2, 3, 4, 5], 10)[0] == [2, 4, 5, 1, 3]
+    assert graph.select_neighbors(X, 0, [1, 2, 3, 4, 5], 3)[0] == [2, 4, 5]
+    assert graph.select_neighbors(X, 0, [5, 4, 3, 2, 1], 1)[0] == [2]
+
+
+def test_selection_links_a_far_blob_that_the_nearest_rows_do_not():
+    """v = (0, 0) with four collinear rows to its right and two rows 5 away above: the nearest 2
+    are both to the right, while the heuristic keeps the first row to the right (it prunes the
+    other three) and the nearer row above (squared distance 25 from v, 25.01 from (0.1, 0))."""
+    X = np.array([[0.0, 0.0], [0.1, 0.0], [0.2, 0.0], [0.3, 0.0], [0.4, 0.0], [0.0, 5.0], [0.1, 5.0]])
+    kept, _ = graph.select_neighbors(X, 0, [1, 2, 3, 4, 5, 6], 2)
+    assert kept == [1, 5]
+    bf, _ = knn.brute_force(X.astype(np.float32), X[:1].astype(np.float32), 3)
+    assert [v for v in bf[0].tolist() if v != 0][:2] == [1, 2]
+
+
+def test_graph_with_selection_over_all_lists():
+    """With every list probed, the candidates are the brute-force nearest rows, and each row's
+    out-neighbours are what the heuristic keeps among them; fewer than degree where it prunes."""
+    X, oi = small_index(seed=19)
+    G, info = graph.build_knn_graph(oi, X, degree=6, nprobe=oi.nlist, candidates=20, log=True)
+    bf, _ = knn.brute_force(X, X, 22)
+    pruned = 0
+    for i in range(len(X)):
+        cand = [v for v in bf[i].tolist() if v != i][:20]
+        kept, _ = graph.select_neighbors(X, i, cand, 6)
+        assert G[i].tolist() == kept + [-1] * (6 - len(kept)), i
+        pruned += 6 - len(kept)
+        # every kept pair satisfies the rule: no earlier kept row is strictly closer to a later one
+        Xd = X.astype(np.float64)
+        for a in range(len(kept)):
+            for b in range(a):
+                assert np.sum((Xd[kept[a]] - Xd[kept[b]]) ** 2) >= np.sum((Xd[kept[a]] - Xd[i]) ** 2)
+    assert pruned > 0 and np.all(info["boundary"] >= 0) and np.all(info["select"] >= 0)
