@@ -379,11 +379,18 @@ int dade_autotune(dade_index* ix, const float* Q, int64_t nq, int32_t k, int32_t
  * its result set (size ef), discarding a neighbour whose DCO answers no.  This engine runs that
  * search on a one-layer graph:
  *
- * dade_graph_build -- the graph of a ROTATED index: each row's `degree` out-neighbours are its
- * degree nearest other rows by this index's FDScanning search (K = degree + 1 over `nprobe`
- * lists, ties by id, the row itself dropped), followed by up to `reverse` back links: rows that
- * list it and that it does not list, nearest first by (squared distance in FP64 over the FP32
- * vectors, row id); rows are degree + reverse (<= 64) wide, -1 padded.  Each list has two entry
+ * dade_graph_build -- the graph of a ROTATED index.  With candidates = 0, each row's `degree`
+ * out-neighbours are its degree nearest other rows by this index's FDScanning search (K = degree
+ * + 1 over `nprobe` lists, ties by id, the row itself dropped).  With candidates in [degree, 127],
+ * the FDScanning search returns each row's `candidates` nearest other rows instead, and its
+ * out-neighbours are those that HNSW's neighbour-selection heuristic keeps (Malkov and Yashunin,
+ * the simple form): candidates taken in ascending (squared distance in FP64 over the FP32
+ * vectors, row id) order, one pruned when a neighbour kept before it is strictly closer to it
+ * than the row is, at most `degree` kept (fewer when it prunes; -1 padded).  This selection runs
+ * on the host over all rows (threads).  The out-neighbours are followed by up to `reverse` back
+ * links: rows that list it and that it does not list, nearest first by (squared distance in FP64
+ * over the FP32 vectors, row id); rows are degree + reverse (<= 64) wide, -1 padded.  The entry
+ * points of the IVF lists stand in for HNSW's upper layers.  Each list has two entry
  * points: its medoid (the member nearest its centroid in FP32, ties to the lower id) and the
  * member farthest from the medoid (ties to the lower id; -1 for a list of one).  The queries of
  * the FDScanning search are the index's own copy of the vectors it was built from, so row i is
@@ -408,7 +415,8 @@ int dade_autotune(dade_index* ix, const float* Q, int64_t nq, int32_t k, int32_t
  * neighbors [n x width] (row i's neighbours), entries [nlist x 2] (-1 where a list has no
  * such member); NULL arrays are skipped.
  */
-int dade_graph_build(dade_index* ix, int32_t degree, int32_t reverse, int32_t nprobe, void* stream);
+int dade_graph_build(dade_index* ix, int32_t degree, int32_t reverse, int32_t nprobe, int32_t candidates,
+                     void* stream);
 int dade_graph_search(dade_index* ix, const float* Q, int64_t nq, int32_t k, int32_t ef, int32_t n_entry,
                       int32_t max_iters, const dade_search_opts* opts, int64_t* out_ids, float* out_dist2,
                       void* stream);

@@ -11,6 +11,7 @@
 #include <mutex>
 #include <numeric>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "dade.h"
@@ -1255,11 +1256,65 @@ int dade_stage_times(dade_index* ix, dade_times* out) {
   return DADE_OK;
 }
 
-int dade_graph_build(dade_index* ix, int32_t degree, int32_t reverse, int32_t nprobe, void* stream) {
+namespace {
+
+// Squared distance between rows a and b of the host copy (FP64 over the FP32 coordinates, in
+// coordinate order).
+double host_d2(const float* xh, int dp, int dim, int64_t a, int64_t b) {
+  const float* x = xh + size_t(a) * dp;
+  const float* y = xh + size_t(b) * dp;
+  double s = 0.0;
+  for (int c = 0; c < dim; ++c) {
+    const double t = double(x[c]) - double(y[c]);
+    s += t * t;
+  }
+  return s;
+}
+
+// True when the squared distance between rows a and b is below `bound`.  The partial sums only
+// grow, so the sum can stop once it reaches the bound without changing the answer.
+bool host_d2_below(const float* xh, int dp, int dim, int64_t a, int64_t b, double bound) {
+  const float* x = xh + size_t(a) * dp;
+  const float* y = xh + size_t(b) * dp;
+  double s = 0.0;
+  for (int c = 0; c < dim; ++c) {
+    const double t = double(x[c]) - double(y[c]);
+    s += t * t;
+    if (s >= bound) return false;
+  }
+  return s < bound;
+}
+
+// HNSW's neighbour selection (Malkov and Yashunin, the simple form of their heuristic: no
+// candidate extension, pruned candidates not added back) for row r: its candidates in ascending
+// (squared distance, row id) order; a candidate is pruned when a neighbour kept before it is
+// strictly closer to it than r is, and kept otherwise, until `degree` are kept.
+void select_neighbours(const float* xh, int dp, int dim, int64_t r, const int64_t* cand, int nc, int degree,
+                       std::vector<std::pair<double, int64_t>>& order, std::vector<int64_t>& kept) {
+  order.clear();
+  for (int i = 0; i < nc; ++i)
+    if (cand[i] >= 0) order.emplace_back(host_d2(xh, dp, dim, r, cand[i]), cand[i]);
+  std::sort(order.begin(), order.end());
+  kept.clear();
+  for (const auto& c : order) {
+    if (int(kept.size()) == degree) break;
+    bool keep = true;
+    for (int64_t k : kept)
+      if (host_d2_below(xh, dp, dim, c.second, k, c.first)) { keep = false; break; }
+    if (keep) kept.push_back(c.second);
+  }
+}
+
+}  // namespace
+
+int dade_graph_build(dade_index* ix, int32_t degree, int32_t reverse, int32_t nprobe, int32_t candidates,
+                     void* stream) {
   if (!ix) FAIL(DADE_EINVAL, "index is NULL");
   if (degree < 1 || reverse < 0 || degree + reverse > kGraphMax)
     FAIL(DADE_EINVAL, "degree >= 1, reverse >= 0 and degree + reverse <= 64 are required");
   if (nprobe < 1) FAIL(DADE_EINVAL, "nprobe must be >= 1");
+  if (candidates != 0 && (candidates < degree || candidates + 1 > kMaxK))
+    FAIL(DADE_EINVAL, "candidates must be 0 or in [degree, 127]");
   if (ix->state < DADE_STATE_ROTATED) FAIL(DADE_ESTATE, "the graph needs a rotated index");
   if (ix->n > kGraphBuildMaxRows)
     FAIL(DADE_EINVAL, "graph build: indexes of more than " + std::to_string(kGraphBuildMaxRows) +
@@ -1268,6 +1323,8 @@ int dade_graph_build(dade_index* ix, int32_t degree, int32_t reverse, int32_t np
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int64_t n = ix->n;
   const int width = degree + reverse;
+  const bool select = candidates > 0;
+  const int kk = (select ? candidates : degree) + 1;   // FDScanning results per row (the row itself among them)
   ix->graph_degree = 0;   // not usable until complete
   if (ix->d_nbr && ix->graph_width != width) {
     HIPC(hipStreamSynchronize(s));
@@ -1282,9 +1339,9 @@ int dade_graph_build(dade_index* ix, int32_t degree, int32_t reverse, int32_t np
   const int64_t chunk = std::min<int64_t>(n, 65536);
   int64_t* res = nullptr;
   float* rd = nullptr;
-  if ((rc = alloc_t(ix, &res, size_t(chunk) * (degree + 1)))) return rc;
-  if ((rc = alloc_t(ix, &rd, size_t(chunk) * (degree + 1)))) {
-    dev_free(ix, res, sizeof(int64_t) * size_t(chunk) * (degree + 1));
+  if ((rc = alloc_t(ix, &res, size_t(chunk) * kk))) return rc;
+  if ((rc = alloc_t(ix, &rd, size_t(chunk) * kk))) {
+    dev_free(ix, res, sizeof(int64_t) * size_t(chunk) * kk);
     return rc;
   }
   dade_search_opts o{};
@@ -1293,14 +1350,31 @@ int dade_graph_build(dade_index* ix, int32_t degree, int32_t reverse, int32_t np
   o.rerank_delta = -1.f;
   o.fill_min = 32;
   o.growth = 0;
-  // every row's degree + 1 nearest by FDScanning over nprobe lists, then itself dropped
+  // with selection: every row's `candidates` nearest other rows (row ids, -1 padded), by row id
+  std::vector<int64_t> cand;
+  if (select) cand.assign(size_t(n) * candidates, -1);
+  std::vector<int64_t> res_h;
+  // every row's kk nearest by FDScanning over nprobe lists, then itself dropped
   for (int64_t c0 = 0; c0 < n && rc == DADE_OK; c0 += chunk) {
     const int64_t cn = std::min(chunk, n - c0);
     // the queries are the index's own rows (zero-padded to dp), row id c0 + i at row c0 + i
-    rc = search_impl(ix, ix->X + c0 * ix->dp, ix->dp, cn, degree + 1, nprobe, nullptr, nullptr, &o, res, rd, stream);
-    if (rc == DADE_OK) {
+    rc = search_impl(ix, ix->X + c0 * ix->dp, ix->dp, cn, kk, nprobe, nullptr, nullptr, &o, res, rd, stream);
+    if (rc != DADE_OK) break;
+    if (!select) {
       const hipError_t e = launch_graph_collect(res, int(cn), c0, degree, width, ix->d_pos, ix->d_nbr, s);
       if (e != hipSuccess) { dade::set_error(hip_msg(e, "graph collect")); rc = DADE_EDEVICE; }
+      continue;
+    }
+    res_h.resize(size_t(cn) * kk);
+    hipError_t e = hipMemcpyAsync(res_h.data(), res, sizeof(int64_t) * res_h.size(), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) { dade::set_error(hip_msg(e, "graph candidates")); rc = DADE_EDEVICE; break; }
+    for (int64_t i = 0; i < cn; ++i) {
+      int w = 0;
+      for (int j = 0; j < kk && w < candidates; ++j) {
+        const int64_t id = res_h[size_t(i) * kk + j];
+        if (id >= 0 && id != c0 + i) cand[size_t(c0 + i) * candidates + w++] = id;
+      }
     }
   }
   if (rc == DADE_OK) {
@@ -1309,48 +1383,71 @@ int dade_graph_build(dade_index* ix, int32_t degree, int32_t reverse, int32_t np
     if (e != hipSuccess) { dade::set_error(hip_msg(e, "graph entry points")); rc = DADE_EDEVICE; }
   }
   const hipError_t e = hipStreamSynchronize(s);
-  dev_free(ix, res, sizeof(int64_t) * size_t(chunk) * (degree + 1));
-  dev_free(ix, rd, sizeof(float) * size_t(chunk) * (degree + 1));
+  dev_free(ix, res, sizeof(int64_t) * size_t(chunk) * kk);
+  dev_free(ix, rd, sizeof(float) * size_t(chunk) * kk);
   if (rc) return rc;
   if (e != hipSuccess) FAIL(DADE_EDEVICE, hip_msg(e, "graph build"));
+  if (!select && reverse == 0) {
+    ix->graph_degree = width;
+    return DADE_OK;
+  }
+  const int dp = ix->dp;
+  std::vector<int32_t> nb(size_t(n) * width, -1);   // by position, neighbour positions
+  std::vector<float> xh(size_t(n) * dp);             // FP32 rows by row id
+  HIPC(hipMemcpy(xh.data(), ix->X, sizeof(float) * xh.size(), hipMemcpyDeviceToHost));
+  if (select) {
+    // rows are independent: split them over host threads, each writing only its own rows
+    const int nt = int(std::max<int64_t>(1, std::min<int64_t>(
+        std::min<unsigned>(16u, std::max(1u, std::thread::hardware_concurrency())), n / 256 + 1)));
+    auto work = [&](int t) {
+      std::vector<std::pair<double, int64_t>> order;
+      std::vector<int64_t> kept;
+      for (int64_t r = t; r < n; r += nt) {
+        select_neighbours(xh.data(), dp, ix->dim, r, cand.data() + size_t(r) * candidates, candidates, degree,
+                          order, kept);
+        int32_t* row = nb.data() + size_t(ix->d_pos_h(r)) * width;
+        for (size_t j = 0; j < kept.size(); ++j) row[j] = int32_t(ix->d_pos_h(kept[j]));
+      }
+    };
+    std::vector<std::thread> pool;
+    int started = 0;
+    try {
+      for (; started < nt; ++started) pool.emplace_back(work, started);
+    } catch (...) {
+    }
+    for (int t = started; t < nt; ++t) work(t);   // shares no thread could take run here
+    for (auto& th : pool) th.join();
+  } else {
+    HIPC(hipMemcpy(nb.data(), ix->d_nbr, sizeof(int32_t) * nb.size(), hipMemcpyDeviceToHost));
+  }
   if (reverse > 0) {
     // back links: for each row, the rows listing it that it does not list, nearest first by
     // (squared distance in FP64 over the FP32 vectors, row id), at most `reverse` of them
-    const int dp = ix->dp;
-    std::vector<int32_t> nb(size_t(n) * width);
-    std::vector<float> xh(size_t(n) * dp);
-    HIPC(hipMemcpy(nb.data(), ix->d_nbr, sizeof(int32_t) * nb.size(), hipMemcpyDeviceToHost));
-    HIPC(hipMemcpy(xh.data(), ix->X, sizeof(float) * xh.size(), hipMemcpyDeviceToHost));
     std::vector<std::vector<int32_t>> incoming(static_cast<size_t>(n));
     for (int64_t p = 0; p < n; ++p)
       for (int j = 0; j < degree; ++j) {
         const int32_t u = nb[size_t(p) * width + j];
         if (u >= 0) incoming[size_t(u)].push_back(int32_t(p));
       }
-    std::vector<std::pair<double, int64_t>> cand;   // (distance, row id)
+    std::vector<std::pair<double, int64_t>> back;   // (distance, row id)
     for (int64_t v = 0; v < n; ++v) {
       int32_t* row = nb.data() + size_t(v) * width;
       const int64_t rv = ix->ids_h[size_t(v)];
-      cand.clear();
+      back.clear();
       for (int32_t u : incoming[size_t(v)]) {
         if (std::find(row, row + degree, u) != row + degree) continue;
         const int64_t ru = ix->ids_h[size_t(u)];
-        double d2 = 0.0;
-        for (int c = 0; c < ix->dim; ++c) {
-          const double t = double(xh[size_t(ru) * dp + c]) - double(xh[size_t(rv) * dp + c]);
-          d2 += t * t;
-        }
-        cand.emplace_back(d2, ru);
+        back.emplace_back(host_d2(xh.data(), dp, ix->dim, ru, rv), ru);
       }
-      std::sort(cand.begin(), cand.end());
-      cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
+      std::sort(back.begin(), back.end());
+      back.erase(std::unique(back.begin(), back.end()), back.end());
       int w = 0;
       while (w < degree && row[w] >= 0) ++w;
-      for (size_t i = 0; i < cand.size() && i < size_t(reverse); ++i) row[w++] = int32_t(ix->d_pos_h(cand[i].second));
+      for (size_t i = 0; i < back.size() && i < size_t(reverse); ++i) row[w++] = int32_t(ix->d_pos_h(back[i].second));
       for (; w < width; ++w) row[w] = -1;
     }
-    HIPC(hipMemcpy(ix->d_nbr, nb.data(), sizeof(int32_t) * nb.size(), hipMemcpyHostToDevice));
   }
+  HIPC(hipMemcpy(ix->d_nbr, nb.data(), sizeof(int32_t) * nb.size(), hipMemcpyHostToDevice));
   ix->graph_degree = width;
   return DADE_OK;
 }

@@ -115,7 +115,7 @@ def lib():
         L.dade_stage_times.argtypes = [vp, ctypes.POINTER(Times)]
         L.dade_serve.argtypes = [vp, i64, vp, vp, vp, vp, vp, ctypes.POINTER(ServeOpts), vp, vp, vp,
                                  ctypes.POINTER(ServeStats), vp]
-        L.dade_graph_build.argtypes = [vp, i32, i32, i32, vp]
+        L.dade_graph_build.argtypes = [vp, i32, i32, i32, i32, vp]
         L.dade_graph_search.argtypes = [vp, vp, i64, i32, i32, i32, i32, ctypes.POINTER(SearchOpts), vp, vp, vp]
         L.dade_graph_export.argtypes = [vp, ctypes.POINTER(i32), vp, vp]
         L.dade_autotune.argtypes = [vp, vp, i64, i32, i32, vp, vp, ctypes.c_float, i32, ctypes.POINTER(SearchOpts),
@@ -363,8 +363,8 @@ def dade_autotune(ix: Index, Q, k, nprobe, k_per_query=None, nprobe_per_query=No
     return chosen, table
 
 
-def dade_graph_build(ix: Index, degree=16, reverse=8, nprobe=4, stream=None):
-    _check(lib().dade_graph_build(ix.handle, degree, reverse, nprobe, _stream(stream)))
+def dade_graph_build(ix: Index, degree=16, reverse=8, nprobe=4, candidates=0, stream=None):
+    _check(lib().dade_graph_build(ix.handle, degree, reverse, nprobe, candidates, _stream(stream)))
 
 
 def dade_graph_search(ix: Index, Q, k, ef, n_entry=4, max_iters=0, delta_d=32, mode="dade", stats=None,

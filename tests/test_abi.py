@@ -68,7 +68,7 @@ def test_new_entry_points_reject_null_handles_before_touching_a_device():
         pytest.skip("libdade.so not built")
     L = dade.lib()
     assert L.dade_autotune(None, None, 1, 10, 8, None, None, 0.5, 1, None, None, None, None) == dade.DADE_EINVAL
-    assert L.dade_graph_build(None, 16, 8, 4, None) == dade.DADE_EINVAL
+    assert L.dade_graph_build(None, 16, 8, 4, 0, None) == dade.DADE_EINVAL
     assert L.dade_graph_search(None, None, 1, 10, 32, 4, 0, None, None, None, None) == dade.DADE_EINVAL
     assert L.dade_graph_export(None, None, None, None) == dade.DADE_EINVAL
     assert "NULL" in dade.dade_last_error()

@@ -67,6 +67,53 @@ def test_graph_build_matches_oracle(f32):
         np.testing.assert_allclose(dg, dw, rtol=1e-12, err_msg=f"row {r}")
 
 
+SEL_DEG, SEL_REV, SEL_CAND = 16, 16, 48
+
+
+@pytest.fixture(scope="module")
+def f32_sel():
+    """The 20k x 128 index with HNSW neighbour selection over 48 candidates: its forward lists
+    (a build with no back links) and its full rows (16 + 16 wide)."""
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    env = _setup(None)
+    dade.dade_graph_build(env["gi"], degree=SEL_DEG, reverse=0, nprobe=NPROBE_BUILD, candidates=SEL_CAND)
+    fwd, _ = dade.dade_graph_export(env["gi"])
+    dade.dade_graph_build(env["gi"], degree=SEL_DEG, reverse=SEL_REV, nprobe=NPROBE_BUILD, candidates=SEL_CAND)
+    env["nb"], env["en"] = dade.dade_graph_export(env["gi"])
+    env["fwd"] = fwd
+    return env
+
+
+def test_graph_build_with_selection_matches_oracle(f32_sel):
+    """Sampled rows: the out-neighbours are what the oracle's heuristic keeps among the oracle's
+    FDScanning candidates, id for id and in order, wherever neither the candidate boundary nor a
+    decision is a near tie; the full rows are the forward lists followed by the oracle's back
+    links over the library's forward lists."""
+    X, oi, fwd, nb = f32_sel["X"], f32_sel["oi"], f32_sel["fwd"], f32_sel["nb"]
+    assert fwd.shape == (len(X), SEL_DEG) and nb.shape == (len(X), SEL_DEG + SEL_REV)
+    rows = np.sort(np.random.default_rng(1).choice(len(X), 300, replace=False))
+    o_nb, info = graph.build_knn_graph(oi, X, SEL_DEG, NPROBE_BUILD, rows=rows, candidates=SEL_CAND, log=True)
+    clear = (info["boundary"] > 1e-4) & (info["select"] > 1e-9)
+    assert clear.mean() > 0.9
+    for i, r in enumerate(rows):
+        got = [int(u) for u in fwd[r] if u >= 0]
+        assert r not in got and len(set(got)) == len(got)
+        assert all(u < 0 for u in fwd[r, len(got):]), r   # kept ones first, then padding
+        if clear[i]:
+            assert got == [int(u) for u in o_nb[i] if u >= 0], f"row {r}"
+    pruned = (fwd < 0).sum()
+    assert pruned > 0   # the heuristic does prune on this workload
+    H = graph.add_reverse_edges(fwd, X, SEL_REV)
+    np.testing.assert_array_equal(nb[rows], H[rows])
+
+
+@pytest.mark.parametrize("mode", ["dade", "full_d"])
+def test_graph_search_with_selection_matches_oracle(f32_sel, mode):
+    st, _ = run_parity(f32_sel, mode)
+    assert st[:, 2].max() <= 2 * 48
+
+
 def test_entry_points_are_medoid_and_farthest_member(f32):
     X, oi, en = f32["X"], f32["oi"], f32["en"]
     assert en.shape == (oi.nlist, 2)
