@@ -15,18 +15,24 @@ __device__ inline float f16_to_f(uint32_t h) {
   return __half2float(__ushort_as_half(static_cast<unsigned short>(h)));
 }
 
-// Coordinates [c, c + 8) of stored row p (c a multiple of 8; the head block holds [0, 32)).
+// Address of coordinates [c, c + 8) of stored row p (c a multiple of 8; the head block holds
+// [0, 32)): 16 bytes for a 16-bit store, 32 for FP32.
 template <int DT>
-__device__ inline void load8(const GraphArgs& a, int64_t p, int c, float v[8]) {
+__device__ inline const uint4* chunk_ptr(const GraphArgs& a, int64_t p, int c) {
   const int64_t off = c < kHead ? p * kHead + c : p * (a.dp - kHead) + (c - kHead);
+  return reinterpret_cast<const uint4*>(static_cast<const char*>(c < kHead ? a.head : a.tail) +
+                                        off * (DT == 0 ? 4 : 2));
+}
+
+// The 8 coordinates of a chunk loaded as raw words (lo; hi holds coordinates 4..7 for FP32).
+template <int DT>
+__device__ inline void unpack8(const uint4& lo, const uint4& hi, float v[8]) {
   if (DT == 0) {
-    const float* base = static_cast<const float*>(c < kHead ? a.head : a.tail) + off;
-    const float4 x = *reinterpret_cast<const float4*>(base), y = *reinterpret_cast<const float4*>(base + 4);
-    v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w; v[4] = y.x; v[5] = y.y; v[6] = y.z; v[7] = y.w;
+    v[0] = __uint_as_float(lo.x); v[1] = __uint_as_float(lo.y); v[2] = __uint_as_float(lo.z);
+    v[3] = __uint_as_float(lo.w); v[4] = __uint_as_float(hi.x); v[5] = __uint_as_float(hi.y);
+    v[6] = __uint_as_float(hi.z); v[7] = __uint_as_float(hi.w);
   } else {
-    const uint16_t* base = static_cast<const uint16_t*>(c < kHead ? a.head : a.tail) + off;
-    const uint4 u = *reinterpret_cast<const uint4*>(base);
-    const uint32_t w[4] = {u.x, u.y, u.z, u.w};
+    const uint32_t w[4] = {lo.x, lo.y, lo.z, lo.w};
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       v[2 * i] = DT == 1 ? bf16_to_f(w[i] & 0xffffu) : f16_to_f(w[i] & 0xffffu);
@@ -36,30 +42,76 @@ __device__ inline void load8(const GraphArgs& a, int64_t p, int c, float v[8]) {
 }
 
 // One DCO of stored row p against r2: S over growing prefixes, rejected at the first tested d
-// (a multiple of delta_d below dim) where S_d > T_d r2.  TEST false: FDScanning.
+// (a multiple of delta_d below dim) where S_d > T_d r2.  TEST false: FDScanning.  The row is
+// read kBatch chunks of 8 coordinates at a time, all row loads of a batch issued before the
+// first chunk is used (a chunk past dim loads the last chunk again and is not used), so a batch
+// costs one memory trip.  With tests, the chunks are then taken in order, each test as soon as
+// its prefix is summed, so a rejected DCO stops reading query chunks and thresholds at its exit.
+// Without tests, the batch's query chunks are read and summed with no branch between them.  The
+// sum takes the coordinates in order, so S, the exit and the dimensions counted are those of a
+// chunk-by-chunk loop.
 template <int DT, bool TEST>
 __device__ inline void dco(const GraphArgs& a, int64_t p, const float* qr, float r2, float& S, bool& rej,
                            int& dexit) {
-  S = 0.f;
+  constexpr int kBatch = DT == 0 ? 8 : 16;
+  float s = 0.f;
   rej = false;
   dexit = a.dim;
-  for (int c = 0; c < a.dim; c += 8) {
-    float v[8];
-    load8<DT>(a, p, c, v);
-    const float4 q0 = *reinterpret_cast<const float4*>(qr + c), q1 = *reinterpret_cast<const float4*>(qr + c + 4);
-    const float qv[8] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
+  const int last = (a.dim - 1) / 8 * 8;   // first coordinate of the last chunk
+  for (int c0 = 0; c0 < a.dim; c0 += 8 * kBatch) {
+    uint4 lo[kBatch], hi[kBatch];
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const float t = qv[i] - v[i];
-      S = fmaf(t, t, S);
+    for (int b = 0; b < kBatch; ++b) {
+      const uint4* src = chunk_ptr<DT>(a, p, min(c0 + 8 * b, last));
+      lo[b] = src[0];
+      if (DT == 0) hi[b] = src[1];
     }
-    const int e = c + 8;
-    if (TEST && e < a.dim && e % a.delta_d == 0 && S > a.T[e - 1] * r2) {
-      rej = true;
-      dexit = e;
-      return;
+    if constexpr (TEST) {
+#pragma unroll
+      for (int b = 0; b < kBatch; ++b) {
+        const int c = c0 + 8 * b;
+        if (c >= a.dim) break;
+        float v[8];
+        unpack8<DT>(lo[b], hi[b], v);
+        const float4 q0 = *reinterpret_cast<const float4*>(qr + c), q1 = *reinterpret_cast<const float4*>(qr + c + 4);
+        const float qv[8] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          const float t = qv[i] - v[i];
+          s = fmaf(t, t, s);
+        }
+        const int e = c + 8;
+        if (e < a.dim && e % a.delta_d == 0 && s > a.T[e - 1] * r2) {
+          S = s;
+          rej = true;
+          dexit = e;
+          return;
+        }
+      }
+    } else {
+      float pre[kBatch];
+#pragma unroll
+      for (int b = 0; b < kBatch; ++b) {
+        const int c = min(c0 + 8 * b, last);
+        float v[8];
+        unpack8<DT>(lo[b], hi[b], v);
+        const float4 q0 = *reinterpret_cast<const float4*>(qr + c), q1 = *reinterpret_cast<const float4*>(qr + c + 4);
+        const float qv[8] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          const float t = qv[i] - v[i];
+          s = fmaf(t, t, s);
+        }
+        pre[b] = s;
+      }
+      // the sum through the batch's last chunk below dim
+      const int n_in = min(kBatch, (a.dim - c0 + 7) / 8);
+#pragma unroll
+      for (int b = 0; b < kBatch; ++b)
+        if (b == n_in - 1) s = pre[b];
     }
   }
+  S = s;
 }
 
 // Inserts position u into the visited table; true if it was not there.  The table always has a
@@ -165,6 +217,7 @@ __global__ __launch_bounds__(64) void graph_search_kernel(GraphArgs a) {
       const int u = a.nbr[int64_t(cp) * deg + lane];
       if (u >= 0 && visit(tab, mask, u)) {
         ++n_vis;
+        const uint32_t rid = uint32_t(a.ids[u]);   // read beside the DCO's loads, not after them
         float S;
         bool rej;
         int dx;
@@ -175,7 +228,7 @@ __global__ __launch_bounds__(64) void graph_search_kernel(GraphArgs a) {
         ++n_dco;
         n_dims += dx;
         if (!rej) {
-          const unsigned long long k = make_key(S, uint32_t(a.ids[u]));
+          const unsigned long long k = make_key(S, rid);
           if (!full || k < worst) {
             nk = k;
             np = u;

@@ -157,8 +157,9 @@ def test_graph_search_matches_oracle_f32(f32, mode):
         assert st[:, 1].sum() < st[:, 0].sum() * f32["w"].dim
 
 
-@pytest.mark.parametrize("ef,n_entry,max_iters,dd", [(10, 1, 0, 8), (64, 8, 40, 16), (32, 2, 0, 64)])
+@pytest.mark.parametrize("ef,n_entry,max_iters,dd", [(10, 1, 0, 8), (64, 8, 40, 16), (32, 2, 0, 64), (8, 8, 0, 16)])
 def test_graph_search_parameters(f32, ef, n_entry, max_iters, dd):
+    """Includes 2 n_entry > ef: the seed merge keeps only the ef nearest of 16 seeds."""
     run_parity(f32, "dade", K=min(10, ef), ef=ef, n_entry=n_entry, max_iters=max_iters, dd=dd)
 
 
