@@ -13,7 +13,7 @@ import itertools
 
 import numpy as np
 
-from oracle import graph, ivf, lowp
+from oracle import estimator, graph, ivf, lowp
 from paper_2411_17229_amd import dade, workloads
 
 # FP32 distances vs the FP64 oracle, and the relative margin of a decision that FP32 rounding may
@@ -136,3 +136,26 @@ def gpu_search(gi, Qd, K, nprobe, **kw):
     torch.cuda.synchronize()
     dade.dade_check(gi)
     return to_np(ids), to_np(d2)
+
+
+def integer_index(store, delta):
+    """An index on which every FP32 operation of the search is exact: integer coordinates in
+    [0, 3] (duplicate rows included), W = I, mu = 0, integer centroids (some rows), lists by
+    nearest centroid (ties to the lower list id), and thresholds T_d = (128 d + 1) / 4096, whose
+    products with the integer r^2 (< 4096) are exact in FP32 and never equal an integer S_d."""
+    rng = np.random.default_rng(77)
+    D, n, nlist = 32, 3000, 16
+    X = rng.integers(0, 4, (n, D)).astype(np.float32)
+    X[2500:2800] = X[rng.integers(0, 2500, 300)]            # duplicate rows
+    Q = rng.integers(0, 4, (60, D)).astype(np.float32)
+    Q[:15] = X[rng.integers(0, n, 15)]                      # queries at distance 0 from some rows
+    C = X[rng.choice(2500, nlist, replace=False)].astype(np.float64)
+    lab = ivf.assign(X, C)
+    off, ids = ivf.build_lists(lab, nlist)
+    lam = np.arange(D, 0, -1, dtype=np.float64)
+    T = np.array([(128 * d + 1) / 4096 for d in range(1, D)] + [1.0])
+    eps = np.sqrt(T * estimator.scale(lam)) - 1.0
+    Y = X.astype(np.float64)
+    oi = ivf.Index(np.zeros(D), np.eye(D), lam, eps, C, off, ids, Y, T=T,
+                   Y_exact=None if store == "f32" else Y, delta=0.0 if store == "f32" else delta)
+    return X, Q, oi

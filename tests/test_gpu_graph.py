@@ -7,7 +7,7 @@ import pytest
 
 from oracle import graph, ivf
 from paper_2411_17229_amd import dade, workloads
-from gpu_helpers import EXCUSE_TOL, artifacts, compare, oracle_graph, oracle_index, to_np
+from gpu_helpers import EXCUSE_TOL, artifacts, compare, integer_index, oracle_graph, oracle_index, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -112,6 +112,42 @@ def test_graph_build_with_selection_matches_oracle(f32_sel):
 def test_graph_search_with_selection_matches_oracle(f32_sel, mode):
     st, _ = run_parity(f32_sel, mode)
     assert st[:, 2].max() <= 2 * 48
+
+
+@pytest.mark.parametrize("store", ["f32", "bf16"])
+def test_graph_exact_integer_inputs_match_exactly(store):
+    """Where FP32 is exact (integer coordinates, W = I, dyadic thresholds, duplicate rows: every
+    distance and threshold product is exact, every tie is broken by id), nothing is excused: the
+    selected graph's forward lists equal the oracle's, and every query's ids, distances (bit for
+    bit), DCOs, dimensions read, expansions and visits equal the oracle's beam on the library's
+    graph, in DADE and FDScanning modes."""
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    X, Q, oi = integer_index(store, 2.0 ** -10)
+    gi = dade.dade_import(artifacts(oi), torch.from_numpy(X).cuda(), store=store)
+    Qd = torch.from_numpy(Q).cuda()
+    deg, rev, cand = 8, 4, 24
+    dade.dade_graph_build(gi, degree=deg, reverse=0, nprobe=oi.nlist, candidates=cand)
+    fwd, _ = dade.dade_graph_export(gi)
+    rows = np.arange(0, len(X), 10)
+    o_fwd = graph.build_knn_graph(oi, X, deg, oi.nlist, rows=rows, candidates=cand)
+    np.testing.assert_array_equal(fwd[rows], o_fwd)
+    dade.dade_graph_build(gi, degree=deg, reverse=rev, nprobe=oi.nlist, candidates=cand)
+    nb, en = dade.dade_graph_export(gi)
+    np.testing.assert_array_equal(nb, graph.add_reverse_edges(fwd, X, rev))
+    np.testing.assert_array_equal(en, graph.list_entries(oi, X))
+    for mode in ("dade", "full_d"):
+        for K, ef, n_entry in ((5, 16, 2), (10, 32, 1), (1, 8, 4)):
+            stats = torch.zeros((len(Q), 4), dtype=torch.int64, device="cuda")
+            ids, d2 = dade.dade_graph_search(gi, Qd, K, ef, n_entry=n_entry, delta_d=8, mode=mode, stats=stats)
+            torch.cuda.synchronize()
+            o_ids, o_d2, logs = graph.search(oi, nb, en, Q, K, ef, n_entry, 8, mode=mode, log=True)
+            assert np.array_equal(to_np(ids), o_ids), (mode, K, ef, n_entry)
+            assert np.array_equal(to_np(d2).astype(np.float64), o_d2), (mode, K, ef, n_entry)
+            st = to_np(stats)
+            for j, key in enumerate(("dcos", "dims", "expansions", "visited")):
+                np.testing.assert_array_equal(st[:, j], logs[key].astype(np.int64), err_msg=f"{mode} {key}")
+    gi.close()
 
 
 def test_entry_points_are_medoid_and_farthest_member(f32):

@@ -5,7 +5,8 @@ import numpy as np
 import pytest
 from scipy.spatial.distance import cdist
 
-from gpu_helpers import artifacts, compare, oracle_ivf, exact_d2, gpu_search, oracle_index, to_np
+from gpu_helpers import (artifacts, compare, oracle_ivf, exact_d2, gpu_search, integer_index, oracle_index,
+                         to_np)
 from oracle import estimator, ivf, knn, pca
 from paper_2411_17229_amd import dade, workloads
 
@@ -124,29 +125,6 @@ def test_probe_selection_beyond_64_probes(small, nprobe):
     gi.close()
 
 
-def _integer_index(store, delta):
-    """An index on which every FP32 operation of the search is exact: integer coordinates in
-    [0, 3] (duplicate rows included), W = I, mu = 0, integer centroids (some rows), lists by
-    nearest centroid (ties to the lower list id), and thresholds T_d = (128 d + 1) / 4096, whose
-    products with the integer r^2 (< 4096) are exact in FP32 and never equal an integer S_d."""
-    rng = np.random.default_rng(77)
-    D, n, nlist = 32, 3000, 16
-    X = rng.integers(0, 4, (n, D)).astype(np.float32)
-    X[2500:2800] = X[rng.integers(0, 2500, 300)]            # duplicate rows
-    Q = rng.integers(0, 4, (60, D)).astype(np.float32)
-    Q[:15] = X[rng.integers(0, n, 15)]                      # queries at distance 0 from some rows
-    C = X[rng.choice(2500, nlist, replace=False)].astype(np.float64)
-    lab = ivf.assign(X, C)
-    off, ids = ivf.build_lists(lab, nlist)
-    lam = np.arange(D, 0, -1, dtype=np.float64)
-    T = np.array([(128 * d + 1) / 4096 for d in range(1, D)] + [1.0])
-    eps = np.sqrt(T * estimator.scale(lam)) - 1.0
-    Y = X.astype(np.float64)
-    oi = ivf.Index(np.zeros(D), np.eye(D), lam, eps, C, off, ids, Y, T=T,
-                   Y_exact=None if store == "f32" else Y, delta=0.0 if store == "f32" else delta)
-    return X, Q, oi
-
-
 @pytest.mark.parametrize("store,rule", [("f32", "all"), ("bf16", "all"), ("bf16", "lazy")])
 def test_exact_integer_inputs_match_bit_for_bit(store, rule):
     """Where FP32 is exact, nothing may be excused: every query's ids, distances (bit for bit),
@@ -154,7 +132,7 @@ def test_exact_integer_inputs_match_bit_for_bit(store, rule):
     Delta_d -- including exact distance ties (duplicate rows) broken by id on the device."""
     _need_gpu()
     delta = 2.0 ** -10
-    X, Q, oi = _integer_index(store, delta)
+    X, Q, oi = integer_index(store, delta)
     gi = dade.dade_import(artifacts(oi), torch.from_numpy(X).cuda(), store=store)
     Qd = torch.from_numpy(Q).cuda()
     for K, npb, dd, sched, fill, growth in ((10, 3, 8, "per_rank", 32, 16), (10, 4, 8, "doubling", 32, 0),
