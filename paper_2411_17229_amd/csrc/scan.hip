@@ -359,18 +359,21 @@ __device__ void dense_item(const RoundArgs& a, const Rows& rows, int q, int cnt,
         const int bi = b0 + ql + 4 * i;
         blk[i] = SS::load(rows, p, bi < nblk ? bi : nblk - 1);
       }
+      // Branch-free: every unit's query chunk is read at the clamped block (in bounds: rows and
+      // queries are padded to whole blocks) and every unit is summed, so all loads can be issued
+      // ahead.  The addend of a unit at or past dim, or of a clamped repeat block, is +0, which
+      // leaves the non-negative sum unchanged: the units below dim are added in the same order.
 #pragma unroll
       for (int i = 0; i < MB; ++i) {
         const int bi = b0 + ql + 4 * i;
+        const int bc = bi < nblk ? bi : nblk - 1;
 #pragma unroll
         for (int j = 0; j < kBlock / 8; ++j) {
-          const int d0 = bi * kBlock + 8 * j;
-          if (bi < nblk && d0 < dim) {
-            float v[8], qq[8];
-            SS::unit(blk[i], j, v);
-            q8(qv, d0, qq);
-            part = part + unit_sum(qq, v);
-          }
+          float v[8], qq[8];
+          SS::unit(blk[i], j, v);
+          q8(qv, bc * kBlock + 8 * j, qq);
+          const float us = unit_sum(qq, v);
+          part = part + ((bi < nblk && bi * kBlock + 8 * j < dim) ? us : 0.f);
         }
       }
     }
