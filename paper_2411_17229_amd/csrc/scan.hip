@@ -339,7 +339,7 @@ __device__ inline void add_stats(const RoundArgs& a, int q, bool fin, int dexit,
 // lanes per candidate, 16 candidates per pass; lane j of a quad sums blocks j, j + 4, j + 8, ...
 // in order, and the quad's partials combine as (P0 + P1) + (P2 + P3).
 template <typename ST, bool RERANK>
-__device__ void dense_item(const RoundArgs& a, const Rows& rows, int q, int cnt, int p0, const float* qv,
+__device__ __forceinline__ void dense_item(const RoundArgs& a, const Rows& rows, int q, int cnt, int p0, const float* qv,
                            bool full, unsigned long long keyr, float gate, int nblk, int lane) {
   using SS = Store<ST>;
   constexpr int MB = SS::kMaxB;
@@ -384,6 +384,36 @@ __device__ void dense_item(const RoundArgs& a, const Rows& rows, int q, int cnt,
   }
 }
 
+// Whole-row items read a query chunk for every unit of every block.  Read from the query rows
+// in memory, those reads cost about as much as the rows themselves (the rows of a fresh batch of
+// queries are not yet in this CU's caches).  A wave therefore first copies its item's query into
+// its own LDS slice, with every load of the copy issued before its first store, and the units
+// read their chunks from there.  Rows of up to kStageMaxDp coordinates are staged; wider ones
+// are read in place.
+constexpr int kStageMaxDp = 1024;
+
+__host__ __device__ inline size_t round_lds_bytes(int dp) {
+  return dp <= kStageMaxDp ? size_t(kWaves) * size_t(dp) * sizeof(float) : 0;
+}
+
+// The query row qv (dp floats, dp <= kStageMaxDp, a multiple of kBlock) into this wave's slice
+// qs.  Loads past dp are clamped in bounds and not stored.
+__device__ inline void stage_query(const float* qv, float* qs, int dp, int lane) {
+  constexpr int kSteps = kStageMaxDp / 256;
+  float4 t[kSteps];
+#pragma unroll
+  for (int i = 0; i < kSteps; ++i) {
+    const int c = 4 * lane + 256 * i;
+    t[i] = *reinterpret_cast<const float4*>(qv + (c < dp ? c : dp - 4));
+  }
+#pragma unroll
+  for (int i = 0; i < kSteps; ++i) {
+    const int c = 4 * lane + 256 * i;
+    if (c < dp) *reinterpret_cast<float4*>(qs + c) = t[i];
+  }
+  __builtin_amdgcn_wave_barrier();
+}
+
 // ------------------------------------------------------------------------------------------------
 // scan_round: the DCOs of one round for every query.
 template <typename ST, bool DADE, bool RERANK, bool PER_DIM>
@@ -396,6 +426,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) v
   constexpr int MB = SS::kMaxB;
   __shared__ int4 stack_lds[kWaves][kStack];
   __shared__ int s_claim;
+  extern __shared__ float4 q_stage[];   // [kWaves][dp] floats when dp <= kStageMaxDp
   const int lane = threadIdx.x & 63;
   int4* stk = stack_lds[threadIdx.x >> 6];
   const int dim = a.dim, dp = a.dp, dd = a.delta_d;
@@ -539,7 +570,13 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) v
     const bool dense = !any_tests || !full;   // no test can reject: whole rows
     if (dense && cnt <= 16) {
       // few candidates (the rounds that fill the heap): four lanes per row
-      dense_item<ST, RERANK>(a, rows, q, cnt, p_item, qv, full, keyr, gate_f * r2, nblk, lane);
+      if (dp <= kStageMaxDp) {
+        float* qs = reinterpret_cast<float*>(q_stage) + (threadIdx.x >> 6) * dp;
+        stage_query(qv, qs, dp, lane);
+        dense_item<ST, RERANK>(a, rows, q, cnt, p_item, qs, full, keyr, gate_f * r2, nblk, lane);
+      } else {
+        dense_item<ST, RERANK>(a, rows, q, cnt, p_item, qv, full, keyr, gate_f * r2, nblk, lane);
+      }
       continue;
     }
     const bool has = lane < cnt;
@@ -1113,10 +1150,13 @@ __global__ __launch_bounds__(kThreads) void merge_round_kernel(RoundArgs a, int 
 
 template <typename ST, bool DADE, bool RERANK>
 hipError_t launch_round_typed(const RoundArgs& a, int r, hipStream_t s) {
+  const size_t lds = round_lds_bytes(a.dp);
   if (DADE && a.delta_d % 8 != 0)
-    hipLaunchKernelGGL((scan_round_kernel<ST, DADE, RERANK, true>), dim3(a.grid), dim3(kThreads), 0, s, a, r, a.qrot, a.T);
+    hipLaunchKernelGGL((scan_round_kernel<ST, DADE, RERANK, true>), dim3(a.grid), dim3(kThreads), lds, s, a, r, a.qrot,
+                       a.T);
   else
-    hipLaunchKernelGGL((scan_round_kernel<ST, DADE, RERANK, false>), dim3(a.grid), dim3(kThreads), 0, s, a, r, a.qrot, a.T);
+    hipLaunchKernelGGL((scan_round_kernel<ST, DADE, RERANK, false>), dim3(a.grid), dim3(kThreads), lds, s, a, r,
+                       a.qrot, a.T);
   return hipGetLastError();
 }
 
@@ -1143,11 +1183,12 @@ hipError_t launch_plan(const RoundArgs& a, int* counts, hipStream_t s) {
   return hipGetLastError();
 }
 
-int round_blocks_per_cu(int dtype, int mode, int delta_d) {
+int round_blocks_per_cu(int dtype, int mode, int delta_d, int dp) {
   int n = 0;
   hipError_t e = hipSuccess;
   const bool pd = mode == 0 && delta_d % 8 != 0;
-#define DADE_OCC(ST, D, R, P) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, scan_round_kernel<ST, D, R, P>, kThreads, 0)
+  const size_t lds = round_lds_bytes(dp);
+#define DADE_OCC(ST, D, R, P) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, scan_round_kernel<ST, D, R, P>, kThreads, lds)
   if (dtype == 0) {
     if (mode != 0) DADE_OCC(float, false, false, false);
     else if (pd) DADE_OCC(float, true, false, true);
