@@ -993,7 +993,7 @@ static int search_impl(dade_index* ix, const float* Q, int64_t ldq, int64_t nq, 
   if (o.use_graph && !ix->cap) HIPC(hipStreamCreateWithFlags(&ix->cap, hipStreamNonBlocking));
   if (o.scan_blocks_per_cu < 0) FAIL(DADE_EINVAL, "scan_blocks_per_cu must be >= 0");
   int& occ = ix->scan_occ[ix->store][o.mode][dd % 8 != 0];
-  if (occ == 0) occ = round_blocks_per_cu(ix->store, o.mode, dd, ix->dp);
+  if (occ == 0) occ = round_blocks_per_cu(ix->store, o.mode, dd);
   const int blocks_per_cu = o.scan_blocks_per_cu > 0 ? std::min(o.scan_blocks_per_cu, occ) : occ;
   if (o.record_times && !ix->ev_made) {
     for (auto& e : ix->ev) HIPC(hipEventCreate(&e));

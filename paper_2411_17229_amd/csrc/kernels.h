@@ -176,7 +176,7 @@ hipError_t launch_plan(const RoundArgs& a, int* counts, hipStream_t s);
 hipError_t launch_round(const RoundArgs& a, int r, hipStream_t s);
 hipError_t launch_merge(const RoundArgs& a, int r, hipStream_t s);
 // Resident scan_round workgroups per CU for a store type / mode / Delta_d.
-int round_blocks_per_cu(int dtype, int mode, int delta_d, int dp);
+int round_blocks_per_cu(int dtype, int mode, int delta_d);
 
 // ---------------------------------------------------------------- graph search (graph.hip)
 constexpr int kGraphMax = 64;   // largest degree, ef and n_entry (one wave holds a query's pool)

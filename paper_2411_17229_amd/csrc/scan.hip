@@ -335,14 +335,29 @@ __device__ inline void add_stats(const RoundArgs& a, int q, bool fin, int dexit,
   }
 }
 
+// Whole-row items read a query chunk for every unit of every block.  Read from the query rows
+// in memory, one per unit, those reads cost about as much as the rows themselves (the rows of a
+// fresh batch of queries are not yet in this CU's caches).  So each step of a whole-row item
+// copies the query coordinates of its blocks into the wave's LDS slice, with the loads issued
+// beside the step's row loads, and its units read their chunks from there.  The per-dimension
+// kernels (Delta_d not a multiple of 8) read in place and are launched without the slices.
+template <typename ST>
+__host__ __device__ constexpr int stage_span() { return 4 * Store<ST>::kMaxB * kBlock; }   // coordinates per step
+
+__host__ __device__ inline size_t round_lds_bytes(int dtype) {
+  const int span = dtype == 0 ? stage_span<float>() : stage_span<__hip_bfloat16>();
+  return size_t(kWaves) * size_t(span) * sizeof(float);
+}
+
 // Wave-wide: whole-row distances of a small item's candidates (no test can reject them).  Four
 // lanes per candidate, 16 candidates per pass; lane j of a quad sums blocks j, j + 4, j + 8, ...
 // in order, and the quad's partials combine as (P0 + P1) + (P2 + P3).
-template <typename ST, bool RERANK>
-__device__ __forceinline__ void dense_item(const RoundArgs& a, const Rows& rows, int q, int cnt, int p0, const float* qv,
-                           bool full, unsigned long long keyr, float gate, int nblk, int lane) {
+template <typename ST, bool RERANK, bool STAGE>
+__device__ void dense_item(const RoundArgs& a, const Rows& rows, int q, int cnt, int p0, const float* qv,
+                           float* qs, bool full, unsigned long long keyr, float gate, int nblk, int lane) {
   using SS = Store<ST>;
   constexpr int MB = SS::kMaxB;
+  constexpr int kSpan = stage_span<ST>();
   const int dim = a.dim;
   const int quad = lane >> 2, ql = lane & 3;
   for (int c0 = 0; c0 < cnt; c0 += 16) {
@@ -353,27 +368,60 @@ __device__ __forceinline__ void dense_item(const RoundArgs& a, const Rows& rows,
     const uint32_t rid = lead ? uint32_t(a.ids[p]) : 0u;
     float part = 0.f;
     for (int b0 = 0; b0 < nblk; b0 += 4 * MB) {
+      // STAGE: this step's query coordinates [b0 kBlock, b0 kBlock + kSpan) go into the wave's
+      // slice, loaded before the rows (loads past the padded row are clamped to its last float4,
+      // and their copies are never read)
+      float4 qt[kSpan / 256];
+      if constexpr (STAGE) {
+#pragma unroll
+        for (int i = 0; i < kSpan / 256; ++i) {
+          const int c = b0 * kBlock + 4 * lane + 256 * i;
+          qt[i] = *reinterpret_cast<const float4*>(qv + (c < a.dp ? c : a.dp - 4));
+        }
+      }
       typename SS::Block blk[MB];
 #pragma unroll
       for (int i = 0; i < MB; ++i) {
         const int bi = b0 + ql + 4 * i;
         blk[i] = SS::load(rows, p, bi < nblk ? bi : nblk - 1);
       }
-      // Branch-free: every unit's query chunk is read at the clamped block (in bounds: rows and
-      // queries are padded to whole blocks) and every unit is summed, so all loads can be issued
-      // ahead.  The addend of a unit at or past dim, or of a clamped repeat block, is +0, which
-      // leaves the non-negative sum unchanged: the units below dim are added in the same order.
+      if constexpr (STAGE) {
 #pragma unroll
-      for (int i = 0; i < MB; ++i) {
-        const int bi = b0 + ql + 4 * i;
-        const int bc = bi < nblk ? bi : nblk - 1;
+        for (int i = 0; i < kSpan / 256; ++i) *reinterpret_cast<float4*>(qs + 4 * lane + 256 * i) = qt[i];
+        __builtin_amdgcn_wave_barrier();
+        // Branch-free: every unit is summed with its query chunk from the slice, at the clamped
+        // block (bc >= b0: a clamped block is the last one, and b0 is at most that); the addend
+        // of a unit at or past dim, or of a clamped repeat block, is +0, which leaves the
+        // non-negative sum unchanged, so the units below dim are added in the same order.
 #pragma unroll
-        for (int j = 0; j < kBlock / 8; ++j) {
-          float v[8], qq[8];
-          SS::unit(blk[i], j, v);
-          q8(qv, bc * kBlock + 8 * j, qq);
-          const float us = unit_sum(qq, v);
-          part = part + ((bi < nblk && bi * kBlock + 8 * j < dim) ? us : 0.f);
+        for (int i = 0; i < MB; ++i) {
+          const int bi = b0 + ql + 4 * i;
+          const int bc = bi < nblk ? bi : nblk - 1;
+#pragma unroll
+          for (int j = 0; j < kBlock / 8; ++j) {
+            float v[8], qq[8];
+            SS::unit(blk[i], j, v);
+            q8(qs, (bc - b0) * kBlock + 8 * j, qq);
+            const float us = unit_sum(qq, v);
+            part = part + ((bi < nblk && bi * kBlock + 8 * j < dim) ? us : 0.f);
+          }
+        }
+      } else {
+        // unit by unit, the query chunk read from memory (the per-dimension kernels: the staged
+        // loop's registers would cost them an occupancy level)
+#pragma unroll
+        for (int i = 0; i < MB; ++i) {
+          const int bi = b0 + ql + 4 * i;
+#pragma unroll
+          for (int j = 0; j < kBlock / 8; ++j) {
+            const int d0 = bi * kBlock + 8 * j;
+            if (bi < nblk && d0 < dim) {
+              float v[8], qq[8];
+              SS::unit(blk[i], j, v);
+              q8(qv, d0, qq);
+              part = part + unit_sum(qq, v);
+            }
+          }
         }
       }
     }
@@ -382,36 +430,6 @@ __device__ __forceinline__ void dense_item(const RoundArgs& a, const Rows& rows,
     append_keys(a, q, lead && passes<RERANK>(S, rid, full, keyr, gate), make_key(S, rid), lane);
     if (a.stats) add_stats(a, q, lead, dim, lane);
   }
-}
-
-// Whole-row items read a query chunk for every unit of every block.  Read from the query rows
-// in memory, those reads cost about as much as the rows themselves (the rows of a fresh batch of
-// queries are not yet in this CU's caches).  A wave therefore first copies its item's query into
-// its own LDS slice, with every load of the copy issued before its first store, and the units
-// read their chunks from there.  Rows of up to kStageMaxDp coordinates are staged; wider ones
-// are read in place.
-constexpr int kStageMaxDp = 1024;
-
-__host__ __device__ inline size_t round_lds_bytes(int dp) {
-  return dp <= kStageMaxDp ? size_t(kWaves) * size_t(dp) * sizeof(float) : 0;
-}
-
-// The query row qv (dp floats, dp <= kStageMaxDp, a multiple of kBlock) into this wave's slice
-// qs.  Loads past dp are clamped in bounds and not stored.
-__device__ inline void stage_query(const float* qv, float* qs, int dp, int lane) {
-  constexpr int kSteps = kStageMaxDp / 256;
-  float4 t[kSteps];
-#pragma unroll
-  for (int i = 0; i < kSteps; ++i) {
-    const int c = 4 * lane + 256 * i;
-    t[i] = *reinterpret_cast<const float4*>(qv + (c < dp ? c : dp - 4));
-  }
-#pragma unroll
-  for (int i = 0; i < kSteps; ++i) {
-    const int c = 4 * lane + 256 * i;
-    if (c < dp) *reinterpret_cast<float4*>(qs + c) = t[i];
-  }
-  __builtin_amdgcn_wave_barrier();
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -426,7 +444,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) v
   constexpr int MB = SS::kMaxB;
   __shared__ int4 stack_lds[kWaves][kStack];
   __shared__ int s_claim;
-  extern __shared__ float4 q_stage[];   // [kWaves][dp] floats when dp <= kStageMaxDp
+  extern __shared__ float4 q_stage[];   // [kWaves][stage span] floats: whole-row items' query chunks
   const int lane = threadIdx.x & 63;
   int4* stk = stack_lds[threadIdx.x >> 6];
   const int dim = a.dim, dp = a.dp, dd = a.delta_d;
@@ -570,13 +588,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) v
     const bool dense = !any_tests || !full;   // no test can reject: whole rows
     if (dense && cnt <= 16) {
       // few candidates (the rounds that fill the heap): four lanes per row
-      if (dp <= kStageMaxDp) {
-        float* qs = reinterpret_cast<float*>(q_stage) + (threadIdx.x >> 6) * dp;
-        stage_query(qv, qs, dp, lane);
-        dense_item<ST, RERANK>(a, rows, q, cnt, p_item, qs, full, keyr, gate_f * r2, nblk, lane);
-      } else {
-        dense_item<ST, RERANK>(a, rows, q, cnt, p_item, qv, full, keyr, gate_f * r2, nblk, lane);
-      }
+      float* qs = reinterpret_cast<float*>(q_stage) + (threadIdx.x >> 6) * stage_span<ST>();
+      dense_item<ST, RERANK, !PER_DIM>(a, rows, q, cnt, p_item, qv, qs, full, keyr, gate_f * r2, nblk, lane);
       continue;
     }
     const bool has = lane < cnt;
@@ -1150,9 +1163,9 @@ __global__ __launch_bounds__(kThreads) void merge_round_kernel(RoundArgs a, int 
 
 template <typename ST, bool DADE, bool RERANK>
 hipError_t launch_round_typed(const RoundArgs& a, int r, hipStream_t s) {
-  const size_t lds = round_lds_bytes(a.dp);
+  const size_t lds = round_lds_bytes(a.dtype);   // the staging slices (not used per dimension)
   if (DADE && a.delta_d % 8 != 0)
-    hipLaunchKernelGGL((scan_round_kernel<ST, DADE, RERANK, true>), dim3(a.grid), dim3(kThreads), lds, s, a, r, a.qrot,
+    hipLaunchKernelGGL((scan_round_kernel<ST, DADE, RERANK, true>), dim3(a.grid), dim3(kThreads), 0, s, a, r, a.qrot,
                        a.T);
   else
     hipLaunchKernelGGL((scan_round_kernel<ST, DADE, RERANK, false>), dim3(a.grid), dim3(kThreads), lds, s, a, r,
@@ -1183,12 +1196,12 @@ hipError_t launch_plan(const RoundArgs& a, int* counts, hipStream_t s) {
   return hipGetLastError();
 }
 
-int round_blocks_per_cu(int dtype, int mode, int delta_d, int dp) {
+int round_blocks_per_cu(int dtype, int mode, int delta_d) {
   int n = 0;
   hipError_t e = hipSuccess;
   const bool pd = mode == 0 && delta_d % 8 != 0;
-  const size_t lds = round_lds_bytes(dp);
-#define DADE_OCC(ST, D, R, P) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, scan_round_kernel<ST, D, R, P>, kThreads, lds)
+  const size_t lds = round_lds_bytes(dtype);
+#define DADE_OCC(ST, D, R, P) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, scan_round_kernel<ST, D, R, P>, kThreads, P ? 0 : lds)
   if (dtype == 0) {
     if (mode != 0) DADE_OCC(float, false, false, false);
     else if (pd) DADE_OCC(float, true, false, true);
