@@ -976,7 +976,8 @@ __global__ __launch_bounds__(kScanThreads) void plan_offsets_kernel(RoundArgs a,
 // the next round; after the query's last round, write its result.
 template <bool RERANK>
 __global__ __launch_bounds__(kThreads) void merge_round_kernel(RoundArgs a, int r) {
-  extern __shared__ float qo[];   // [dp] original query (RERANK)
+  extern __shared__ float4 qo4[];   // [dp] original query (RERANK)
+  float* qo = reinterpret_cast<float*>(qo4);
   __shared__ __align__(16) unsigned long long topk[kMaxK];
   __shared__ __align__(16) unsigned long long newk[kMaxK];
   __shared__ __align__(16) unsigned long long fk[RERANK ? kMaxK : 8];
@@ -999,6 +1000,10 @@ __global__ __launch_bounds__(kThreads) void merge_round_kernel(RoundArgs a, int 
   const int n_head = a.kb_cap < kHeadKeys ? int(a.kb_cap) : kHeadKeys;
   for (int i = tid; i < a.k_max; i += kThreads) topk[i] = gtop[i];
   if (tid < n_head) qk[tid] = kb[tid];
+  // and the original query for the rerank, 16 bytes per thread (one step for dp <= 1024)
+  if (RERANK)
+    for (int c = 4 * tid; c < dp; c += 4 * kThreads)
+      *reinterpret_cast<float4*>(qo + c) = *reinterpret_cast<const float4*>(a.qorig + int64_t(q) * dp + c);
   // the query's items of round r + 1 (they get the snapshot its scan tests against)
   const bool has_next = r + 1 < a.rounds;
   const int64_t ro = int64_t(r + 1) * a.nq;
@@ -1021,8 +1026,6 @@ __global__ __launch_bounds__(kThreads) void merge_round_kernel(RoundArgs a, int 
   const bool in_lds = m <= kMergeChunk;
   if (in_lds)
     for (int i = n_head + tid; i < m; i += kThreads) qk[i] = kb[i];
-  if (RERANK && m > 0)
-    for (int c = tid; c < dp; c += kThreads) qo[c] = a.qorig[int64_t(q) * dp + c];
   const bool full = keyr != ~0ull;
   auto queued = [&](int i) { return in_lds ? qk[i] : kb[i]; };
   unsigned st_kept = 0, st_rr = 0;
