@@ -591,7 +591,7 @@ def main():
         log(f"[bench] copy probe: 5 copies of {src.numel() * 4} bytes")
         return
     if args.gpus != 1:
-        print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for {args.gpus}).",
+        print(f"bench.py measures one GPU: this library has no multi-GPU path (asked for {args.gpus}).",
               file=sys.stderr)
         sys.exit(2)
 
