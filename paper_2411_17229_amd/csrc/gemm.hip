@@ -65,20 +65,21 @@ __global__ __launch_bounds__(kThreads) void gemm_kernel(GemmArgs g) {
     arow[l] = nullptr;
     if (gm < g.M) arow[l] = g.A + (g.a_rows ? int64_t(g.a_rows[gm]) : int64_t(gm)) * g.lda;
   }
-  float4 ra[LA], rb[LB];
+  // A and its shift are kept apart until stage(): nothing in fetch() uses a loaded value, so all
+  // of a slice's loads are issued before any of them is waited for.  (x - +0 is x, so rows with
+  // no shift, and rows past M, which load nothing, stage the same values.)
+  float4 ra[LA], rs[LA], rb[LB];
   auto fetch = [&](int k0) {
 #pragma unroll
     for (int l = 0; l < LA; ++l) {
       const int q = (tid + l * kThreads) % (BK / 4);
-      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f), sh = make_float4(0.f, 0.f, 0.f, 0.f);
       if (arow[l]) {
         v = *reinterpret_cast<const float4*>(arow[l] + k0 + 4 * q);
-        if (g.a_shift) {
-          const float4 sh = *reinterpret_cast<const float4*>(g.a_shift + k0 + 4 * q);
-          v.x -= sh.x; v.y -= sh.y; v.z -= sh.z; v.w -= sh.w;
-        }
+        if (g.a_shift) sh = *reinterpret_cast<const float4*>(g.a_shift + k0 + 4 * q);
       }
       ra[l] = v;
+      rs[l] = sh;
     }
 #pragma unroll
     for (int l = 0; l < LB; ++l) {
@@ -108,10 +109,10 @@ __global__ __launch_bounds__(kThreads) void gemm_kernel(GemmArgs g) {
     for (int l = 0; l < LA; ++l) {
       const int e = tid + l * kThreads;
       const int r = e / (BK / 4), q = e % (BK / 4);
-      As[(4 * q + 0) * PA + r] = ra[l].x;
-      As[(4 * q + 1) * PA + r] = ra[l].y;
-      As[(4 * q + 2) * PA + r] = ra[l].z;
-      As[(4 * q + 3) * PA + r] = ra[l].w;
+      As[(4 * q + 0) * PA + r] = ra[l].x - rs[l].x;
+      As[(4 * q + 1) * PA + r] = ra[l].y - rs[l].y;
+      As[(4 * q + 2) * PA + r] = ra[l].z - rs[l].z;
+      As[(4 * q + 3) * PA + r] = ra[l].w - rs[l].w;
     }
 #pragma unroll
     for (int l = 0; l < LB; ++l) {
