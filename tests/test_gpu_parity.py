@@ -275,30 +275,45 @@ def test_low_precision_store(small, store):
     gl.close()
 
 
+def _identity_rotation_case(store, delta, rule, dim, searches):
+    """An index with W = I and mu = 0 (the library's stored coordinates are then exactly the
+    oracle's rounded X), searched on the GPU and by the oracle; ids compared as everywhere."""
+    from oracle import estimator, lowp
+    X, Q = workloads.make_mixture(6000, dim, 12, 1.2, 60, seed=13)
+    init = workloads.kmeans_init_rows(len(X), 24, 13)
+    pairs = workloads.calibration_pairs(len(X), 30000, 13)
+    lam = np.sort(np.var(X.astype(np.float64), axis=0))[::-1].copy()
+    Ys = lowp.store(X.astype(np.float64), store)
+    eps, T, _ = estimator.calibrate(X, np.eye(dim), lam, pairs, 0.1, stored=Ys)
+    C = ivf.kmeans(X, init, 10)
+    off, ids = ivf.build_lists(ivf.assign(X, C), 24)
+    oi = ivf.Index(np.zeros(dim), np.eye(dim), lam, eps, C, off, ids, Ys,
+                   Y_exact=X.astype(np.float64), delta=delta, T=T)
+    gi = dade.dade_import(artifacts(oi), torch.from_numpy(X).cuda(), store=store)
+    for K, npb, sched in searches:
+        o = oracle_ivf(oi, Q, K, npb, 16, schedule=sched, rerank=rule)
+        g_ids, g_d2 = gpu_search(gi, torch.from_numpy(Q).cuda(), K, npb, delta_d=16, schedule=sched,
+                                 rerank_delta=delta, rerank_rule=rule)
+        compare(o, g_ids, g_d2, X, Q, K)
+    gi.close()
+
+
 @pytest.mark.parametrize("rule", ["all", "lazy"])
 @pytest.mark.parametrize("store,delta", [("bf16", 0.02), ("f16", 0.002), ("bf16", 0.0)])
 def test_low_precision_rerank_rule_parity(store, delta, rule):
     """With W = I and mu = 0 the library's stored coordinates are exactly the oracle's rounded
     X, so the rerank rule (gate, K smallest, bound from the K-th exact) is compared ID for ID."""
     _need_gpu()
-    from oracle import estimator, lowp
-    X, Q = workloads.make_mixture(6000, 64, 12, 1.2, 60, seed=13)
-    init = workloads.kmeans_init_rows(len(X), 24, 13)
-    pairs = workloads.calibration_pairs(len(X), 30000, 13)
-    lam = np.sort(np.var(X.astype(np.float64), axis=0))[::-1].copy()
-    Ys = lowp.store(X.astype(np.float64), store)
-    eps, T, _ = estimator.calibrate(X, np.eye(64), lam, pairs, 0.1, stored=Ys)
-    C = ivf.kmeans(X, init, 10)
-    off, ids = ivf.build_lists(ivf.assign(X, C), 24)
-    oi = ivf.Index(np.zeros(64), np.eye(64), lam, eps, C, off, ids, Ys,
-                   Y_exact=X.astype(np.float64), delta=delta, T=T)
-    gi = dade.dade_import(artifacts(oi), torch.from_numpy(X).cuda(), store=store)
-    for K, npb, sched in ((10, 4, "per_rank"), (25, 6, "doubling"), (1, 3, "per_rank")):
-        o = oracle_ivf(oi, Q, K, npb, 16, schedule=sched, rerank=rule)
-        g_ids, g_d2 = gpu_search(gi, torch.from_numpy(Q).cuda(), K, npb, delta_d=16, schedule=sched,
-                                 rerank_delta=delta, rerank_rule=rule)
-        compare(o, g_ids, g_d2, X, Q, K)
-    gi.close()
+    _identity_rotation_case(store, delta, rule, 64, ((10, 4, "per_rank"), (25, 6, "doubling"), (1, 3, "per_rank")))
+
+
+@pytest.mark.parametrize("rule", ["all", "lazy"])
+def test_low_precision_odd_dimension(rule):
+    """D = 100 with a BF16 store (rows padded to 128: the last block is partly padding) over the
+    three schedules; the heap-filling rounds read whole rows, whose query chunks are staged per
+    step of blocks, so their clamped loads and the +0 addends past D are exercised."""
+    _need_gpu()
+    _identity_rotation_case("bf16", 0.02, rule, 100, ((10, 4, "whole"), (25, 6, "doubling"), (1, 3, "per_rank")))
 
 
 def test_data_oblivious_rotation_matches_oracle():
