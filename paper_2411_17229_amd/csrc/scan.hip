@@ -21,7 +21,9 @@
 //     levels of growing size (all loads of a level in flight at once), each level replaying the
 //     tests it covers in order: 64 survivors at a time, one lane each, while items remain; a
 //     quad of lanes per survivor once the items are done and at most 16 are left.  Rounds whose
-//     heap is not yet full (no test can reject) and FDScanning read whole rows.
+//     heap is not yet full (no test can reject) and FDScanning read whole rows; items of at
+//     most 16 candidates take four lanes per row and read the query's chunks from the wave's
+//     LDS slice, filled step by step beside the row loads.
 //   * merge_round: one workgroup per query merges the round's queued keys into its top-K (for
 //     low-precision stores through the rerank rule below), takes the snapshot for the next
 //     round and writes it into the query's work items of that round; after the query's last
